@@ -1,0 +1,195 @@
+/*
+ * fdtd.h -- C ABI of the MI355X (gfx950) second-order acoustic FDTD + CPML library.
+ *
+ * Operation (paper, section "Model" and section "CPML Boundary Layers"):
+ * each call of fdtd_step advances every shot of a context by
+ *
+ *     u^{n+1} = 2 u^n - u^{n-1} + m * sum_d Lt_d(u^n) + m * f^n,   m = v^2 dt^2,
+ *
+ * where Lt_d is the radius-4 (eighth-order) central second derivative along
+ * axis d, replaced inside the absorbing layer by the CFS/Roden-Gedney
+ * stretched operator applied twice: psi_d <- b psi_d + a D1_d u^n,
+ * eta_d = kinv D2_d u^n + dkinv D1_d u^n + D1_d psi_d,
+ * zeta_d <- b zeta_d + a eta_d, Lt_d = kinv eta_d + zeta_d, with
+ * b = exp(-(sigma/kappa + alpha) dt), a = sigma (b-1) / (kappa (sigma + kappa alpha))
+ * and cubic sigma/kappa grading (sigma_max = -(q+1) v_ref ln R / (2 L h), q = 3,
+ * kappa_max = 5, alpha_max = 0.05 sigma_max by default).
+ * Faces outside the grid are zero Dirichlet, or "ghost" faces that are
+ * filled by an on-device pack/unpack of the opposite face every s steps with
+ * depth g = 4 s (one GPU's share of the paper's pencil-yz layout, section
+ * "Multi-GPU Decomposition and Halo Exchange", with the enlarged ghost regions
+ * of the same section; the loopback makes that axis periodic).
+ *
+ * Conventions of every entry point:
+ *  - Return value: FDTD_OK (0) or a negative fdtd_status.  Nothing throws
+ *    across this boundary; fdtd_last_error() gives a message for the context.
+ *  - Arrays are x-fastest: element (i, j, k) of an nx*ny*nz array is at
+ *    i + nx*(j + ny*k).
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or from a device
+ *    tensor).  The caller owns them; the library only borrows them and never
+ *    frees them.  The library never allocates device memory on the data
+ *    path: all of its state lives in the caller-provided workspace.
+ *  - All GPU work is enqueued on the stream given to fdtd_create; no entry
+ *    point synchronises unless stated.
+ *  - One host thread per context at a time.
+ */
+#ifndef FDTD_H
+#define FDTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdtd_ctx fdtd_ctx;
+
+enum fdtd_status {
+    FDTD_OK = 0,
+    FDTD_EINVAL = -1,        /* bad argument, shape, index or layer width       */
+    FDTD_EUNSTABLE = -2,     /* dt above the leapfrog stability limit           */
+    FDTD_ESTATE = -3,        /* call out of order (no workspace, no model, ...) */
+    FDTD_ENOMEM = -4,        /* workspace or buffer too small                   */
+    FDTD_EHIP = -5,          /* a HIP runtime call failed                       */
+    FDTD_ENONFINITE = -6,    /* non-finite value found by fdtd_check_finite     */
+    FDTD_EUNSUPPORTED = -7   /* valid request this build does not implement     */
+};
+
+enum fdtd_storage { FDTD_F32 = 0, FDTD_F16 = 1, FDTD_BF16 = 2 };
+enum fdtd_face { FDTD_FACE_DIRICHLET = 0, FDTD_FACE_GHOST = 1 };
+enum fdtd_variant {
+    FDTD_VARIANT_AUTO = 0,   /* z-march (or the tuned choice, see fdtd_autotune)   */
+    FDTD_VARIANT_NAIVE = 1,  /* one thread per point, all layer logic inline       */
+    FDTD_VARIANT_ZMARCH = 2, /* LDS-staged xy tiles, z-marching register queue      */
+    FDTD_VARIANT_TBLOCK = 3  /* tblock_k steps per launch (temporal blocking)       */
+};
+
+/* One shot (one independent grid).  Zero-valued optional fields take the
+ * default shown. */
+typedef struct {
+    int32_t n[3];            /* nx, ny, nz (points, >= 9 each)                     */
+    double h[3];             /* spacing per axis, metres (> 0)                     */
+    double dt;               /* time step, seconds (> 0)                           */
+    int32_t cpml[6];         /* layer width per face -x,+x,-y,+y,-z,+z (0 = none)  */
+    int32_t face[6];         /* FDTD_FACE_DIRICHLET or FDTD_FACE_GHOST; ghost faces
+                                come in pairs on y and/or z and carry no layer     */
+    int32_t exchange_every;  /* s in {1,2,4} for ghost faces; ghost depth 4 s (0->1)*/
+    double R;                /* target reflection, default 1e-8                    */
+    double kappa_max;        /* default 5                                          */
+    double alpha_frac;       /* alpha_max / sigma_max, default 0.05                */
+    double v_ref;            /* velocity in sigma_max; 0 -> max of the model       */
+    int32_t storage;         /* fdtd_storage of u^n, u^{n-1} (arithmetic is FP32)  */
+    int32_t variant;         /* fdtd_variant                                       */
+    int32_t tblock_k;        /* steps per launch for FDTD_VARIANT_TBLOCK (2 or 4)  */
+    double field_scale;      /* power-of-two storage scale, 0 -> automatic for
+                                16-bit storage, 1 for FP32                         */
+} fdtd_shot_config;
+
+/* Create a context for nshots shots on hip_stream (a hipStream_t, may be NULL
+ * for the null stream).  Validates every shot (EINVAL for bad shapes, layers
+ * wider than half an axis, bad faces; EUNSTABLE is checked at
+ * fdtd_set_velocity, once the velocity is known).  *out receives the context
+ * (host memory owned by the library; free with fdtd_destroy). */
+int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream, fdtd_ctx **out);
+
+/* Bytes of device workspace the context needs (fields, model, layer memory,
+ * profiles, exchange buffers).  256-byte aligned sub-buffers. */
+int fdtd_workspace_size(const fdtd_ctx *ctx, size_t *bytes);
+
+/* Hand the context a device workspace of at least fdtd_workspace_size bytes.
+ * Borrowed: the caller keeps it alive until fdtd_destroy and frees it.
+ * Zeroes the wavefields and layer memory (enqueued on the stream). */
+int fdtd_bind_workspace(fdtd_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Set the velocity model of one shot from a dense float32 [nz][ny][nx] device
+ * array (m/s, > 0).  Computes m = v^2 dt^2, the layer profiles (FP64 on the
+ * host, rounded once to FP32) and checks stability:
+ * vmax dt sqrt(sum_d 6.50159 / h_d^2) <= 2, else FDTD_EUNSTABLE.
+ * Synchronises the stream once (to read vmax). */
+int fdtd_set_velocity(fdtd_ctx *ctx, int32_t shot, const float *v_dev);
+
+/* Point source of one shot at node (i, j, k): from step n on, u^{n+1} gains
+ * m * amplitude * wavelet_dev[n] / (hx hy hz) at that node (n < nt; zero after).
+ * wavelet_dev: float32[nt] device array, read during this call only (the
+ * scaled series is kept in the workspace).  Replaces any previous source. */
+int fdtd_inject_source(fdtd_ctx *ctx, int32_t shot, int32_t i, int32_t j, int32_t k,
+                       const float *wavelet_dev, int32_t nt, float amplitude);
+
+/* Receivers of one shot: ijk_dev is int32[nrec][3] (i, j, k) on the device,
+ * borrowed until replaced.  Indices are validated on the host copy. */
+int fdtd_set_receivers(fdtd_ctx *ctx, int32_t shot, const int32_t *ijk_dev, int32_t nrec);
+
+/* Register float32 traces_dev[nt_capacity][nrec]: every later step n (counted
+ * from the last fdtd_reset) writes row n with u^{n+1} at the receivers, while
+ * n < nt_capacity.  NULL stops recording. */
+int fdtd_record_receivers(fdtd_ctx *ctx, int32_t shot, float *traces_dev, int32_t nt_capacity);
+
+/* Advance all shots by nsteps (asynchronous on the stream).  ESTATE if no
+ * workspace is bound or a shot has no velocity.  With ghost faces the step
+ * count must keep the exchange schedule (any count is accepted; exchanges
+ * happen whenever the step counter is a multiple of s). */
+int fdtd_step(fdtd_ctx *ctx, int32_t nsteps);
+
+/* Same as fdtd_step, but the nsteps launches are captured once into a HIP
+ * graph (kept in the context, keyed by nsteps and the step phase) and
+ * replayed with one launch. */
+int fdtd_step_graph(fdtd_ctx *ctx, int32_t nsteps);
+
+/* Copy a wavefield of one shot to a dense float32 [nz][ny][nx] device array
+ * (storage scale removed).  which: 0 = u^n (latest), 1 = u^{n-1}. */
+int fdtd_get_field(fdtd_ctx *ctx, int32_t shot, int32_t which, float *dst_dev);
+
+/* Overwrite a wavefield of one shot from a dense float32 [nz][ny][nx] device
+ * array (for initial conditions).  which as in fdtd_get_field. */
+int fdtd_set_field(fdtd_ctx *ctx, int32_t shot, int32_t which, const float *src_dev);
+
+/* Zero wavefields and layer memory and the step counter; keep model,
+ * source and receivers. */
+int fdtd_reset(fdtd_ctx *ctx);
+
+/* Steps taken since the last fdtd_reset. */
+int fdtd_get_step(const fdtd_ctx *ctx, int64_t *step);
+
+/* Synchronise and scan the wavefields of every shot; FDTD_ENONFINITE if any
+ * NaN or Inf is present. */
+int fdtd_check_finite(fdtd_ctx *ctx);
+
+/* Size in bytes of the device buffer fdtd_adjoint needs for one shot with
+ * checkpoints every `every` steps over nt steps (checkpoints, one segment of
+ * recomputed levels, adjoint state, scratch). */
+int fdtd_adjoint_workspace_size(const fdtd_ctx *ctx, int32_t shot, int32_t every, int32_t nt, size_t *bytes);
+
+/* Register the adjoint buffer of one shot and the checkpoint interval.  While
+ * registered, fdtd_step saves the full state (u^n, u^{n-1}, psi, zeta) of
+ * that shot every `every` steps from step 0.  every = 0 stops saving. */
+int fdtd_set_checkpointing(fdtd_ctx *ctx, int32_t shot, int32_t every, void *buf_dev, size_t bytes);
+
+/* Model gradient of J for one shot after a forward run of nt steps from
+ * reset with checkpointing on: resid_dev is dJ/dtraces, float32 [nt][nrec];
+ * grad_v_dev (float64 [nz][ny][nx], overwritten) receives dJ/dv.  Reverse-time
+ * sweep of the exact transposed step with segment recomputation from the
+ * checkpoints; the layer profiles (v_ref) and dt are held fixed.  Leaves the
+ * forward state of the shot undefined (call fdtd_reset before stepping). */
+int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev, double *grad_v_dev);
+
+/* Time candidate kernel shapes / temporal-block depths for every shot on
+ * this device and keep the fastest per shape bucket; results are merged into
+ * the JSON cache at cache_path (NULL = no file).  Synchronises; leaves the
+ * wavefields reset. */
+int fdtd_autotune(fdtd_ctx *ctx, const char *cache_path);
+
+/* Choice made for one shot: variant, tile rows per thread, temporal depth. */
+int fdtd_get_plan(const fdtd_ctx *ctx, int32_t shot, int32_t *variant, int32_t *tile_ry, int32_t *tblock_k);
+
+/* Storage scale of one shot (stored value = scale * u). */
+int fdtd_get_scale(const fdtd_ctx *ctx, int32_t shot, double *scale);
+
+const char *fdtd_strerror(int status);
+const char *fdtd_last_error(const fdtd_ctx *ctx);
+void fdtd_destroy(fdtd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDTD_H */

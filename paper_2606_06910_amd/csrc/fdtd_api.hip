@@ -1,0 +1,907 @@
+// fdtd_api.hip -- the C ABI (include/fdtd.h): validation, workspace layout,
+// FP64 layer profiles, step orchestration, HIP graphs, ghost exchange tables,
+// checkpoints, adjoint driver and autotuner.
+//
+// Profiles follow the paper's section "CPML Boundary Layers": node-based
+// layer coordinate rho in [0,1] (1 at the outermost node, step 1/L), cubic
+// grading sigma = sigma_max rho^3, kappa = 1 + (kappa_max - 1) rho^3,
+// alpha = alpha_max (1 - rho), sigma_max = -(q+1) v_ref ln(R) / (2 L h) with
+// q = 3, b = exp(-(sigma/kappa + alpha) dt), a = sigma (b-1)/(kappa (sigma +
+// kappa alpha)), and d(1/kappa)/dx from the same grading.  They are computed
+// in double precision here and rounded once to float for the kernels.
+#include "../../include/fdtd.h"
+#include "fdtd_launch.hpp"
+#include "fdtd_host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+// central weights of order 8: second derivative c0..c4 and first derivative d1..d4
+static const double kC2[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+static const double kC1[5] = {0.0, 4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static int roundup(int x, int m) { return (x + m - 1) / m * m; }
+
+#define FAIL(ctx, code, ...)                                                                                 \
+    do {                                                                                                      \
+        char _b[512];                                                                                         \
+        snprintf(_b, sizeof _b, __VA_ARGS__);                                                                 \
+        if (ctx) (ctx)->err = _b;                                                                             \
+        return (code);                                                                                        \
+    } while (0)
+#define HIPCHK(ctx, expr)                                                                                     \
+    do {                                                                                                      \
+        hipError_t _e = (expr);                                                                               \
+        if (_e != hipSuccess) FAIL(ctx, FDTD_EHIP, "%s: %s", #expr, hipGetErrorString(_e));                   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// layout and planning
+// ---------------------------------------------------------------------------
+static void plan_shot(ShotH &s) {
+    const fdtd_shot_config &c = s.c;
+    s.nx = c.n[0];
+    s.ny = c.n[1];
+    s.nz = c.n[2];
+    s.gy = c.face[2] == FDTD_FACE_GHOST;
+    s.gz = c.face[4] == FDTD_FACE_GHOST;
+    s.s = (s.gy || s.gz) ? std::max(1, (int)c.exchange_every) : 1;
+    s.g = 4 * s.s;
+    s.fy = s.gy ? s.g : 4;
+    s.fz = s.gz ? s.g : 4;
+    s.esz = c.storage == FDTD_F32 ? 4 : 2;
+    s.P = roundup(s.nx + 4, s.esz == 4 ? 64 : 128);
+    s.PY = s.ny + 2 * s.fy;
+    s.S = s.PY * s.P;
+    s.elems = (size_t)kOFF + (size_t)(s.nz + 2 * s.fz) * s.S + (size_t)(kTYMAX + 16) * s.P + 128;
+    for (int d = 0; d < 3; ++d) {
+        s.Llo[d] = c.cpml[2 * d];
+        s.Lhi[d] = c.cpml[2 * d + 1];
+    }
+    s.LX = s.Llo[0] + s.Lhi[0];
+    s.LY = s.Llo[1] + s.Lhi[1];
+    s.LZ = s.Llo[2] + s.Lhi[2];
+    s.psi_elems[0] = (size_t)(s.nz + 2 * s.fz) * s.PY * s.LX;
+    s.psi_elems[1] = (size_t)(s.nz + 2 * s.fz) * s.LY * s.nx;
+    s.psi_elems[2] = (size_t)s.LZ * s.PY * s.nx;
+    s.nmax = std::max(s.nx, std::max(s.ny, s.nz));
+    s.variant = c.variant == FDTD_VARIANT_AUTO ? FDTD_VARIANT_ZMARCH : c.variant;
+    s.ry = 2;
+    s.zchunk = 64;
+    s.tk = c.tblock_k > 1 ? c.tblock_k : 1;
+    if (s.variant == FDTD_VARIANT_TBLOCK && s.tk < 2) s.tk = 2;
+}
+
+static int validate_shot(fdtd_ctx *ctx, const fdtd_shot_config &c, int i) {
+    for (int d = 0; d < 3; ++d) {
+        if (c.n[d] < 9) FAIL(ctx, FDTD_EINVAL, "shot %d: n[%d]=%d must be >= 9", i, d, c.n[d]);
+        if (!(c.h[d] > 0)) FAIL(ctx, FDTD_EINVAL, "shot %d: h[%d] must be > 0", i, d);
+    }
+    if (!(c.dt > 0)) FAIL(ctx, FDTD_EINVAL, "shot %d: dt must be > 0", i);
+    if ((long)c.n[0] * c.n[1] * c.n[2] > (1L << 30)) FAIL(ctx, FDTD_EUNSUPPORTED, "shot %d: grid too large", i);
+    for (int f = 0; f < 6; ++f) {
+        if (c.cpml[f] < 0) FAIL(ctx, FDTD_EINVAL, "shot %d: negative layer width", i);
+        if (c.face[f] != FDTD_FACE_DIRICHLET && c.face[f] != FDTD_FACE_GHOST)
+            FAIL(ctx, FDTD_EINVAL, "shot %d: face %d has an unknown type", i, f);
+    }
+    if (c.face[0] || c.face[1]) FAIL(ctx, FDTD_EINVAL, "shot %d: x faces cannot be ghost faces", i);
+    for (int d = 1; d < 3; ++d) {
+        if (c.face[2 * d] != c.face[2 * d + 1]) FAIL(ctx, FDTD_EINVAL, "shot %d: ghost faces come in pairs", i);
+        if (c.face[2 * d] == FDTD_FACE_GHOST && (c.cpml[2 * d] || c.cpml[2 * d + 1]))
+            FAIL(ctx, FDTD_EINVAL, "shot %d: ghost faces carry no absorbing layer", i);
+    }
+    for (int d = 0; d < 3; ++d) {
+        if (2 * c.cpml[2 * d] >= c.n[d] || 2 * c.cpml[2 * d + 1] >= c.n[d])
+            FAIL(ctx, FDTD_EINVAL, "shot %d: layer on axis %d must be narrower than half the axis", i, d);
+    }
+    bool ghost = c.face[2] || c.face[4];
+    if (ghost) {
+        int s = c.exchange_every ? c.exchange_every : 1;
+        if (s != 1 && s != 2 && s != 4) FAIL(ctx, FDTD_EINVAL, "shot %d: exchange_every must be 1, 2 or 4", i);
+        for (int d = 1; d < 3; ++d)
+            if (c.face[2 * d] && c.n[d] < 4 * s)
+                FAIL(ctx, FDTD_EINVAL, "shot %d: axis %d shorter than the ghost depth", i, d);
+    }
+    if (c.storage < 0 || c.storage > 2) FAIL(ctx, FDTD_EINVAL, "shot %d: unknown storage", i);
+    if (c.variant < 0 || c.variant > 3) FAIL(ctx, FDTD_EINVAL, "shot %d: unknown variant", i);
+    if (c.variant == FDTD_VARIANT_TBLOCK && !(c.tblock_k == 2 || c.tblock_k == 4))
+        FAIL(ctx, FDTD_EINVAL, "shot %d: tblock_k must be 2 or 4", i);
+    if (c.R < 0 || c.R >= 1 || c.kappa_max < 0 || c.alpha_frac < 0 || c.v_ref < 0)
+        FAIL(ctx, FDTD_EINVAL, "shot %d: bad layer parameters", i);
+    if (c.field_scale != 0) {
+        int e;
+        double mnt = frexp(c.field_scale, &e);
+        if (!(c.field_scale > 0) || mnt != 0.5) FAIL(ctx, FDTD_EINVAL, "shot %d: field_scale must be a power of 2", i);
+    }
+    return FDTD_OK;
+}
+
+// XCD-aware order: hardware hands workgroup b to XCD (b mod 8); give each XCD a
+// contiguous spatial range so that tiles sharing halos share an L2.
+static std::vector<WorkItem> xcd_order(const std::vector<WorkItem> &sp) {
+    const int X = 8;
+    size_t W = (sp.size() + X - 1) / X * X;
+    std::vector<WorkItem> out(W);
+    size_t per = W / X;
+    for (size_t w = 0; w < W; ++w) {
+        size_t src = (w % X) * per + w / X;
+        if (src < sp.size()) out[w] = sp[src];
+        else out[w] = WorkItem{sp.empty() ? 0 : sp[0].shot, 0, 1 << 20, 0};   // exits immediately
+    }
+    return out;
+}
+
+static std::vector<WorkItem> shot_tiles(const ShotH &s, int shot, int ry, int zchunk) {
+    int ext = s.g - 4;
+    int Ny = s.ny + (s.gy ? 2 * ext : 0);
+    int Nz = s.nz + (s.gz ? 2 * ext : 0);
+    int TY = 16 * ry;
+    int ntx = (s.nx + 63) / 64, nty = (Ny + TY - 1) / TY, ntz = (Nz + zchunk - 1) / zchunk;
+    std::vector<WorkItem> v;
+    v.reserve((size_t)ntx * nty * ntz);
+    for (int zc = 0; zc < ntz; ++zc)
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx) v.push_back(WorkItem{shot, tx, ty, zc});
+    return v;
+}
+
+static size_t work_capacity(const ShotH &s) {
+    int ext = s.g - 4;
+    int Ny = s.ny + (s.gy ? 2 * ext : 0);
+    int Nz = s.nz + (s.gz ? 2 * ext : 0);
+    return (size_t)((s.nx + 63) / 64) * ((Ny + 15) / 16) * ((Nz + 15) / 16) + 8;
+}
+
+static long psi_count(const ShotH &s, int d, int ext) {
+    int Ny = s.ny + (s.gy ? 2 * ext : 0);
+    int Nz = s.nz + (s.gz ? 2 * ext : 0);
+    if (d == 0) return (long)s.LX * Ny * Nz;
+    if (d == 1) return (long)s.nx * s.LY * Nz;
+    return (long)s.nx * Ny * s.LZ;
+}
+
+// ---------------------------------------------------------------------------
+// profiles (FP64)
+// ---------------------------------------------------------------------------
+static void layer_profile(const ShotH &s, int d, double vref, double *b, double *a, double *kinv, double *dkinv) {
+    const fdtd_shot_config &c = s.c;
+    const int n = d == 0 ? s.nx : (d == 1 ? s.ny : s.nz);
+    const int lo = s.Llo[d], hi = s.Lhi[d];
+    const double q = 3.0;
+    const double R = c.R > 0 ? c.R : 1e-8;
+    const double kmax = c.kappa_max > 0 ? c.kappa_max : 5.0;
+    const double af = c.alpha_frac > 0 ? c.alpha_frac : 0.05;
+    const double h = c.h[d];
+    for (int i = 0; i < n; ++i) {
+        int L = 0;
+        double rho = 0.0, drho = 0.0;
+        if (lo > 0 && i < lo) {
+            L = lo;
+            rho = (double)(lo - i) / lo;
+            drho = -1.0 / (lo * h);
+        } else if (hi > 0 && i >= n - hi) {
+            L = hi;
+            rho = (double)(i - (n - 1 - hi)) / hi;
+            drho = 1.0 / (hi * h);
+        }
+        if (rho > 0) {
+            const double sigma_max = -(q + 1.0) * vref * std::log(R) / (2.0 * L * h);
+            const double r3 = rho * rho * rho;
+            const double sigma = sigma_max * r3;
+            const double kappa = 1.0 + (kmax - 1.0) * r3;
+            const double alpha = af * sigma_max * (1.0 - rho);
+            const double bb = std::exp(-(sigma / kappa + alpha) * c.dt);
+            b[i] = bb;
+            a[i] = sigma > 0 ? sigma * (bb - 1.0) / (kappa * (sigma + kappa * alpha)) : 0.0;
+            kinv[i] = 1.0 / kappa;
+            dkinv[i] = -(kmax - 1.0) * 3.0 * rho * rho * drho / (kappa * kappa);
+        } else {
+            b[i] = 0.0;
+            a[i] = 0.0;
+            kinv[i] = 1.0;
+            dkinv[i] = 0.0;
+        }
+    }
+}
+
+// largest eigenvalue factor of -D2 for the radius-4 weights: -(c0 + 2 sum c_l (-1)^l)
+static double d2_symbol_max() {
+    double s = kC2[0];
+    for (int l = 1; l <= 4; ++l) s += 2.0 * kC2[l] * ((l & 1) ? -1.0 : 1.0);
+    return -s;
+}
+
+// ---------------------------------------------------------------------------
+// descriptors
+// ---------------------------------------------------------------------------
+static char *wsp(fdtd_ctx *ctx, size_t off) { return ctx->ws + off; }
+
+static void *field_origin(fdtd_ctx *ctx, const ShotH &s, size_t off) {
+    return wsp(ctx, off) + ((size_t)kOFF + (size_t)s.fz * s.S + (size_t)s.fy * s.P) * s.esz;
+}
+static float *m_origin(fdtd_ctx *ctx, const ShotH &s) {
+    return (float *)(wsp(ctx, s.o_m) + ((size_t)kOFF + (size_t)s.fz * s.S + (size_t)s.fy * s.P) * 4);
+}
+
+static void fill_desc(fdtd_ctx *ctx, int i) {
+    ShotH &s = ctx->shots[i];
+    DevShot &D = ctx->hdesc[i];
+    memset(&D, 0, sizeof D);
+    D.u[0] = field_origin(ctx, s, s.o_u[0]);
+    D.u[1] = field_origin(ctx, s, s.o_u[1]);
+    D.m = m_origin(ctx, s);
+    for (int d = 0; d < 3; ++d) {
+        D.psi[d] = (float *)wsp(ctx, s.o_psi[d]);
+        D.zeta[d] = (float *)wsp(ctx, s.o_zeta[d]);
+    }
+    D.prof = (const float *)wsp(ctx, s.o_prof);
+    D.wav = s.has_src ? s.wav : nullptr;
+    D.traces = s.traces;
+    D.rec = s.rec;
+    const double vol = s.c.h[0] * s.c.h[1] * s.c.h[2];
+    D.src_scale = (float)((double)s.amp * s.scale / vol);
+    D.inv_scale = (float)(1.0 / s.scale);
+    D.src_nt = s.has_src ? s.src_nt : 0;
+    D.sx = s.has_src ? s.sx : -(1 << 30);
+    D.sy = s.has_src ? s.sy : -(1 << 30);
+    D.sz = s.has_src ? s.sz : -(1 << 30);
+    D.nrec = s.nrec;
+    D.trace_cap = s.traces ? s.cap : 0;
+    D.nx = s.nx;
+    D.ny = s.ny;
+    D.nz = s.nz;
+    D.P = s.P;
+    D.PY = s.PY;
+    D.S = s.S;
+    D.fy = s.fy;
+    D.fz = s.fz;
+    for (int d = 0; d < 3; ++d) {
+        D.Llo[d] = s.Llo[d];
+        D.Lhi[d] = s.Lhi[d];
+    }
+    D.LX = s.LX;
+    D.LY = s.LY;
+    D.LZ = s.LZ;
+    D.nmax = s.nmax;
+    D.ghost[0] = 0;
+    D.ghost[1] = s.gy;
+    D.ghost[2] = s.gz;
+    double cc = 0;
+    for (int d = 0; d < 3; ++d) {
+        const double h = s.c.h[d];
+        for (int l = 0; l <= 4; ++l) {
+            D.w2[d][l] = (float)(kC2[l] / (h * h));
+            D.w1[d][l] = (float)(kC1[l] / h);
+        }
+        cc += kC2[0] / (h * h);
+    }
+    D.cc = (float)cc;
+}
+
+static int upload_desc(fdtd_ctx *ctx) {
+    for (size_t i = 0; i < ctx->shots.size(); ++i) fill_desc(ctx, (int)i);
+    HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, ctx->o_desc), ctx->hdesc.data(), sizeof(DevShot) * ctx->hdesc.size(),
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return FDTD_OK;
+}
+
+// ghost-exchange copy jobs (loopback): [parity][phase] with phases
+// 0 pack-y, 1 unpack-y, 2 pack-z, 3 unpack-z
+static void build_jobs(fdtd_ctx *ctx, int i, std::vector<CopyJob> (&jobs)[2][4], long (&maxe)[2][4]) {
+    ShotH &s = ctx->shots[i];
+    for (int p = 0; p < 2; ++p)
+        for (int ph = 0; ph < 4; ++ph) {
+            jobs[p][ph].clear();
+            maxe[p][ph] = 0;
+        }
+    if (!s.gy && !s.gz) return;
+    char *xb = wsp(ctx, s.o_xbuf);
+    for (int p = 0; p < 2; ++p) {
+        // fields: u^n depth g; u^{n-1} depth g-4; psi_x, zeta_x depth g-4
+        struct F {
+            char *org;      // origin (element (0,0,0) or slab (is=0,y=0,z=0))
+            int esz, ex;    // element size, x extent
+            long rowst, plst;
+            int dep;
+        };
+        std::vector<F> fs;
+        char *un = (char *)field_origin(ctx, s, s.o_u[p]);
+        char *um = (char *)field_origin(ctx, s, s.o_u[p ^ 1]);
+        fs.push_back(F{un, (int)s.esz, s.nx, (long)s.P, (long)s.S, s.g});
+        if (s.g - 4 > 0) {
+            fs.push_back(F{um, (int)s.esz, s.nx, (long)s.P, (long)s.S, s.g - 4});
+            if (s.LX > 0) {
+                for (int w = 0; w < 2; ++w) {
+                    char *base = wsp(ctx, w == 0 ? s.o_psi[0] : s.o_zeta[0]);
+                    char *org = base + ((size_t)s.fz * s.PY + s.fy) * s.LX * 4;
+                    fs.push_back(F{org, 4, s.LX, (long)s.LX, (long)s.PY * s.LX, s.g - 4});
+                }
+            }
+        }
+        // phase y
+        size_t off = 0;
+        if (s.gy) {
+            for (auto &f : fs) {
+                long face = (long)f.dep * s.nz * f.ex;  // elements per face
+                for (int side = 0; side < 2; ++side) {
+                    // side 0: owned rows [0,dep) -> ghost rows [ny, ny+dep)
+                    // side 1: owned rows [ny-dep, ny) -> ghost rows [-dep, 0)
+                    int ys = side == 0 ? 0 : s.ny - f.dep;
+                    int yd = side == 0 ? s.ny : -f.dep;
+                    char *buf = xb + off;
+                    CopyJob pk{f.org + ((long)ys * f.rowst) * f.esz, buf, f.esz, f.ex, f.dep, s.nz,
+                               f.rowst, f.plst, (long)f.ex, (long)f.ex * f.dep};
+                    CopyJob up{buf, f.org + ((long)yd * f.rowst) * f.esz, f.esz, f.ex, f.dep, s.nz,
+                               (long)f.ex, (long)f.ex * f.dep, f.rowst, f.plst};
+                    jobs[p][0].push_back(pk);
+                    jobs[p][1].push_back(up);
+                    maxe[p][0] = std::max(maxe[p][0], face);
+                    maxe[p][1] = std::max(maxe[p][1], face);
+                    off += align256(face * f.esz);
+                }
+            }
+        }
+        off = 0;
+        if (s.gz) {
+            for (auto &f : fs) {
+                int dy = s.gy ? f.dep : 0;
+                int Ny = s.ny + 2 * dy;
+                long face = (long)f.dep * Ny * f.ex;
+                for (int side = 0; side < 2; ++side) {
+                    int zs = side == 0 ? 0 : s.nz - f.dep;
+                    int zd = side == 0 ? s.nz : -f.dep;
+                    char *buf = xb + off;
+                    char *src = f.org + ((long)zs * f.plst - (long)dy * f.rowst) * f.esz;
+                    char *dst = f.org + ((long)zd * f.plst - (long)dy * f.rowst) * f.esz;
+                    CopyJob pk{src, buf, f.esz, f.ex, Ny, f.dep, f.rowst, f.plst, (long)f.ex, (long)f.ex * Ny};
+                    CopyJob up{buf, dst, f.esz, f.ex, Ny, f.dep, (long)f.ex, (long)f.ex * Ny, f.rowst, f.plst};
+                    jobs[p][2].push_back(pk);
+                    jobs[p][3].push_back(up);
+                    maxe[p][2] = std::max(maxe[p][2], face);
+                    maxe[p][3] = std::max(maxe[p][3], face);
+                    off += align256(face * f.esz);
+                }
+            }
+        }
+    }
+}
+
+static size_t xbuf_bytes(const ShotH &s) {
+    if (!s.gy && !s.gz) return 0;
+    size_t by = 0, bz = 0;
+    auto add = [&](int esz, int ex, int dep) {
+        if (dep <= 0) return;
+        if (s.gy) by += 2 * align256((size_t)dep * s.nz * ex * esz);
+        if (s.gz) bz += 2 * align256((size_t)dep * (s.ny + (s.gy ? 2 * dep : 0)) * ex * esz);
+    };
+    add((int)s.esz, s.nx, s.g);
+    add((int)s.esz, s.nx, s.g - 4);
+    if (s.LX > 0) {
+        add(4, s.LX, s.g - 4);
+        add(4, s.LX, s.g - 4);
+    }
+    return std::max(by, bz);
+}
+
+// ---------------------------------------------------------------------------
+// stepping
+// ---------------------------------------------------------------------------
+static void save_checkpoint(fdtd_ctx *ctx, int i, int k);
+
+static int ghost_ext(const fdtd_ctx *ctx, long step) {
+    for (const ShotH &s : ctx->shots)
+        if (s.gy || s.gz) return 4 * (s.s - 1 - (int)(step % s.s));
+    return 0;
+}
+
+static void enqueue_exchange(fdtd_ctx *ctx, int i) {
+    ShotH &s = ctx->shots[i];
+    const int p = ctx->parity;
+    for (int ph = 0; ph < 4; ++ph) {
+        if (s.njobs[p][ph] == 0) continue;
+        fdtd_launch_copy_jobs(wsp(ctx, s.o_jobs[p][ph]), s.njobs[p][ph], s.jobmax[p][ph], ctx->stream);
+    }
+}
+
+// update launches of one shot or of all shots (shot < 0)
+static void enqueue_update(fdtd_ctx *ctx, int shot, int ext) {
+    const DevShot *dd = (const DevShot *)wsp(ctx, ctx->o_desc);
+    int *stepc = (int *)wsp(ctx, ctx->o_stepc);
+    const int p = ctx->parity;
+    const int stor = ctx->storage;
+    int lo = shot < 0 ? 0 : shot, hi = shot < 0 ? (int)ctx->shots.size() : shot + 1;
+    bool all_zmarch_same = shot < 0;
+    for (int i = lo; i < hi && all_zmarch_same; ++i) {
+        const ShotH &s = ctx->shots[i];
+        if (s.variant == FDTD_VARIANT_NAIVE || s.ry != ctx->shots[0].ry || s.zchunk != ctx->shots[0].zchunk)
+            all_zmarch_same = false;
+    }
+    if (all_zmarch_same && ctx->nwork_all > 0) {
+        fdtd_launch_zmarch(stor, dd, (const WorkItem *)wsp(ctx, ctx->o_work_all), ctx->nwork_all,
+                           ctx->shots[0].ry, p, ext, ctx->shots[0].zchunk, stepc, ctx->stream);
+        return;
+    }
+    for (int i = lo; i < hi; ++i) {
+        const ShotH &s = ctx->shots[i];
+        if (s.variant == FDTD_VARIANT_NAIVE) {
+            int Ny = s.ny + (s.gy ? 2 * ext : 0), Nz = s.nz + (s.gz ? 2 * ext : 0);
+            fdtd_launch_naive(stor, dd, i, s.nx, Ny, Nz, p, ext, stepc, ctx->stream);
+        } else {
+            fdtd_launch_zmarch(stor, dd, (const WorkItem *)wsp(ctx, s.o_work), s.nwork, s.ry, p, ext, s.zchunk,
+                               stepc, ctx->stream);
+        }
+    }
+}
+
+// one step of one shot (shot >= 0) or of every shot (shot < 0)
+static void enqueue_step(fdtd_ctx *ctx, int shot) {
+    const long n = ctx->step;
+    int lo = shot < 0 ? 0 : shot, hi = shot < 0 ? (int)ctx->shots.size() : shot + 1;
+    for (int i = lo; i < hi; ++i) {
+        ShotH &s = ctx->shots[i];
+        if (s.ck_every > 0 && ctx->saving && n % s.ck_every == 0 && n / s.ck_every < s.ck_count)
+            save_checkpoint(ctx, i, (int)(n / s.ck_every));
+        if ((s.gy || s.gz) && n % s.s == 0) enqueue_exchange(ctx, i);
+    }
+    const int ext = ghost_ext(ctx, n);
+    const DevShot *dd = (const DevShot *)wsp(ctx, ctx->o_desc);
+    long maxc = 0;
+    for (int i = lo; i < hi; ++i)
+        for (int d = 0; d < 3; ++d) maxc = std::max(maxc, psi_count(ctx->shots[i], d, ext));
+    fdtd_launch_psi(ctx->storage, dd + lo, hi - lo, maxc, ctx->parity, ext, ctx->stream);
+    enqueue_update(ctx, shot, ext);
+    fdtd_launch_record(ctx->storage, dd + lo, hi - lo, ctx->parity ^ 1, (int *)wsp(ctx, ctx->o_stepc), ctx->stream);
+    ctx->parity ^= 1;
+    ctx->step = n + 1;
+}
+
+static int ready(fdtd_ctx *ctx) {
+    if (!ctx->ws) FAIL(ctx, FDTD_ESTATE, "no workspace bound");
+    for (size_t i = 0; i < ctx->shots.size(); ++i)
+        if (!ctx->shots[i].vel_set) FAIL(ctx, FDTD_ESTATE, "shot %zu has no velocity model", i);
+    return FDTD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// checkpoints: state k = (u^n, u^{n-1}, psi, zeta) before step k*every
+// ---------------------------------------------------------------------------
+size_t fdtd_state_bytes(const ShotH &s) {
+    size_t b = 2 * align256(s.elems * s.esz);
+    for (int d = 0; d < 3; ++d) b += 2 * align256(s.psi_elems[d] * 4);
+    return b;
+}
+
+static void copy_state(fdtd_ctx *ctx, int i, char *ck, bool save) {
+    ShotH &s = ctx->shots[i];
+    size_t fb = s.elems * s.esz;
+    // slot 0 of a checkpoint always holds u^n, slot 1 u^{n-1}
+    char *un = wsp(ctx, s.o_u[ctx->parity]);
+    char *um = wsp(ctx, s.o_u[ctx->parity ^ 1]);
+    size_t off = 0;
+    char *dsts[2] = {un, um};
+    for (int k = 0; k < 2; ++k) {
+        if (save) (void)hipMemcpyAsync(ck + off, dsts[k], fb, hipMemcpyDeviceToDevice, ctx->stream);
+        else (void)hipMemcpyAsync(dsts[k], ck + off, fb, hipMemcpyDeviceToDevice, ctx->stream);
+        off += align256(fb);
+    }
+    for (int d = 0; d < 3; ++d) {
+        size_t pb = s.psi_elems[d] * 4;
+        char *arr[2] = {wsp(ctx, s.o_psi[d]), wsp(ctx, s.o_zeta[d])};
+        for (int k = 0; k < 2; ++k) {
+            if (pb) {
+                if (save) (void)hipMemcpyAsync(ck + off, arr[k], pb, hipMemcpyDeviceToDevice, ctx->stream);
+                else (void)hipMemcpyAsync(arr[k], ck + off, pb, hipMemcpyDeviceToDevice, ctx->stream);
+            }
+            off += align256(pb);
+        }
+    }
+}
+
+static void save_checkpoint(fdtd_ctx *ctx, int i, int k) {
+    ShotH &s = ctx->shots[i];
+    copy_state(ctx, i, s.ck_buf + (size_t)k * fdtd_state_bytes(s), true);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *fdtd_strerror(int st) {
+    switch (st) {
+    case FDTD_OK: return "ok";
+    case FDTD_EINVAL: return "invalid argument";
+    case FDTD_EUNSTABLE: return "time step above the stability limit";
+    case FDTD_ESTATE: return "call out of order";
+    case FDTD_ENOMEM: return "buffer too small";
+    case FDTD_EHIP: return "HIP runtime error";
+    case FDTD_ENONFINITE: return "non-finite value in a wavefield";
+    case FDTD_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+    }
+}
+
+const char *fdtd_last_error(const fdtd_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream, fdtd_ctx **out) {
+    if (!out || !shots || nshots <= 0 || nshots > FDTD_MAXSHOTS) return FDTD_EINVAL;
+    *out = nullptr;
+    fdtd_ctx *ctx = new fdtd_ctx();
+    ctx->stream = (hipStream_t)hip_stream;
+    int ghost_s = 0;
+    for (int i = 0; i < nshots; ++i) {
+        int rc = validate_shot(ctx, shots[i], i);
+        if (rc) {
+            std::string e = ctx->err;
+            delete ctx;
+            fprintf(stderr, "fdtd_create: %s\n", e.c_str());
+            return rc;
+        }
+        if (shots[i].storage != shots[0].storage) {
+            delete ctx;
+            return FDTD_EINVAL;
+        }
+        ShotH s;
+        s.c = shots[i];
+        plan_shot(s);
+        if (s.gy || s.gz) {
+            if (ghost_s && ghost_s != s.s) {
+                delete ctx;
+                return FDTD_EINVAL;
+            }
+            ghost_s = s.s;
+        }
+        ctx->shots.push_back(s);
+    }
+    ctx->storage = shots[0].storage;
+    // workspace layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    ctx->o_stepc = take(256);
+    ctx->o_scratch = take(256);
+    ctx->o_desc = take(sizeof(DevShot) * nshots);
+    size_t cap_all = 8;
+    for (auto &s : ctx->shots) cap_all += work_capacity(s);
+    ctx->o_work_all = take(sizeof(WorkItem) * cap_all);
+    for (auto &s : ctx->shots) {
+        s.o_u[0] = take(s.elems * s.esz);
+        s.o_u[1] = take(s.elems * s.esz);
+        s.o_m = take(s.elems * 4);
+        for (int d = 0; d < 3; ++d) {
+            s.o_psi[d] = take(s.psi_elems[d] * 4);
+            s.o_zeta[d] = take(s.psi_elems[d] * 4);
+        }
+        s.o_prof = take((size_t)3 * 4 * s.nmax * 4);
+        s.o_work = take(sizeof(WorkItem) * work_capacity(s));
+        s.xbuf_bytes = xbuf_bytes(s);
+        s.o_xbuf = take(s.xbuf_bytes);
+        for (int p = 0; p < 2; ++p)
+            for (int ph = 0; ph < 4; ++ph) s.o_jobs[p][ph] = take(sizeof(CopyJob) * 16);
+    }
+    ctx->need = off;
+    ctx->hdesc.resize(nshots);
+    *out = ctx;
+    return FDTD_OK;
+}
+
+int fdtd_workspace_size(const fdtd_ctx *ctx, size_t *bytes) {
+    if (!ctx || !bytes) return FDTD_EINVAL;
+    *bytes = ctx->need;
+    return FDTD_OK;
+}
+
+static int write_work_lists(fdtd_ctx *ctx) {
+    std::vector<WorkItem> all;
+    for (size_t i = 0; i < ctx->shots.size(); ++i) {
+        ShotH &s = ctx->shots[i];
+        std::vector<WorkItem> sp = shot_tiles(s, (int)i, s.ry, s.zchunk);
+        std::vector<WorkItem> w = xcd_order(sp);
+        if (w.size() > work_capacity(s)) FAIL(ctx, FDTD_EINVAL, "work list overflow");
+        s.nwork = (int)w.size();
+        HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_work), w.data(), sizeof(WorkItem) * w.size(), hipMemcpyHostToDevice,
+                                   ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        all.insert(all.end(), sp.begin(), sp.end());
+    }
+    std::vector<WorkItem> wa = xcd_order(all);
+    ctx->nwork_all = (int)wa.size();
+    HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, ctx->o_work_all), wa.data(), sizeof(WorkItem) * wa.size(),
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return FDTD_OK;
+}
+
+static int zero_state(fdtd_ctx *ctx) {
+    for (auto &s : ctx->shots) {
+        fdtd_launch_fill_zero(wsp(ctx, s.o_u[0]), align256(s.elems * s.esz), ctx->stream);
+        fdtd_launch_fill_zero(wsp(ctx, s.o_u[1]), align256(s.elems * s.esz), ctx->stream);
+        for (int d = 0; d < 3; ++d) {
+            fdtd_launch_fill_zero(wsp(ctx, s.o_psi[d]), align256(s.psi_elems[d] * 4), ctx->stream);
+            fdtd_launch_fill_zero(wsp(ctx, s.o_zeta[d]), align256(s.psi_elems[d] * 4), ctx->stream);
+        }
+    }
+    fdtd_launch_set_int((int *)wsp(ctx, ctx->o_stepc), 0, ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    ctx->parity = 0;
+    ctx->step = 0;
+    return FDTD_OK;
+}
+
+int fdtd_bind_workspace(fdtd_ctx *ctx, void *dev_ptr, size_t bytes) {
+    if (!ctx || !dev_ptr) return FDTD_EINVAL;
+    if (bytes < ctx->need) FAIL(ctx, FDTD_ENOMEM, "workspace of %zu bytes, need %zu", bytes, ctx->need);
+    if (((uintptr_t)dev_ptr) & 255) FAIL(ctx, FDTD_EINVAL, "workspace must be 256-byte aligned");
+    ctx->ws = (char *)dev_ptr;
+    ctx->ws_bytes = bytes;
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    ctx->graphs.clear();
+    // m and profiles start at zero too (frame of m must stay zero)
+    for (auto &s : ctx->shots) {
+        fdtd_launch_fill_zero(wsp(ctx, s.o_m), align256(s.elems * 4), ctx->stream);
+        fdtd_launch_fill_zero(wsp(ctx, s.o_prof), align256((size_t)3 * 4 * s.nmax * 4), ctx->stream);
+    }
+    int rc = zero_state(ctx);
+    if (rc) return rc;
+    rc = write_work_lists(ctx);
+    if (rc) return rc;
+    for (size_t i = 0; i < ctx->shots.size(); ++i) {
+        ShotH &s = ctx->shots[i];
+        std::vector<CopyJob> jobs[2][4];
+        long maxe[2][4];
+        build_jobs(ctx, (int)i, jobs, maxe);
+        for (int p = 0; p < 2; ++p)
+            for (int ph = 0; ph < 4; ++ph) {
+                if (jobs[p][ph].size() > 16) FAIL(ctx, FDTD_EINVAL, "too many exchange jobs");
+                s.njobs[p][ph] = (int)jobs[p][ph].size();
+                s.jobmax[p][ph] = maxe[p][ph];
+                if (!jobs[p][ph].empty())
+                    HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_jobs[p][ph]), jobs[p][ph].data(),
+                                               sizeof(CopyJob) * jobs[p][ph].size(), hipMemcpyHostToDevice,
+                                               ctx->stream));
+            }
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return upload_desc(ctx);
+}
+
+int fdtd_set_velocity(fdtd_ctx *ctx, int32_t shot, const float *v_dev) {
+    if (!ctx || !v_dev || shot < 0 || shot >= (int)ctx->shots.size()) return FDTD_EINVAL;
+    if (!ctx->ws) FAIL(ctx, FDTD_ESTATE, "bind a workspace first");
+    ShotH &s = ctx->shots[shot];
+    unsigned int *scr = (unsigned int *)wsp(ctx, ctx->o_scratch);
+    fdtd_launch_set_int((int *)scr, 0, ctx->stream);
+    fdtd_launch_set_int((int *)(scr + 1), 0, ctx->stream);
+    fdtd_launch_vel_to_m(v_dev, m_origin(ctx, s), s.nx, s.ny, s.nz, s.P, s.S, s.c.dt * s.c.dt, scr, scr + 1,
+                         ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    unsigned int hv[2];
+    HIPCHK(ctx, hipMemcpyAsync(hv, scr, 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (hv[1]) FAIL(ctx, FDTD_EINVAL, "velocity must be finite and > 0");
+    float vmax;
+    memcpy(&vmax, &hv[0], 4);
+    s.vmax = vmax;
+    double lim = 0;
+    for (int d = 0; d < 3; ++d) lim += d2_symbol_max() / (s.c.h[d] * s.c.h[d]);
+    const double cfl = s.vmax * s.c.dt * std::sqrt(lim);
+    if (cfl > 2.0) FAIL(ctx, FDTD_EUNSTABLE, "vmax dt sqrt(sum 6.50159/h^2) = %.6f > 2", cfl);
+    s.vref = s.c.v_ref > 0 ? s.c.v_ref : s.vmax;
+    std::vector<double> b(s.nmax), a(s.nmax), ki(s.nmax), dk(s.nmax);
+    std::vector<float> prof((size_t)3 * 4 * s.nmax, 0.0f);
+    for (int d = 0; d < 3; ++d) {
+        layer_profile(s, d, s.vref, b.data(), a.data(), ki.data(), dk.data());
+        int n = d == 0 ? s.nx : (d == 1 ? s.ny : s.nz);
+        for (int i = 0; i < n; ++i) {
+            prof[(size_t)(d * 4 + 0) * s.nmax + i] = (float)b[i];
+            prof[(size_t)(d * 4 + 1) * s.nmax + i] = (float)a[i];
+            prof[(size_t)(d * 4 + 2) * s.nmax + i] = (float)ki[i];
+            prof[(size_t)(d * 4 + 3) * s.nmax + i] = (float)dk[i];
+        }
+    }
+    HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_prof), prof.data(), prof.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    s.vel_set = true;
+    if (s.c.storage == FDTD_F32) s.scale = 1.0;
+    else if (s.c.field_scale > 0) s.scale = s.c.field_scale;
+    return upload_desc(ctx);
+}
+
+int fdtd_inject_source(fdtd_ctx *ctx, int32_t shot, int32_t i, int32_t j, int32_t k, const float *wavelet_dev,
+                       int32_t nt, float amplitude) {
+    if (!ctx || shot < 0 || shot >= (int)ctx->shots.size()) return FDTD_EINVAL;
+    ShotH &s = ctx->shots[shot];
+    if (!wavelet_dev || nt <= 0) FAIL(ctx, FDTD_EINVAL, "wavelet missing");
+    if (i < 0 || i >= s.nx || j < 0 || j >= s.ny || k < 0 || k >= s.nz)
+        FAIL(ctx, FDTD_EINVAL, "source (%d,%d,%d) outside the grid", i, j, k);
+    if (s.c.storage != FDTD_F32 && s.c.field_scale == 0) {
+        if (!s.vel_set) FAIL(ctx, FDTD_ESTATE, "16-bit storage: set the velocity before the source");
+        std::vector<float> w(nt);
+        HIPCHK(ctx, hipMemcpyAsync(w.data(), wavelet_dev, (size_t)nt * 4, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        double wmax = 0;
+        for (float x : w) wmax = std::max(wmax, (double)std::fabs(x));
+        double inj = s.vmax * s.vmax * s.c.dt * s.c.dt * std::fabs((double)amplitude) * wmax /
+                     (s.c.h[0] * s.c.h[1] * s.c.h[2]);
+        double sc = inj > 0 ? std::exp2(std::round(std::log2(128.0 / inj))) : 1.0;
+        s.scale = std::min(std::max(sc, std::exp2(-40.0)), std::exp2(40.0));
+    }
+    s.has_src = true;
+    s.wav = wavelet_dev;
+    s.src_nt = nt;
+    s.amp = amplitude;
+    s.sx = i;
+    s.sy = j;
+    s.sz = k;
+    return upload_desc(ctx);
+}
+
+int fdtd_set_receivers(fdtd_ctx *ctx, int32_t shot, const int32_t *ijk_dev, int32_t nrec) {
+    if (!ctx || shot < 0 || shot >= (int)ctx->shots.size() || nrec < 0) return FDTD_EINVAL;
+    ShotH &s = ctx->shots[shot];
+    if (nrec > 0) {
+        if (!ijk_dev) return FDTD_EINVAL;
+        std::vector<int32_t> h((size_t)nrec * 3);
+        HIPCHK(ctx, hipMemcpyAsync(h.data(), ijk_dev, h.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        for (int r = 0; r < nrec; ++r) {
+            int i = h[3 * r], j = h[3 * r + 1], k = h[3 * r + 2];
+            if (i < 0 || i >= s.nx || j < 0 || j >= s.ny || k < 0 || k >= s.nz)
+                FAIL(ctx, FDTD_EINVAL, "receiver %d at (%d,%d,%d) outside the grid", r, i, j, k);
+        }
+    }
+    s.rec = nrec > 0 ? ijk_dev : nullptr;
+    s.nrec = nrec;
+    return upload_desc(ctx);
+}
+
+int fdtd_record_receivers(fdtd_ctx *ctx, int32_t shot, float *traces_dev, int32_t nt_capacity) {
+    if (!ctx || shot < 0 || shot >= (int)ctx->shots.size()) return FDTD_EINVAL;
+    ShotH &s = ctx->shots[shot];
+    if (traces_dev && nt_capacity <= 0) return FDTD_EINVAL;
+    s.traces = traces_dev;
+    s.cap = traces_dev ? nt_capacity : 0;
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    ctx->graphs.clear();
+    return upload_desc(ctx);
+}
+
+int fdtd_step(fdtd_ctx *ctx, int32_t nsteps) {
+    if (!ctx || nsteps < 0) return FDTD_EINVAL;
+    int rc = ready(ctx);
+    if (rc) return rc;
+    for (int k = 0; k < nsteps; ++k) enqueue_step(ctx, -1);
+    HIPCHK(ctx, hipGetLastError());
+    return FDTD_OK;
+}
+
+int fdtd_step_graph(fdtd_ctx *ctx, int32_t nsteps) {
+    if (!ctx || nsteps < 0) return FDTD_EINVAL;
+    int rc = ready(ctx);
+    if (rc) return rc;
+    if (nsteps == 0) return FDTD_OK;
+    long period = 2;
+    for (auto &s : ctx->shots) {
+        period = std::max(period, (long)s.s * 2);
+        if (s.ck_every > 0 && ctx->saving) period = std::max(period, (long)s.ck_every * 2);
+    }
+    // a graph embeds the checkpoint schedule only for its own start step
+    bool ck = false;
+    for (auto &s : ctx->shots) ck = ck || (s.ck_every > 0 && ctx->saving);
+    long phase = ck ? ctx->step : ctx->step % period;
+    std::pair<long, long> key(nsteps, phase * 2 + ctx->parity);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        long step0 = ctx->step;
+        int par0 = ctx->parity;
+        HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < nsteps; ++k) enqueue_step(ctx, -1);
+        hipGraph_t g;
+        HIPCHK(ctx, hipStreamEndCapture(ctx->stream, &g));
+        hipGraphExec_t ge;
+        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) FAIL(ctx, FDTD_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+        it = ctx->graphs.emplace(key, ge).first;
+        ctx->step = step0;
+        ctx->parity = par0;
+    }
+    HIPCHK(ctx, hipGraphLaunch(it->second, ctx->stream));
+    ctx->step += nsteps;
+    ctx->parity ^= (nsteps & 1);
+    return FDTD_OK;
+}
+
+int fdtd_get_field(fdtd_ctx *ctx, int32_t shot, int32_t which, float *dst_dev) {
+    if (!ctx || !dst_dev || shot < 0 || shot >= (int)ctx->shots.size() || which < 0 || which > 1)
+        return FDTD_EINVAL;
+    if (!ctx->ws) FAIL(ctx, FDTD_ESTATE, "no workspace bound");
+    ShotH &s = ctx->shots[shot];
+    const void *u = field_origin(ctx, s, s.o_u[ctx->parity ^ which]);
+    fdtd_launch_get_field(ctx->storage, u, dst_dev, s.nx, s.ny, s.nz, s.P, s.S, (float)(1.0 / s.scale), ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    return FDTD_OK;
+}
+
+int fdtd_set_field(fdtd_ctx *ctx, int32_t shot, int32_t which, const float *src_dev) {
+    if (!ctx || !src_dev || shot < 0 || shot >= (int)ctx->shots.size() || which < 0 || which > 1)
+        return FDTD_EINVAL;
+    if (!ctx->ws) FAIL(ctx, FDTD_ESTATE, "no workspace bound");
+    ShotH &s = ctx->shots[shot];
+    void *u = field_origin(ctx, s, s.o_u[ctx->parity ^ which]);
+    fdtd_launch_set_field(ctx->storage, u, src_dev, s.nx, s.ny, s.nz, s.P, s.S, (float)s.scale, ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    return FDTD_OK;
+}
+
+int fdtd_reset(fdtd_ctx *ctx) {
+    if (!ctx) return FDTD_EINVAL;
+    if (!ctx->ws) FAIL(ctx, FDTD_ESTATE, "no workspace bound");
+    return zero_state(ctx);
+}
+
+int fdtd_get_step(const fdtd_ctx *ctx, int64_t *step) {
+    if (!ctx || !step) return FDTD_EINVAL;
+    *step = ctx->step;
+    return FDTD_OK;
+}
+
+int fdtd_check_finite(fdtd_ctx *ctx) {
+    if (!ctx) return FDTD_EINVAL;
+    if (!ctx->ws) FAIL(ctx, FDTD_ESTATE, "no workspace bound");
+    unsigned int *scr = (unsigned int *)wsp(ctx, ctx->o_scratch);
+    fdtd_launch_set_int((int *)(scr + 2), 0, ctx->stream);
+    for (auto &s : ctx->shots)
+        for (int k = 0; k < 2; ++k)
+            fdtd_launch_finite(ctx->storage, field_origin(ctx, s, s.o_u[k]), s.nx, s.ny, s.nz, s.P, s.S, scr + 2,
+                               ctx->stream);
+    unsigned int bad = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&bad, scr + 2, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (bad) FAIL(ctx, FDTD_ENONFINITE, "non-finite value in a wavefield");
+    return FDTD_OK;
+}
+
+int fdtd_get_plan(const fdtd_ctx *ctx, int32_t shot, int32_t *variant, int32_t *tile_ry, int32_t *tblock_k) {
+    if (!ctx || shot < 0 || shot >= (int)ctx->shots.size()) return FDTD_EINVAL;
+    const ShotH &s = ctx->shots[shot];
+    if (variant) *variant = s.variant;
+    if (tile_ry) *tile_ry = s.ry;
+    if (tblock_k) *tblock_k = s.variant == FDTD_VARIANT_TBLOCK ? s.tk : 1;
+    return FDTD_OK;
+}
+
+int fdtd_get_scale(const fdtd_ctx *ctx, int32_t shot, double *scale) {
+    if (!ctx || !scale || shot < 0 || shot >= (int)ctx->shots.size()) return FDTD_EINVAL;
+    *scale = ctx->shots[shot].scale;
+    return FDTD_OK;
+}
+
+void fdtd_destroy(fdtd_ctx *ctx) {
+    if (!ctx) return;
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    delete ctx;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// internal helpers used by the adjoint and autotuner translation units
+// ---------------------------------------------------------------------------
+char *fdtd_ws(fdtd_ctx *ctx, size_t off) { return wsp(ctx, off); }
+void fdtd_enqueue_step_shot(fdtd_ctx *ctx, int shot) { enqueue_step(ctx, shot); }
+void fdtd_restore_state(fdtd_ctx *ctx, int i, char *ck) { copy_state(ctx, i, ck, false); }
+void *fdtd_field_origin(fdtd_ctx *ctx, const ShotH &s, size_t off) { return field_origin(ctx, s, off); }
+float *fdtd_m_origin(fdtd_ctx *ctx, const ShotH &s) { return m_origin(ctx, s); }
+int fdtd_rewrite_work(fdtd_ctx *ctx) { return write_work_lists(ctx); }
+int fdtd_reupload(fdtd_ctx *ctx) { return upload_desc(ctx); }

@@ -1,0 +1,271 @@
+// fdtd_dev.hpp -- device-side definitions shared by the gfx950 kernels.
+//
+// Per-point arithmetic of the second-order acoustic leapfrog with the
+// kappa-inclusive CPML of the paper's section "CPML Boundary Layers"
+// (stretched derivative (1/kappa) D f + psi applied twice):
+//   psi_d  <- b psi_d + a D1_d u                        (slab points, pre-pass)
+//   eta_d   = kinv D2_d u + dkinv D1_d u + D1_d psi_d   (slab + 4-cell band)
+//   zeta_d <- b zeta_d + a eta_d                        (slab points)
+//   Lt_d    = kinv eta_d + zeta_d
+//   u^{n+1} = (2 u^n - u^{n-1}) + m * sum_d Lt_d   (+ m * source)
+// Every kernel variant evaluates a point through the functions below, in the
+// same operation order, so variants agree bit for bit.  Compiled with
+// -ffp-contract=off: every fused multiply-add is written out.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define FDTD_R 4          // stencil radius
+#define FDTD_MAXSHOTS 64
+
+// ---------------------------------------------------------------------------
+// storage types: FP32, FP16 (_Float16) and BF16 (__bf16); arithmetic is FP32.
+// ---------------------------------------------------------------------------
+template <typename T> struct Store;
+template <> struct Store<float> {
+    static __device__ __forceinline__ float ld(const float *p) { return *p; }
+    static __device__ __forceinline__ void st(float *p, float v) { *p = v; }
+    static __device__ __forceinline__ float4 ld4(const float *p) { return *(const float4 *)p; }
+    static __device__ __forceinline__ void st4(float *p, float4 v) { *(float4 *)p = v; }
+};
+template <> struct Store<_Float16> {
+    static __device__ __forceinline__ float ld(const _Float16 *p) { return (float)*p; }
+    static __device__ __forceinline__ void st(_Float16 *p, float v) { *p = (_Float16)v; }
+    static __device__ __forceinline__ float4 ld4(const _Float16 *p) {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        h4 v = *(const h4 *)p;
+        return make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
+    }
+    static __device__ __forceinline__ void st4(_Float16 *p, float4 v) {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        h4 o;
+        o.x = (_Float16)v.x;
+        o.y = (_Float16)v.y;
+        o.z = (_Float16)v.z;
+        o.w = (_Float16)v.w;
+        *(h4 *)p = o;
+    }
+};
+template <> struct Store<__bf16> {
+    static __device__ __forceinline__ float ld(const __bf16 *p) { return (float)*p; }
+    static __device__ __forceinline__ void st(__bf16 *p, float v) { *p = (__bf16)v; }
+    static __device__ __forceinline__ float4 ld4(const __bf16 *p) {
+        typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+        b4 v = *(const b4 *)p;
+        return make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
+    }
+    static __device__ __forceinline__ void st4(__bf16 *p, float4 v) {
+        typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+        b4 o;
+        o.x = (__bf16)v.x;
+        o.y = (__bf16)v.y;
+        o.z = (__bf16)v.z;
+        o.w = (__bf16)v.w;
+        *(b4 *)p = o;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// One shot as the kernels see it (device-resident; read with uniform loads).
+// Field element (x, y, z), -4 <= x < nx+4, -fy <= y < ny+fy, -fz <= z < nz+fz,
+// is at  origin + z*S + y*P + x  in both level buffers and in m.
+// ---------------------------------------------------------------------------
+struct DevShot {
+    void *u[2];            // level buffers (origin-adjusted), storage type T
+    const float *m;        // v^2 dt^2 (origin-adjusted), 0 in the frame
+    float *psi[3];         // layer memory, compact slab layouts (see psi_index)
+    float *zeta[3];
+    const float *prof;     // [3][4][nmax]: b, a, kinv, dkinv per axis index
+    const float *wav;      // source wavelet (borrowed), may be null
+    float *traces;         // [cap][nrec] or null
+    const int32_t *rec;    // [nrec][3] or null
+    float src_scale;       // amplitude * storage_scale / (hx hy hz)
+    float inv_scale;       // 1 / storage_scale
+    int src_nt, sx, sy, sz;
+    int nrec, trace_cap;
+    int nx, ny, nz, P, PY, S, fy, fz;
+    int Llo[3], Lhi[3];
+    int LX, LY, LZ, nmax;
+    int ghost[3];          // 1 if the axis has ghost (loopback) faces
+    float cc;              // (c0/hx^2 + c0/hy^2 + c0/hz^2)
+    float w2[3][5];        // c_l / h_d^2
+    float w1[3][5];        // d_l / h_d   (w1[d][0] unused)
+};
+
+// Strided box copy (ghost pack/unpack, checkpoints).
+struct CopyJob {
+    const void *src;
+    void *dst;
+    int esz;              // bytes per element (2 or 4)
+    int ex, ey, ez;       // box extent (elements)
+    long sy, sz, dy, dz;  // row / plane strides (elements) of source and destination
+};
+
+// Work item of the z-marching kernels: shot, x tile, y tile, z chunk.
+struct WorkItem {
+    int shot, tx, ty, zc;
+};
+
+// ---------------------------------------------------------------------------
+// layer geometry
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool in_slab(int c, int n, int lo, int hi) {
+    return (c < lo) || (c >= n - hi);
+}
+__device__ __forceinline__ bool in_band(int c, int n, int lo, int hi) {
+    return (lo > 0 && c < lo + FDTD_R) || (hi > 0 && c >= n - hi - FDTD_R);
+}
+// slab index along an axis of width lo+hi (valid only when in_slab)
+__device__ __forceinline__ int slab_pos(int c, int n, int lo, int hi) {
+    return c < lo ? c : lo + (c - (n - hi));
+}
+// element index of (x, y, z) in the compact psi/zeta array of axis d
+__device__ __forceinline__ long psi_index(const DevShot &s, int d, int x, int y, int z) {
+    if (d == 0) return ((long)(z + s.fz) * s.PY + (y + s.fy)) * s.LX + slab_pos(x, s.nx, s.Llo[0], s.Lhi[0]);
+    if (d == 1) return ((long)(z + s.fz) * s.LY + slab_pos(y, s.ny, s.Llo[1], s.Lhi[1])) * s.nx + x;
+    return ((long)slab_pos(z, s.nz, s.Llo[2], s.Lhi[2]) * s.PY + (y + s.fy)) * s.nx + x;
+}
+__device__ __forceinline__ int coord_n(const DevShot &s, int d) { return d == 0 ? s.nx : (d == 1 ? s.ny : s.nz); }
+
+// psi_d at (x,y,z), zero outside the slab of axis d (and outside [0,n) along d)
+__device__ __forceinline__ float psi_at(const DevShot &s, int d, int x, int y, int z) {
+    int c = d == 0 ? x : (d == 1 ? y : z);
+    int n = coord_n(s, d);
+    if (c < 0 || c >= n || !in_slab(c, n, s.Llo[d], s.Lhi[d])) return 0.0f;
+    return s.psi[d][psi_index(s, d, x, y, z)];
+}
+
+__device__ __forceinline__ float prof_at(const DevShot &s, int d, int f, int c) {
+    return s.prof[(d * 4 + f) * s.nmax + c];
+}
+
+// ---------------------------------------------------------------------------
+// stencil arithmetic (operation order is part of the contract)
+// lo[l-1] = f(c - l), hi[l-1] = f(c + l), l = 1..4
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float pairs2(const float *w, const float lo[4], const float hi[4], float acc) {
+    acc = fmaf(w[1], lo[0] + hi[0], acc);
+    acc = fmaf(w[2], lo[1] + hi[1], acc);
+    acc = fmaf(w[3], lo[2] + hi[2], acc);
+    acc = fmaf(w[4], lo[3] + hi[3], acc);
+    return acc;
+}
+__device__ __forceinline__ float d2_axis(const float *w, float c, const float lo[4], const float hi[4]) {
+    return pairs2(w, lo, hi, w[0] * c);
+}
+__device__ __forceinline__ float d1_axis(const float *w, const float lo[4], const float hi[4]) {
+    float acc = w[1] * (hi[0] - lo[0]);
+    acc = fmaf(w[2], hi[1] - lo[1], acc);
+    acc = fmaf(w[3], hi[2] - lo[2], acc);
+    acc = fmaf(w[4], hi[3] - lo[3], acc);
+    return acc;
+}
+// interior points (outside every band): cc*c + x pairs + y pairs + z pairs
+__device__ __forceinline__ float lap_interior(const DevShot &s, float c, const float xl[4], const float xh[4],
+                                              const float yl[4], const float yh[4], const float zl[4],
+                                              const float zh[4]) {
+    float acc = s.cc * c;
+    acc = pairs2(s.w2[0], xl, xh, acc);
+    acc = pairs2(s.w2[1], yl, yh, acc);
+    acc = pairs2(s.w2[2], zl, zh, acc);
+    return acc;
+}
+// layer term of one axis; zeta updated in place when the point is in the slab
+__device__ __forceinline__ float cpml_axis(float d2, float d1, float dpsi, float kinv, float dkinv, float a,
+                                           float b, bool slab, float *zeta) {
+    float eta = fmaf(kinv, d2, fmaf(dkinv, d1, dpsi));
+    float z = 0.0f;
+    if (slab) {
+        z = fmaf(b, *zeta, a * eta);
+        *zeta = z;
+    }
+    return fmaf(kinv, eta, z);
+}
+__device__ __forceinline__ float leapfrog(float m, float lt, float c, float um1) {
+    return fmaf(m, lt, fmaf(2.0f, c, -um1));
+}
+__device__ __forceinline__ float psi_update(float b, float psi, float a, float d1) {
+    return fmaf(b, psi, a * d1);
+}
+
+// Layer-aware Laplacian of one point whose neighbours are given; reads psi
+// neighbours from memory.  Returns sum_d Lt_d (or lap_interior when the point
+// is outside every band).
+__device__ __forceinline__ float lap_point(const DevShot &s, int x, int y, int z, float c, const float xl[4],
+                                           const float xh[4], const float yl[4], const float yh[4],
+                                           const float zl[4], const float zh[4]) {
+    bool bx = in_band(x, s.nx, s.Llo[0], s.Lhi[0]);
+    bool by = in_band(y, s.ny, s.Llo[1], s.Lhi[1]);
+    bool bz = in_band(z, s.nz, s.Llo[2], s.Lhi[2]);
+    if (!(bx || by || bz)) return lap_interior(s, c, xl, xh, yl, yh, zl, zh);
+    float L[3];
+    const float *lo[3] = {xl, yl, zl};
+    const float *hi[3] = {xh, yh, zh};
+    const bool band[3] = {bx, by, bz};
+    const int cc[3] = {x, y, z};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        float d2 = d2_axis(s.w2[d], c, lo[d], hi[d]);
+        if (!band[d]) {
+            L[d] = d2;
+            continue;
+        }
+        int n = coord_n(s, d);
+        int k = cc[d];
+        float d1 = d1_axis(s.w1[d], lo[d], hi[d]);
+        float pl[4], ph[4];
+#pragma unroll
+        for (int l = 1; l <= 4; ++l) {
+            int xm = x, ym = y, zm = z, xp = x, yp = y, zp = z;
+            if (d == 0) { xm -= l; xp += l; }
+            if (d == 1) { ym -= l; yp += l; }
+            if (d == 2) { zm -= l; zp += l; }
+            pl[l - 1] = psi_at(s, d, xm, ym, zm);
+            ph[l - 1] = psi_at(s, d, xp, yp, zp);
+        }
+        float dpsi = d1_axis(s.w1[d], pl, ph);
+        bool slab = in_slab(k, n, s.Llo[d], s.Lhi[d]);
+        float zv = 0.0f;
+        float *zptr = &zv;
+        if (slab) zptr = &s.zeta[d][psi_index(s, d, x, y, z)];
+        L[d] = cpml_axis(d2, d1, dpsi, prof_at(s, d, 2, k), prof_at(s, d, 3, k), prof_at(s, d, 1, k),
+                         prof_at(s, d, 0, k), slab, zptr);
+    }
+    return (L[0] + L[1]) + L[2];
+}
+
+// source amplitude (already multiplied by storage scale / cell volume) at step n
+__device__ __forceinline__ float source_at(const DevShot &s, int n) {
+    return (s.wav != nullptr && n >= 0 && n < s.src_nt) ? s.wav[n] * s.src_scale : 0.0f;
+}
+
+__device__ __forceinline__ bool any_band(const DevShot &s, int x, int y, int z) {
+    return in_band(x, s.nx, s.Llo[0], s.Lhi[0]) || in_band(y, s.ny, s.Llo[1], s.Lhi[1]) ||
+           in_band(z, s.nz, s.Llo[2], s.Lhi[2]);
+}
+
+// Full update of one point with every neighbour read from memory:
+// u^{n+1} = leapfrog(m, Lt, u^n, u^{n-1}) (+ m * src at the source node),
+// written over u^{n-1}.  The naive kernel uses it for every point and the
+// z-marching kernels for the points of the layer bands.
+template <typename T>
+__device__ __forceinline__ void point_update_global(const DevShot &s, const T *__restrict__ u, T *__restrict__ w,
+                                                    int x, int y, int z, float src) {
+    const long c = (long)z * s.S + (long)y * s.P + x;
+    float xl[4], xh[4], yl[4], yh[4], zl[4], zh[4];
+#pragma unroll
+    for (int l = 1; l <= 4; ++l) {
+        xl[l - 1] = Store<T>::ld(u + c - l);
+        xh[l - 1] = Store<T>::ld(u + c + l);
+        yl[l - 1] = Store<T>::ld(u + c - (long)l * s.P);
+        yh[l - 1] = Store<T>::ld(u + c + (long)l * s.P);
+        zl[l - 1] = Store<T>::ld(u + c - (long)l * s.S);
+        zh[l - 1] = Store<T>::ld(u + c + (long)l * s.S);
+    }
+    const float uc = Store<T>::ld(u + c);
+    const float lt = lap_point(s, x, y, z, uc, xl, xh, yl, yh, zl, zh);
+    const float mm = s.m[c];
+    float un = leapfrog(mm, lt, uc, Store<T>::ld(w + c));
+    if (x == s.sx && y == s.sy && z == s.sz) un = fmaf(mm, src, un);
+    Store<T>::st(w + c, un);
+}

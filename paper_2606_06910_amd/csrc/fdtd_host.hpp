@@ -1,0 +1,77 @@
+// fdtd_host.hpp -- host-side context of the C ABI (shared by the API,
+// adjoint and autotuner translation units).
+#pragma once
+#include "../../include/fdtd.h"
+#include "fdtd_dev.hpp"
+
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+constexpr int kOFF = 128;   // leading pad of every field (elements)
+constexpr int kTYMAX = 64;  // tallest y tile (rows) a kernel may overhang
+
+struct ShotH {
+    fdtd_shot_config c;
+    int nx = 0, ny = 0, nz = 0;
+    int gy = 0, gz = 0;        // ghost (loopback) axes
+    int s = 1, g = 4;          // exchange interval and ghost depth
+    int fy = 4, fz = 4;        // frame rows / planes
+    int P = 0, PY = 0, S = 0;  // row pitch, rows per plane, plane stride (elements)
+    size_t elems = 0;          // elements per field buffer
+    size_t esz = 4;            // bytes per stored field element
+    int Llo[3] = {0, 0, 0}, Lhi[3] = {0, 0, 0};
+    int LX = 0, LY = 0, LZ = 0, nmax = 0;
+    size_t psi_elems[3] = {0, 0, 0};
+    // workspace offsets
+    size_t o_u[2] = {0, 0}, o_m = 0, o_psi[3] = {0, 0, 0}, o_zeta[3] = {0, 0, 0}, o_prof = 0;
+    size_t o_work = 0, o_xbuf = 0, xbuf_bytes = 0;
+    size_t o_jobs[2][4] = {};
+    int njobs[2][4] = {};
+    long jobmax[2][4] = {};
+    int nwork = 0;
+    // model / source / receivers
+    bool vel_set = false;
+    double vmax = 0, vref = 0, scale = 1;
+    bool has_src = false;
+    const float *wav = nullptr;
+    int src_nt = 0, sx = 0, sy = 0, sz = 0;
+    float amp = 0;
+    const int32_t *rec = nullptr;
+    int nrec = 0;
+    float *traces = nullptr;
+    int cap = 0;
+    // plan
+    int variant = FDTD_VARIANT_ZMARCH, ry = 2, zchunk = 64, tk = 1;
+    // checkpoints / adjoint
+    int ck_every = 0, ck_count = 0, ck_nt = 0;
+    char *ck_buf = nullptr;
+    size_t ck_bytes = 0;
+};
+
+struct fdtd_ctx {
+    std::vector<ShotH> shots;
+    std::vector<DevShot> hdesc;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0, need = 0;
+    size_t o_stepc = 0, o_scratch = 0, o_desc = 0, o_work_all = 0;
+    int nwork_all = 0;
+    int storage = 0;
+    int parity = 0;     // level buffer u[parity] holds u^n
+    long step = 0;
+    bool saving = true; // checkpoint saving enabled (off during adjoint recomputation)
+    std::string err;
+    std::map<std::pair<long, long>, hipGraphExec_t> graphs;
+};
+
+// helpers exported by fdtd_api.hip for the other translation units
+size_t fdtd_state_bytes(const ShotH &s);
+char *fdtd_ws(fdtd_ctx *ctx, size_t off);
+void fdtd_enqueue_step_shot(fdtd_ctx *ctx, int shot);
+void fdtd_restore_state(fdtd_ctx *ctx, int i, char *ck);
+void *fdtd_field_origin(fdtd_ctx *ctx, const ShotH &s, size_t off);
+float *fdtd_m_origin(fdtd_ctx *ctx, const ShotH &s);
+int fdtd_rewrite_work(fdtd_ctx *ctx);
+int fdtd_reupload(fdtd_ctx *ctx);

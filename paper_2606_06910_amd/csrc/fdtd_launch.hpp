@@ -1,0 +1,23 @@
+// fdtd_launch.hpp -- host-side launcher declarations (kernels live in the .hip files).
+#pragma once
+#include "fdtd_dev.hpp"
+
+void fdtd_launch_psi(int stor, const DevShot *d_shots, int nshots, long max_count, int parity, int ext,
+                     hipStream_t st);
+void fdtd_launch_naive(int stor, const DevShot *d_shots, int shot, int nx, int Ny, int Nz, int parity, int ext,
+                       const int *stepc, hipStream_t st);
+void fdtd_launch_zmarch(int stor, const DevShot *d_shots, const WorkItem *work, int nwork, int ry, int parity,
+                        int ext, int zchunk, const int *stepc, hipStream_t st);
+void fdtd_launch_record(int stor, const DevShot *d_shots, int nshots, int parity_new, int *stepc, hipStream_t st);
+
+void fdtd_launch_fill_zero(void *p, size_t bytes, hipStream_t st);
+void fdtd_launch_vel_to_m(const float *v, float *m, int nx, int ny, int nz, int P, int S, double dt2,
+                          unsigned int *vmax_bits, unsigned int *bad, hipStream_t st);
+void fdtd_launch_get_field(int stor, const void *u, float *dst, int nx, int ny, int nz, int P, int S, float inv,
+                           hipStream_t st);
+void fdtd_launch_set_field(int stor, void *u, const float *src, int nx, int ny, int nz, int P, int S, float sc,
+                           hipStream_t st);
+void fdtd_launch_finite(int stor, const void *u, int nx, int ny, int nz, int P, int S, unsigned int *bad,
+                        hipStream_t st);
+void fdtd_launch_copy_jobs(const void *jobs, int njobs, long max_elems, hipStream_t st);
+void fdtd_launch_set_int(int *p, int v, hipStream_t st);

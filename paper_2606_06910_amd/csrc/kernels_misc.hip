@@ -1,0 +1,156 @@
+// kernels_misc.hip -- setup, conversion and ghost-exchange kernels (gfx950).
+//
+//  k_fill_zero       zero a byte range with 16-byte stores (used instead of a
+//                    runtime memset so that captured work never contains one)
+//  k_vel_to_m        m = v^2 dt^2 into the padded field layout, and max(v)
+//  k_get_field/k_set_field  dense float32 <-> padded storage (scale applied)
+//  k_copy_jobs       strided box copies: ghost-face pack into contiguous
+//                    buffers and unpack into the opposite ghost rows (the
+//                    loopback stands in for the neighbour of one GPU's
+//                    pencil-yz share, paper section "Multi-GPU Decomposition
+//                    and Halo Exchange")
+//  k_finite          flag any NaN/Inf in a field
+#include "fdtd_dev.hpp"
+
+__global__ __launch_bounds__(256) void k_fill_zero(uint4 *p, size_t n16) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n16; i += stride) p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// grid: (ceil(nx/256), ny, nz)
+__global__ __launch_bounds__(256) void k_vel_to_m(const float *__restrict__ v, float *__restrict__ m, int nx, int ny,
+                                                 int P, int S, double dt2, unsigned int *__restrict__ vmax_bits) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    float vv = 0.0f;
+    if (x < nx) {
+        vv = v[((long)z * ny + y) * nx + x];
+        m[(long)z * S + (long)y * P + x] = (float)((double)vv * (double)vv * dt2);
+    }
+    // block max of the bit patterns (v > 0, so float order == unsigned order)
+    __shared__ unsigned int red[256];
+    unsigned int b = __float_as_uint(fmaxf(vv, 0.0f));
+    red[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(vmax_bits, red[0]);
+}
+
+// minimum of v (to reject v <= 0): grid as k_vel_to_m
+__global__ __launch_bounds__(256) void k_vel_min(const float *__restrict__ v, int nx, int ny,
+                                                unsigned int *__restrict__ bad) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    float vv = v[((long)blockIdx.z * ny + blockIdx.y) * nx + x];
+    if (!(vv > 0.0f) || !isfinite(vv)) atomicOr(bad, 1u);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_get_field(const T *__restrict__ u, float *__restrict__ dst, int nx, int ny,
+                                                  int P, int S, float inv_scale) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    const int y = blockIdx.y, z = blockIdx.z;
+    dst[((long)z * ny + y) * nx + x] = Store<T>::ld(u + (long)z * S + (long)y * P + x) * inv_scale;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_set_field(T *__restrict__ u, const float *__restrict__ src, int nx, int ny,
+                                                  int P, int S, float scale) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    const int y = blockIdx.y, z = blockIdx.z;
+    Store<T>::st(u + (long)z * S + (long)y * P + x, src[((long)z * ny + y) * nx + x] * scale);
+}
+
+// grid: (ceil(ex*ey*ez / 256), njobs)
+__global__ __launch_bounds__(256) void k_copy_jobs(const CopyJob *__restrict__ jobs) {
+    const CopyJob j = jobs[blockIdx.y];
+    const long n = (long)j.ex * j.ey * j.ez;
+    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int x = (int)(t % j.ex);
+    const long r = t / j.ex;
+    const int y = (int)(r % j.ey);
+    const int z = (int)(r / j.ey);
+    const long so = (long)z * j.sz + (long)y * j.sy + x;
+    const long dof = (long)z * j.dz + (long)y * j.dy + x;
+    if (j.esz == 4) ((uint32_t *)j.dst)[dof] = ((const uint32_t *)j.src)[so];
+    else ((uint16_t *)j.dst)[dof] = ((const uint16_t *)j.src)[so];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_finite(const T *__restrict__ u, int nx, int ny, int P, int S,
+                                               unsigned int *__restrict__ bad) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    float f = Store<T>::ld(u + (long)blockIdx.z * S + (long)blockIdx.y * P + x);
+    if (!isfinite(f)) atomicOr(bad, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void fdtd_launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
+    size_t n16 = bytes / 16;
+    if (n16 == 0) return;
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, (uint4 *)p, n16);
+}
+void fdtd_launch_vel_to_m(const float *v, float *m, int nx, int ny, int nz, int P, int S, double dt2,
+                          unsigned int *vmax_bits, unsigned int *bad, hipStream_t st) {
+    dim3 grid((nx + 255) / 256, ny, nz);
+    hipLaunchKernelGGL(k_vel_min, grid, dim3(256), 0, st, v, nx, ny, bad);
+    hipLaunchKernelGGL(k_vel_to_m, grid, dim3(256), 0, st, v, m, nx, ny, P, S, dt2, vmax_bits);
+}
+template <typename T>
+static void gf(const void *u, float *dst, int nx, int ny, int nz, int P, int S, float inv, hipStream_t st) {
+    hipLaunchKernelGGL(k_get_field<T>, dim3((nx + 255) / 256, ny, nz), dim3(256), 0, st, (const T *)u, dst, nx, ny, P,
+                       S, inv);
+}
+template <typename T>
+static void sf(void *u, const float *src, int nx, int ny, int nz, int P, int S, float sc, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_field<T>, dim3((nx + 255) / 256, ny, nz), dim3(256), 0, st, (T *)u, src, nx, ny, P, S,
+                       sc);
+}
+template <typename T>
+static void fin(const void *u, int nx, int ny, int nz, int P, int S, unsigned int *bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_finite<T>, dim3((nx + 255) / 256, ny, nz), dim3(256), 0, st, (const T *)u, nx, ny, P, S, bad);
+}
+#define MISC_DISPATCH(stor, F, ...)                                                                      \
+    do {                                                                                                  \
+        if ((stor) == 1) F<_Float16>(__VA_ARGS__);                                                        \
+        else if ((stor) == 2) F<__bf16>(__VA_ARGS__);                                                     \
+        else F<float>(__VA_ARGS__);                                                                       \
+    } while (0)
+
+void fdtd_launch_get_field(int stor, const void *u, float *dst, int nx, int ny, int nz, int P, int S, float inv,
+                           hipStream_t st) {
+    MISC_DISPATCH(stor, gf, u, dst, nx, ny, nz, P, S, inv, st);
+}
+void fdtd_launch_set_field(int stor, void *u, const float *src, int nx, int ny, int nz, int P, int S, float sc,
+                           hipStream_t st) {
+    MISC_DISPATCH(stor, sf, u, src, nx, ny, nz, P, S, sc, st);
+}
+void fdtd_launch_finite(int stor, const void *u, int nx, int ny, int nz, int P, int S, unsigned int *bad,
+                        hipStream_t st) {
+    MISC_DISPATCH(stor, fin, u, nx, ny, nz, P, S, bad, st);
+}
+void fdtd_launch_copy_jobs(const void *jobs, int njobs, long max_elems, hipStream_t st) {
+    if (njobs <= 0 || max_elems <= 0) return;
+    hipLaunchKernelGGL(k_copy_jobs, dim3((unsigned)((max_elems + 255) / 256), njobs), dim3(256), 0, st,
+                       (const CopyJob *)jobs);
+}
+
+
+__global__ void k_set_int(int *p, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+void fdtd_launch_set_int(int *p, int v, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, p, v);
+}

@@ -1,0 +1,95 @@
+"""C ABI: the library loads, exports every entry point of include/fdtd.h, and
+validates configurations on the host (no GPU work involved)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "fdtd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdtd_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ["fdtd_create", "fdtd_set_velocity", "fdtd_inject_source", "fdtd_step", "fdtd_record_receivers",
+                 "fdtd_adjoint"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2606_06910_amd import _lib
+
+    L = _lib.lib()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(_lib.exported_names()) == _declared()
+
+
+def _cfg(**kw):
+    from paper_2606_06910_amd import Shot
+
+    base = dict(n=(32, 30, 28), h=(10.0, 10.0, 10.0), dt=1e-3, cpml=(5,) * 6)
+    base.update(kw)
+    return Shot(**base).c()
+
+
+def _create(cfgs):
+    from paper_2606_06910_amd import _lib
+
+    L = _lib.lib()
+    arr = (_lib.ShotConfig * len(cfgs))(*cfgs)
+    ctx = ctypes.c_void_p()
+    rc = L.fdtd_create(arr, len(cfgs), None, ctypes.byref(ctx))
+    return L, rc, ctx
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=(8, 30, 28)),                       # axis shorter than the stencil
+    dict(h=(0.0, 10.0, 10.0)),
+    dict(dt=0.0),
+    dict(cpml=(16, 5, 5, 5, 5, 5)),            # layer wider than half the axis
+    dict(cpml=(-1, 5, 5, 5, 5, 5)),
+    dict(face=(1, 1, 0, 0, 0, 0)),             # ghost faces only on y/z
+    dict(face=(0, 0, 1, 0, 0, 0)),             # ghost faces in pairs
+    dict(face=(0, 0, 1, 1, 0, 0)),             # ghost faces carry no layer
+    dict(face=(0, 0, 1, 1, 0, 0), cpml=(5, 5, 0, 0, 5, 5), exchange_every=3),
+    dict(storage=7),
+    dict(variant=9),
+    dict(variant=3, tblock_k=3),
+    dict(field_scale=3.0),
+])
+def test_create_rejects_invalid_configs(bad):
+    from paper_2606_06910_amd import _lib
+
+    L, rc, ctx = _create([_cfg(**bad)])
+    assert rc == -1, (bad, rc)
+    assert not ctx.value
+
+
+def test_create_and_workspace_size_on_host():
+    from paper_2606_06910_amd import _lib
+
+    L, rc, ctx = _create([_cfg(), _cfg(n=(40, 41, 42))])
+    assert rc == 0
+    nb = ctypes.c_size_t()
+    assert L.fdtd_workspace_size(ctx, ctypes.byref(nb)) == 0
+    # two FP32 level buffers + m per shot dominate: at least 3 * 4 bytes per padded point
+    assert nb.value > 3 * 4 * (32 * 30 * 28 + 40 * 41 * 42)
+    # calls that need a workspace fail cleanly before one is bound
+    assert L.fdtd_step(ctx, 1) == -3
+    assert b"workspace" in L.fdtd_last_error(ctx)
+    L.fdtd_destroy(ctx)
+
+
+def test_strerror_covers_every_status():
+    from paper_2606_06910_amd import _lib
+
+    L = _lib.lib()
+    for st in range(-7, 1):
+        assert L.fdtd_strerror(st) and L.fdtd_strerror(st) != b"unknown status"
