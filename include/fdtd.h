@@ -111,8 +111,11 @@ int fdtd_set_velocity(fdtd_ctx *ctx, int32_t shot, const float *v_dev);
 
 /* Point source of one shot at node (i, j, k): from step n on, u^{n+1} gains
  * m * amplitude * wavelet_dev[n] / (hx hy hz) at that node (n < nt; zero after).
- * wavelet_dev: float32[nt] device array, read during this call only (the
- * scaled series is kept in the workspace).  Replaces any previous source. */
+ * wavelet_dev: float32[nt] device array, borrowed (read by every step; keep
+ * it alive and unchanged while stepping).  With 16-bit storage and an
+ * automatic scale, this call copies the wavelet to the host once to choose
+ * the power-of-two storage scale (synchronises).  Replaces any previous
+ * source. */
 int fdtd_inject_source(fdtd_ctx *ctx, int32_t shot, int32_t i, int32_t j, int32_t k,
                        const float *wavelet_dev, int32_t nt, float amplitude);
 
@@ -184,6 +187,16 @@ int fdtd_get_plan(const fdtd_ctx *ctx, int32_t shot, int32_t *variant, int32_t *
 
 /* Storage scale of one shot (stored value = scale * u). */
 int fdtd_get_scale(const fdtd_ctx *ctx, int32_t shot, double *scale);
+
+/* Per-kernel timing for measurement: while enabled (eager fdtd_step only;
+ * fdtd_step_graph returns FDTD_EUNSUPPORTED), every launch of the kernel
+ * classes below is bracketed by HIP events on the context's stream.
+ * fdtd_get_timing synchronises, returns the mean duration (ms) and count of
+ * one class since timing was enabled, and keeps accumulating.
+ * Classes: 0 = wavefield update, 1 = psi pre-pass, 2 = receiver gather,
+ * 3 = ghost pack/unpack.  Enabling again clears the counters. */
+int fdtd_set_timing(fdtd_ctx *ctx, int32_t enable);
+int fdtd_get_timing(fdtd_ctx *ctx, int32_t kernel_class, double *mean_ms, int64_t *count);
 
 const char *fdtd_strerror(int status);
 const char *fdtd_last_error(const fdtd_ctx *ctx);

@@ -86,6 +86,8 @@ def _L():
         lib.og_step.argtypes = [og, dp, dp, ctypes.c_int, dp, dp, dp, dp, ctypes.c_long,
                                 ctypes.c_double, dp, dp]
         lib.og_adjoint_step.argtypes = [og, dp, dp, ctypes.c_int, dp, dp, dp, dp, dp]
+        lib.og_threads.argtypes = []
+        lib.og_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -131,6 +133,11 @@ class Grid:
     @property
     def npts(self) -> int:
         return int(np.prod(self.shape))
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_L().og_threads())
 
 
 def weights(r: int = 4):
@@ -214,7 +221,7 @@ class Stepper:
         self.v = v
         self.m = np.ascontiguousarray(v * v * (g.dt * g.dt))
         self.prof, self.nmax = _profiles_block(g)
-        self.work = np.zeros(7 * g.npts)
+        self.work = np.zeros(g.npts)          # grows to 7 N for the adjoint step
 
     def step(self, st: State, src_index: int = -1, src_amp: float = 0.0,
              lapf: Optional[np.ndarray] = None):
@@ -226,6 +233,8 @@ class Stepper:
             raise RuntimeError("og_step failed (%d)" % rc)
 
     def adjoint_step(self, lam: np.ndarray, lamp: np.ndarray, psib: np.ndarray, zetab: np.ndarray):
+        if self.work.size < 7 * self.g.npts:
+            self.work = np.zeros(7 * self.g.npts)
         rc = _L().og_adjoint_step(ctypes.byref(self.gc), _p(self.m), _p(self.prof), self.nmax,
                                   _p(lam), _p(lamp), _p(psib), _p(zetab), _p(self.work))
         if rc != 0:

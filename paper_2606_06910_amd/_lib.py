@@ -87,6 +87,9 @@ _SIGS = {
     "fdtd_get_plan": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "fdtd_get_scale": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "fdtd_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "fdtd_get_timing": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64)]),
     "fdtd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fdtd_last_error": (ctypes.c_char_p, [_P]),
     "fdtd_destroy": (None, [_P]),

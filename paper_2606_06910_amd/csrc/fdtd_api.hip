@@ -279,7 +279,9 @@ static void fill_desc(fdtd_ctx *ctx, int i) {
             D.w2[d][l] = (float)(kC2[l] / (h * h));
             D.w1[d][l] = (float)(kC1[l] / h);
         }
-        cc += kC2[0] / (h * h);
+        // centre weight of the difference form (the nearest pair enters as f_{+-1} - f_c)
+        D.w2[d][0] = (float)((kC2[0] + 2.0 * kC2[1]) / (h * h));
+        cc += (kC2[0] + 2.0 * kC2[1]) / (h * h);
     }
     D.cc = (float)cc;
 }
@@ -391,6 +393,46 @@ static size_t xbuf_bytes(const ShotH &s) {
 }
 
 // ---------------------------------------------------------------------------
+// per-kernel-class event timing
+// ---------------------------------------------------------------------------
+static hipEvent_t take_event(fdtd_ctx *ctx) {
+    if (ctx->ev_used == ctx->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ctx->ev_pool.push_back(e);
+    }
+    return ctx->ev_pool[ctx->ev_used++];
+}
+static hipEvent_t tic(fdtd_ctx *ctx) {
+    if (!ctx->timing) return nullptr;
+    hipEvent_t e = take_event(ctx);
+    if (e) (void)hipEventRecord(e, ctx->stream);
+    return e;
+}
+static void toc(fdtd_ctx *ctx, int cls, hipEvent_t start) {
+    if (!ctx->timing || !start) return;
+    hipEvent_t e = take_event(ctx);
+    if (!e) return;
+    (void)hipEventRecord(e, ctx->stream);
+    ctx->ev_pairs[cls].push_back(std::make_pair(start, e));
+}
+// fold recorded pairs into the sums (synchronises) and recycle the events
+static int drain_timing(fdtd_ctx *ctx) {
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int c = 0; c < 4; ++c) {
+        for (auto &pr : ctx->ev_pairs[c]) {
+            float ms = 0;
+            HIPCHK(ctx, hipEventElapsedTime(&ms, pr.first, pr.second));
+            ctx->t_sum[c] += ms;
+            ctx->t_cnt[c] += 1;
+        }
+        ctx->ev_pairs[c].clear();
+    }
+    ctx->ev_used = 0;
+    return FDTD_OK;
+}
+
+// ---------------------------------------------------------------------------
 // stepping
 // ---------------------------------------------------------------------------
 static void save_checkpoint(fdtd_ctx *ctx, int i, int k);
@@ -417,15 +459,17 @@ static void enqueue_update(fdtd_ctx *ctx, int shot, int ext) {
     const int p = ctx->parity;
     const int stor = ctx->storage;
     int lo = shot < 0 ? 0 : shot, hi = shot < 0 ? (int)ctx->shots.size() : shot + 1;
-    bool all_zmarch_same = shot < 0;
-    for (int i = lo; i < hi && all_zmarch_same; ++i) {
-        const ShotH &s = ctx->shots[i];
-        if (s.variant == FDTD_VARIANT_NAIVE || s.ry != ctx->shots[0].ry || s.zchunk != ctx->shots[0].zchunk)
-            all_zmarch_same = false;
-    }
-    if (all_zmarch_same && ctx->nwork_all > 0) {
-        fdtd_launch_zmarch(stor, dd, (const WorkItem *)wsp(ctx, ctx->o_work_all), ctx->nwork_all,
-                           ctx->shots[0].ry, p, ext, ctx->shots[0].zchunk, stepc, ctx->stream);
+    if (shot < 0 && !ctx->groups.empty()) {
+        // every z-march shot, grouped by plan; naive shots below
+        const WorkItem *wa = (const WorkItem *)wsp(ctx, ctx->o_work_all);
+        for (const auto &g : ctx->groups)
+            fdtd_launch_zmarch(stor, dd, wa + g.off, g.nwork, g.ry, p, ext, g.zchunk, stepc, ctx->stream);
+        for (int i = lo; i < hi; ++i) {
+            const ShotH &s = ctx->shots[i];
+            if (s.variant != FDTD_VARIANT_NAIVE) continue;
+            int Ny = s.ny + (s.gy ? 2 * ext : 0), Nz = s.nz + (s.gz ? 2 * ext : 0);
+            fdtd_launch_naive(stor, dd, i, s.nx, Ny, Nz, p, ext, stepc, ctx->stream);
+        }
         return;
     }
     for (int i = lo; i < hi; ++i) {
@@ -448,16 +492,26 @@ static void enqueue_step(fdtd_ctx *ctx, int shot) {
         ShotH &s = ctx->shots[i];
         if (s.ck_every > 0 && ctx->saving && n % s.ck_every == 0 && n / s.ck_every < s.ck_count)
             save_checkpoint(ctx, i, (int)(n / s.ck_every));
-        if ((s.gy || s.gz) && n % s.s == 0) enqueue_exchange(ctx, i);
+        if ((s.gy || s.gz) && n % s.s == 0) {
+            hipEvent_t t0 = tic(ctx);
+            enqueue_exchange(ctx, i);
+            toc(ctx, 3, t0);
+        }
     }
     const int ext = ghost_ext(ctx, n);
     const DevShot *dd = (const DevShot *)wsp(ctx, ctx->o_desc);
     long maxc = 0;
     for (int i = lo; i < hi; ++i)
         for (int d = 0; d < 3; ++d) maxc = std::max(maxc, psi_count(ctx->shots[i], d, ext));
+    hipEvent_t t0 = tic(ctx);
     fdtd_launch_psi(ctx->storage, dd + lo, hi - lo, maxc, ctx->parity, ext, ctx->stream);
+    toc(ctx, 1, t0);
+    t0 = tic(ctx);
     enqueue_update(ctx, shot, ext);
+    toc(ctx, 0, t0);
+    t0 = tic(ctx);
     fdtd_launch_record(ctx->storage, dd + lo, hi - lo, ctx->parity ^ 1, (int *)wsp(ctx, ctx->o_stepc), ctx->stream);
+    toc(ctx, 2, t0);
     ctx->parity ^= 1;
     ctx->step = n + 1;
 }
@@ -571,8 +625,8 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
     ctx->o_stepc = take(256);
     ctx->o_scratch = take(256);
     ctx->o_desc = take(sizeof(DevShot) * nshots);
-    size_t cap_all = 8;
-    for (auto &s : ctx->shots) cap_all += work_capacity(s);
+    size_t cap_all = 0;
+    for (auto &s : ctx->shots) cap_all += work_capacity(s) + 8;
     ctx->o_work_all = take(sizeof(WorkItem) * cap_all);
     for (auto &s : ctx->shots) {
         s.o_u[0] = take(s.elems * s.esz);
@@ -602,7 +656,7 @@ int fdtd_workspace_size(const fdtd_ctx *ctx, size_t *bytes) {
 }
 
 static int write_work_lists(fdtd_ctx *ctx) {
-    std::vector<WorkItem> all;
+    std::map<std::pair<int, int>, std::vector<WorkItem>> byplan;
     for (size_t i = 0; i < ctx->shots.size(); ++i) {
         ShotH &s = ctx->shots[i];
         std::vector<WorkItem> sp = shot_tiles(s, (int)i, s.ry, s.zchunk);
@@ -612,13 +666,25 @@ static int write_work_lists(fdtd_ctx *ctx) {
         HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_work), w.data(), sizeof(WorkItem) * w.size(), hipMemcpyHostToDevice,
                                    ctx->stream));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-        all.insert(all.end(), sp.begin(), sp.end());
+        if (s.variant != FDTD_VARIANT_NAIVE) {
+            auto &v = byplan[std::make_pair(s.ry, s.zchunk)];
+            v.insert(v.end(), sp.begin(), sp.end());
+        }
     }
-    std::vector<WorkItem> wa = xcd_order(all);
-    ctx->nwork_all = (int)wa.size();
-    HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, ctx->o_work_all), wa.data(), sizeof(WorkItem) * wa.size(),
-                               hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->groups.clear();
+    std::vector<WorkItem> all;
+    for (auto &kv : byplan) {
+        std::vector<WorkItem> wa = xcd_order(kv.second);
+        fdtd_ctx::Group g{kv.first.first, kv.first.second, all.size(), (int)wa.size()};
+        ctx->groups.push_back(g);
+        all.insert(all.end(), wa.begin(), wa.end());
+    }
+    ctx->nwork_all = (int)all.size();
+    if (!all.empty()) {
+        HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, ctx->o_work_all), all.data(), sizeof(WorkItem) * all.size(),
+                                   hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
     return FDTD_OK;
 }
 
@@ -780,8 +846,39 @@ int fdtd_step(fdtd_ctx *ctx, int32_t nsteps) {
     if (!ctx || nsteps < 0) return FDTD_EINVAL;
     int rc = ready(ctx);
     if (rc) return rc;
-    for (int k = 0; k < nsteps; ++k) enqueue_step(ctx, -1);
+    for (int k = 0; k < nsteps; ++k) {
+        enqueue_step(ctx, -1);
+        if (ctx->timing && ctx->ev_used > 4000) {
+            rc = drain_timing(ctx);
+            if (rc) return rc;
+        }
+    }
     HIPCHK(ctx, hipGetLastError());
+    return FDTD_OK;
+}
+
+int fdtd_set_timing(fdtd_ctx *ctx, int32_t enable) {
+    if (!ctx) return FDTD_EINVAL;
+    if (ctx->timing) {
+        int rc = drain_timing(ctx);
+        if (rc) return rc;
+    }
+    ctx->timing = enable != 0;
+    for (int c = 0; c < 4; ++c) {
+        ctx->t_sum[c] = 0;
+        ctx->t_cnt[c] = 0;
+        ctx->ev_pairs[c].clear();
+    }
+    ctx->ev_used = 0;
+    return FDTD_OK;
+}
+
+int fdtd_get_timing(fdtd_ctx *ctx, int32_t cls, double *mean_ms, int64_t *count) {
+    if (!ctx || cls < 0 || cls > 3 || !mean_ms || !count) return FDTD_EINVAL;
+    int rc = drain_timing(ctx);
+    if (rc) return rc;
+    *count = ctx->t_cnt[cls];
+    *mean_ms = ctx->t_cnt[cls] ? ctx->t_sum[cls] / ctx->t_cnt[cls] : 0.0;
     return FDTD_OK;
 }
 
@@ -789,6 +886,7 @@ int fdtd_step_graph(fdtd_ctx *ctx, int32_t nsteps) {
     if (!ctx || nsteps < 0) return FDTD_EINVAL;
     int rc = ready(ctx);
     if (rc) return rc;
+    if (ctx->timing) FAIL(ctx, FDTD_EUNSUPPORTED, "per-kernel timing needs eager stepping");
     if (nsteps == 0) return FDTD_OK;
     long period = 2;
     for (auto &s : ctx->shots) {
@@ -890,6 +988,7 @@ int fdtd_get_scale(const fdtd_ctx *ctx, int32_t shot, double *scale) {
 void fdtd_destroy(fdtd_ctx *ctx) {
     if (!ctx) return;
     for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -905,3 +1004,5 @@ void *fdtd_field_origin(fdtd_ctx *ctx, const ShotH &s, size_t off) { return fiel
 float *fdtd_m_origin(fdtd_ctx *ctx, const ShotH &s) { return m_origin(ctx, s); }
 int fdtd_rewrite_work(fdtd_ctx *ctx) { return write_work_lists(ctx); }
 int fdtd_reupload(fdtd_ctx *ctx) { return upload_desc(ctx); }
+int fdtd_ready(fdtd_ctx *ctx) { return ready(ctx); }
+int fdtd_zero_state(fdtd_ctx *ctx) { return zero_state(ctx); }

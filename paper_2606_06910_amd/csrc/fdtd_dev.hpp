@@ -87,8 +87,8 @@ struct DevShot {
     int Llo[3], Lhi[3];
     int LX, LY, LZ, nmax;
     int ghost[3];          // 1 if the axis has ghost (loopback) faces
-    float cc;              // (c0/hx^2 + c0/hy^2 + c0/hz^2)
-    float w2[3][5];        // c_l / h_d^2
+    float cc;              // sum_d (c0 + 2 c1) / h_d^2
+    float w2[3][5];        // (c0 + 2 c1) / h_d^2, then c_l / h_d^2 for l = 1..4
     float w1[3][5];        // d_l / h_d   (w1[d][0] unused)
 };
 
@@ -142,16 +142,22 @@ __device__ __forceinline__ float prof_at(const DevShot &s, int d, int f, int c) 
 // ---------------------------------------------------------------------------
 // stencil arithmetic (operation order is part of the contract)
 // lo[l-1] = f(c - l), hi[l-1] = f(c + l), l = 1..4
+//
+// The nearest pair enters as differences from the centre,
+//   D2 f = (c0 + 2 c1) f_c + c1 ((f_{+1} - f_c) + (f_{-1} - f_c)) + sum_{l>=2} c_l (f_{+l} + f_{-l}),
+// (all weights / h^2), which is the same operator but keeps FP32 round-off
+// from the large c0 f_c / 2 c1 f_c cancellation out of smooth fields; the
+// weight array w2 holds (c0 + 2 c1)/h^2 in slot 0.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float pairs2(const float *w, const float lo[4], const float hi[4], float acc) {
-    acc = fmaf(w[1], lo[0] + hi[0], acc);
+__device__ __forceinline__ float pairs2(const float *w, float c, const float lo[4], const float hi[4], float acc) {
+    acc = fmaf(w[1], (hi[0] - c) + (lo[0] - c), acc);
     acc = fmaf(w[2], lo[1] + hi[1], acc);
     acc = fmaf(w[3], lo[2] + hi[2], acc);
     acc = fmaf(w[4], lo[3] + hi[3], acc);
     return acc;
 }
 __device__ __forceinline__ float d2_axis(const float *w, float c, const float lo[4], const float hi[4]) {
-    return pairs2(w, lo, hi, w[0] * c);
+    return pairs2(w, c, lo, hi, w[0] * c);
 }
 __device__ __forceinline__ float d1_axis(const float *w, const float lo[4], const float hi[4]) {
     float acc = w[1] * (hi[0] - lo[0]);
@@ -160,14 +166,15 @@ __device__ __forceinline__ float d1_axis(const float *w, const float lo[4], cons
     acc = fmaf(w[4], hi[3] - lo[3], acc);
     return acc;
 }
-// interior points (outside every band): cc*c + x pairs + y pairs + z pairs
+// interior points (outside every band): cc*c + x pairs + y pairs + z pairs,
+// cc = sum_d w2[d][0]
 __device__ __forceinline__ float lap_interior(const DevShot &s, float c, const float xl[4], const float xh[4],
                                               const float yl[4], const float yh[4], const float zl[4],
                                               const float zh[4]) {
     float acc = s.cc * c;
-    acc = pairs2(s.w2[0], xl, xh, acc);
-    acc = pairs2(s.w2[1], yl, yh, acc);
-    acc = pairs2(s.w2[2], zl, zh, acc);
+    acc = pairs2(s.w2[0], c, xl, xh, acc);
+    acc = pairs2(s.w2[1], c, yl, yh, acc);
+    acc = pairs2(s.w2[2], c, zl, zh, acc);
     return acc;
 }
 // layer term of one axis; zeta updated in place when the point is in the slab

@@ -58,12 +58,26 @@ struct fdtd_ctx {
     size_t ws_bytes = 0, need = 0;
     size_t o_stepc = 0, o_scratch = 0, o_desc = 0, o_work_all = 0;
     int nwork_all = 0;
+    // multi-shot z-march launches: one per distinct (ry, zchunk) plan
+    struct Group {
+        int ry, zchunk;
+        size_t off;   // offset into the o_work_all region (items)
+        int nwork;
+    };
+    std::vector<Group> groups;
     int storage = 0;
     int parity = 0;     // level buffer u[parity] holds u^n
     long step = 0;
     bool saving = true; // checkpoint saving enabled (off during adjoint recomputation)
     std::string err;
     std::map<std::pair<long, long>, hipGraphExec_t> graphs;
+    // per-kernel-class event timing (eager stepping only)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[4];
+    double t_sum[4] = {0, 0, 0, 0};
+    long t_cnt[4] = {0, 0, 0, 0};
 };
 
 // helpers exported by fdtd_api.hip for the other translation units
@@ -75,3 +89,5 @@ void *fdtd_field_origin(fdtd_ctx *ctx, const ShotH &s, size_t off);
 float *fdtd_m_origin(fdtd_ctx *ctx, const ShotH &s);
 int fdtd_rewrite_work(fdtd_ctx *ctx);
 int fdtd_reupload(fdtd_ctx *ctx);
+int fdtd_ready(fdtd_ctx *ctx);
+int fdtd_zero_state(fdtd_ctx *ctx);

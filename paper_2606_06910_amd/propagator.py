@@ -154,6 +154,15 @@ class Propagator:
         p = cache_path.encode() if cache_path else None
         check(self.L.fdtd_autotune(self.ctx, p), self.ctx)
 
+    def set_timing(self, enable: bool) -> None:
+        check(self.L.fdtd_set_timing(self.ctx, 1 if enable else 0), self.ctx)
+
+    def timing(self, kernel_class: int = 0):
+        """(mean ms, count) of one kernel class: 0 update, 1 psi, 2 receivers, 3 exchange."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        check(self.L.fdtd_get_timing(self.ctx, kernel_class, ctypes.byref(ms), ctypes.byref(n)), self.ctx)
+        return float(ms.value), int(n.value)
+
     # -- adjoint -----------------------------------------------------------------
     def adjoint_workspace_size(self, shot: int, every: int, nt: int) -> int:
         nb = ctypes.c_size_t()

@@ -1,0 +1,108 @@
+"""GPU adjoint and velocity gradient against the FP64 oracle (through the C ABI).
+
+Bar (written here): GPU gradient vs the oracle's gradient, relative L2 <= 1e-4
+(FP32 fields, FP64 accumulation); the checkpoint interval does not change the
+result (bitwise: segment recomputation replays identical forward bits).
+"""
+import numpy as np
+import pytest
+
+import synth
+from helpers import oracle_grid, rel_l2, v32
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(n=(40, 36, 32), L=6, nt=120, seed=21, nrec=10):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = n
+    vt = synth.layered_model((nz, ny, nx), rng, nlayers=(3, 5), smooth_sigma=2.0)
+    v0 = vt * (1.0 + 0.03 * synth.smooth_field((nz, ny, nx), rng, sigma=3.0))
+    dt = synth.dt_from_courant(max(vt.max(), v0.max()), (10.0,) * 3)
+    rec = synth.receivers_on_plane(n, L, nrec, rng)
+    src = np.array([[nx // 2, ny // 2, nz // 2]], np.int32)
+    w = synth.Workload("adj", tuple(n), (10.0,) * 3, dt, nt, (L,) * 6, v0, src, synth.ricker(nt, dt, 25.0), rec)
+    return w, vt
+
+
+def _gpu_grad(w, dobs, every, storage=0):
+    import torch
+
+    from paper_2606_06910_amd import Propagator, Shot
+
+    vref = float(v32(w).max())
+    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, v_ref=vref, storage=storage)])
+    p.set_velocity(0, torch.from_numpy(w.v.astype(np.float32)).cuda())
+    p.inject_source(0, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)))
+    p.set_receivers(0, w.rec)
+    p.set_checkpointing(0, every, w.nt)
+    tr = p.record(0, w.nt)
+    p.step(w.nt)
+    torch.cuda.synchronize()
+    d = tr.cpu().double().numpy()
+    resid = torch.from_numpy((d - dobs).astype(np.float32))
+    g = p.adjoint(0, w.nt, resid).cpu().numpy()
+    p.close()
+    return d, g
+
+
+@pytest.fixture(scope="module")
+def adj_case():
+    from oracle import oracle as O
+
+    w, vt = _problem()
+    g = oracle_grid(w)
+    wt = synth.Workload("t", w.n, w.h, w.dt, w.nt, w.cpml, vt, w.src, w.wavelet, w.rec)
+    dobs = O.forward(g, v32(wt), w.nt, w.src, w.wavelet, w.rec)["traces"]
+    fwd = O.forward(g, v32(w), w.nt, w.src, w.wavelet, w.rec, keep_lapf=True)
+    gref = O.gradient(g, v32(w), w.nt, w.src, w.wavelet, w.rec, fwd["traces"] - dobs, fwd=fwd)
+    return w, dobs, fwd["traces"], gref
+
+
+def test_gradient_matches_oracle(adj_case):
+    w, dobs, tr_ref, gref = adj_case
+    d, g = _gpu_grad(w, dobs, every=25)
+    assert rel_l2(d, tr_ref) <= 1e-5
+    e = rel_l2(g, gref)
+    print("gradient rel-L2 vs oracle: %.3e" % e, flush=True)
+    assert e <= 1e-4
+
+
+def test_gradient_independent_of_checkpoint_interval(adj_case):
+    w, dobs, _, _ = adj_case
+    _, g1 = _gpu_grad(w, dobs, every=25)
+    _, g2 = _gpu_grad(w, dobs, every=7)
+    _, g3 = _gpu_grad(w, dobs, every=120)
+    assert np.array_equal(g1, g2) and np.array_equal(g1, g3)
+
+
+def test_autograd_function(adj_case):
+    import torch
+
+    from paper_2606_06910_amd import Shot
+    from paper_2606_06910_amd.autograd import simulate
+
+    w, dobs, _, gref = adj_case
+    v = torch.from_numpy(w.v.astype(np.float32)).cuda().requires_grad_(True)
+    shot = Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, v_ref=float(v32(w).max()))
+    tr = simulate(v, shot, torch.from_numpy(w.wavelet.astype(np.float32)), w.src[0], w.rec, w.nt, every=25)
+    J = 0.5 * ((tr.double() - torch.from_numpy(dobs).cuda()) ** 2).sum()
+    J.backward()
+    assert rel_l2(v.grad.double().cpu().numpy(), gref) <= 1e-4
+
+
+def test_adjoint_state_errors():
+    import torch
+
+    from paper_2606_06910_amd import FDTDError, Propagator, Shot
+
+    w, _ = _problem(n=(20, 20, 20), L=4, nt=10)
+    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml)])
+    p.set_velocity(0, torch.from_numpy(w.v.astype(np.float32)).cuda())
+    p.set_receivers(0, w.rec)
+    with pytest.raises(FDTDError):          # no checkpointing registered
+        p.adjoint(0, 10, torch.zeros(10, len(w.rec)))
+    p.set_checkpointing(0, 5, 10)
+    with pytest.raises(FDTDError):          # forward not run yet
+        p.adjoint(0, 10, torch.zeros(10, len(w.rec)))
+    p.close()
