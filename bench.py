@@ -112,7 +112,21 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--compare", action="store_true", help="also time the other kernel variants")
+    ap.add_argument("--eager", action="store_true", help="launch every step eagerly (no HIP graph)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (counter calibration run)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+
+        n = args.copy_probe * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
@@ -126,7 +140,7 @@ def main():
     n = (args.n, args.n, args.n)
     w = synth.layered(n_xyz=n, nt=K + W + 2)
     print("bench: layered %s, %d+%d steps" % (str(n), W, K), file=sys.stderr, flush=True)
-    ms, upd, psi, rec = time_gpu(w, K, W, args.variant)
+    ms, upd, psi, rec = time_gpu(w, K, W, args.variant, graph=not args.eager)
     N = w.npts
     value = N * K / (ms / 1e3) / 1e6
     upd_bytes = update_kernel_bytes(w.n, w.cpml)
@@ -145,7 +159,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "layered %dx%dx%d, 20-cell CPML on 6 faces, Ricker 10 Hz, FP32 fields" % n,
-                   "grid": list(n), "cpml": 20, "variant": args.variant},
+                   "grid": list(n), "cpml": 20, "variant": args.variant, "graph": not args.eager},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                      "kernel": "k_zmarch<float> (wavefield update)",
@@ -156,7 +170,7 @@ def main():
     if args.compare:
         var = {}
         for name, vv in (("naive", 1), ("zmarch", 2)):
-            m2, u2, _, _ = time_gpu(w, min(K, 200), W, vv)
+            m2, u2, _, _ = time_gpu(w, min(K, 200), W, vv, graph=not args.eager)
             var[name] = round(N * min(K, 200) / (m2 / 1e3) / 1e6, 1)
         out["variants_mpts"] = var
     if not args.no_cpu:

@@ -144,7 +144,9 @@ int fdtd_step_graph(fdtd_ctx *ctx, int32_t nsteps);
 int fdtd_get_field(fdtd_ctx *ctx, int32_t shot, int32_t which, float *dst_dev);
 
 /* Overwrite a wavefield of one shot from a dense float32 [nz][ny][nx] device
- * array (for initial conditions).  which as in fdtd_get_field. */
+ * array (for initial conditions).  which as in fdtd_get_field.  With 16-bit
+ * storage the state is kept as (u^n, d^n = u^n - u^{n-1}): set u^n first,
+ * then u^{n-1}. */
 int fdtd_set_field(fdtd_ctx *ctx, int32_t shot, int32_t which, const float *src_dev);
 
 /* Zero wavefields and layer memory and the step counter; keep model,
@@ -181,6 +183,13 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
  * the JSON cache at cache_path (NULL = no file).  Synchronises; leaves the
  * wavefields reset. */
 int fdtd_autotune(fdtd_ctx *ctx, const char *cache_path);
+
+/* Fix the kernel plan of one shot by hand (what fdtd_autotune chooses):
+ * variant (naive / z-march / temporal blocking), z-march tile rows per thread
+ * (1, 2 or 4: tiles of 64 x 16*rows points), z-chunk length (16..4096 planes
+ * per workgroup) and temporal depth (2 or 4, temporal blocking only).
+ * Results do not depend on the plan (same bits). */
+int fdtd_set_plan(fdtd_ctx *ctx, int32_t shot, int32_t variant, int32_t tile_ry, int32_t zchunk, int32_t tblock_k);
 
 /* Choice made for one shot: variant, tile rows per thread, temporal depth. */
 int fdtd_get_plan(const fdtd_ctx *ctx, int32_t shot, int32_t *variant, int32_t *tile_ry, int32_t *tblock_k);

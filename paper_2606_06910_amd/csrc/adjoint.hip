@@ -323,6 +323,7 @@ int fdtd_set_checkpointing(fdtd_ctx *ctx, int32_t shot, int32_t every, void *buf
     }
     if (!buf_dev) return FDTD_EINVAL;
     if (s.gy || s.gz) AFAIL(ctx, FDTD_EUNSUPPORTED, "the adjoint supports Dirichlet faces only");
+    if (s.esz != 4) AFAIL(ctx, FDTD_EUNSUPPORTED, "the adjoint runs on FP32 fields");
     if (((uintptr_t)buf_dev) & 255) AFAIL(ctx, FDTD_EINVAL, "adjoint buffer must be 256-byte aligned");
     // capacity: the largest nt this buffer holds checkpoints for
     int nck = 0;

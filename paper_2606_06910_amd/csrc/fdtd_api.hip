@@ -235,6 +235,7 @@ static void fill_desc(fdtd_ctx *ctx, int i) {
     memset(&D, 0, sizeof D);
     D.u[0] = field_origin(ctx, s, s.o_u[0]);
     D.u[1] = field_origin(ctx, s, s.o_u[1]);
+    D.dinc = s.esz == 2 ? field_origin(ctx, s, s.o_d) : nullptr;
     D.m = m_origin(ctx, s);
     for (int d = 0; d < 3; ++d) {
         D.psi[d] = (float *)wsp(ctx, s.o_psi[d]);
@@ -315,7 +316,7 @@ static void build_jobs(fdtd_ctx *ctx, int i, std::vector<CopyJob> (&jobs)[2][4],
         };
         std::vector<F> fs;
         char *un = (char *)field_origin(ctx, s, s.o_u[p]);
-        char *um = (char *)field_origin(ctx, s, s.o_u[p ^ 1]);
+        char *um = (char *)field_origin(ctx, s, s.esz == 2 ? s.o_d : s.o_u[p ^ 1]);
         fs.push_back(F{un, (int)s.esz, s.nx, (long)s.P, (long)s.S, s.g});
         if (s.g - 4 > 0) {
             fs.push_back(F{um, (int)s.esz, s.nx, (long)s.P, (long)s.S, s.g - 4});
@@ -535,9 +536,9 @@ size_t fdtd_state_bytes(const ShotH &s) {
 static void copy_state(fdtd_ctx *ctx, int i, char *ck, bool save) {
     ShotH &s = ctx->shots[i];
     size_t fb = s.elems * s.esz;
-    // slot 0 of a checkpoint always holds u^n, slot 1 u^{n-1}
+    // slot 0 of a checkpoint always holds u^n, slot 1 u^{n-1} (FP32) or d^n (16-bit)
     char *un = wsp(ctx, s.o_u[ctx->parity]);
-    char *um = wsp(ctx, s.o_u[ctx->parity ^ 1]);
+    char *um = s.esz == 2 ? wsp(ctx, s.o_d) : wsp(ctx, s.o_u[ctx->parity ^ 1]);
     size_t off = 0;
     char *dsts[2] = {un, um};
     for (int k = 0; k < 2; ++k) {
@@ -631,6 +632,7 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
     for (auto &s : ctx->shots) {
         s.o_u[0] = take(s.elems * s.esz);
         s.o_u[1] = take(s.elems * s.esz);
+        s.o_d = s.esz == 2 ? take(s.elems * s.esz) : 0;   // 16-bit: increment field
         s.o_m = take(s.elems * 4);
         for (int d = 0; d < 3; ++d) {
             s.o_psi[d] = take(s.psi_elems[d] * 4);
@@ -692,6 +694,7 @@ static int zero_state(fdtd_ctx *ctx) {
     for (auto &s : ctx->shots) {
         fdtd_launch_fill_zero(wsp(ctx, s.o_u[0]), align256(s.elems * s.esz), ctx->stream);
         fdtd_launch_fill_zero(wsp(ctx, s.o_u[1]), align256(s.elems * s.esz), ctx->stream);
+        if (s.esz == 2) fdtd_launch_fill_zero(wsp(ctx, s.o_d), align256(s.elems * s.esz), ctx->stream);
         for (int d = 0; d < 3; ++d) {
             fdtd_launch_fill_zero(wsp(ctx, s.o_psi[d]), align256(s.psi_elems[d] * 4), ctx->stream);
             fdtd_launch_fill_zero(wsp(ctx, s.o_zeta[d]), align256(s.psi_elems[d] * 4), ctx->stream);
@@ -902,17 +905,32 @@ int fdtd_step_graph(fdtd_ctx *ctx, int32_t nsteps) {
     if (it == ctx->graphs.end()) {
         long step0 = ctx->step;
         int par0 = ctx->parity;
-        HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        // capture on a private stream (the caller's may be the null stream,
+        // which cannot be captured); the graph is launched on the caller's
+        if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        hipStream_t user = ctx->stream;
+        ctx->stream = ctx->cap_stream;
+        hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            ctx->stream = user;
+            (void)hipGetLastError();
+            FAIL(ctx, FDTD_EHIP, "graph capture: %s", hipGetErrorString(e));
+        }
         for (int k = 0; k < nsteps; ++k) enqueue_step(ctx, -1);
-        hipGraph_t g;
-        HIPCHK(ctx, hipStreamEndCapture(ctx->stream, &g));
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(ctx->stream, &g);
+        ctx->stream = user;
+        ctx->step = step0;
+        ctx->parity = par0;
+        if (e != hipSuccess || !g) {
+            (void)hipGetLastError();
+            FAIL(ctx, FDTD_EHIP, "graph capture: %s", hipGetErrorString(e));
+        }
         hipGraphExec_t ge;
-        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) FAIL(ctx, FDTD_EHIP, "graph instantiate: %s", hipGetErrorString(e));
         it = ctx->graphs.emplace(key, ge).first;
-        ctx->step = step0;
-        ctx->parity = par0;
     }
     HIPCHK(ctx, hipGraphLaunch(it->second, ctx->stream));
     ctx->step += nsteps;
@@ -925,6 +943,13 @@ int fdtd_get_field(fdtd_ctx *ctx, int32_t shot, int32_t which, float *dst_dev) {
         return FDTD_EINVAL;
     if (!ctx->ws) FAIL(ctx, FDTD_ESTATE, "no workspace bound");
     ShotH &s = ctx->shots[shot];
+    if (which == 1 && s.esz == 2) {
+        // 16-bit state holds d^n = u^n - u^{n-1}
+        fdtd_launch_get_prev(ctx->storage, field_origin(ctx, s, s.o_u[ctx->parity]), field_origin(ctx, s, s.o_d),
+                             dst_dev, s.nx, s.ny, s.nz, s.P, s.S, (float)(1.0 / s.scale), ctx->stream);
+        HIPCHK(ctx, hipGetLastError());
+        return FDTD_OK;
+    }
     const void *u = field_origin(ctx, s, s.o_u[ctx->parity ^ which]);
     fdtd_launch_get_field(ctx->storage, u, dst_dev, s.nx, s.ny, s.nz, s.P, s.S, (float)(1.0 / s.scale), ctx->stream);
     HIPCHK(ctx, hipGetLastError());
@@ -936,6 +961,12 @@ int fdtd_set_field(fdtd_ctx *ctx, int32_t shot, int32_t which, const float *src_
         return FDTD_EINVAL;
     if (!ctx->ws) FAIL(ctx, FDTD_ESTATE, "no workspace bound");
     ShotH &s = ctx->shots[shot];
+    if (which == 1 && s.esz == 2) {
+        fdtd_launch_set_prev(ctx->storage, field_origin(ctx, s, s.o_u[ctx->parity]), field_origin(ctx, s, s.o_d),
+                             src_dev, s.nx, s.ny, s.nz, s.P, s.S, (float)s.scale, ctx->stream);
+        HIPCHK(ctx, hipGetLastError());
+        return FDTD_OK;
+    }
     void *u = field_origin(ctx, s, s.o_u[ctx->parity ^ which]);
     fdtd_launch_set_field(ctx->storage, u, src_dev, s.nx, s.ny, s.nz, s.P, s.S, (float)s.scale, ctx->stream);
     HIPCHK(ctx, hipGetLastError());
@@ -970,6 +1001,23 @@ int fdtd_check_finite(fdtd_ctx *ctx) {
     return FDTD_OK;
 }
 
+int fdtd_set_plan(fdtd_ctx *ctx, int32_t shot, int32_t variant, int32_t tile_ry, int32_t zchunk, int32_t tblock_k) {
+    if (!ctx || shot < 0 || shot >= (int)ctx->shots.size()) return FDTD_EINVAL;
+    if (variant < 1 || variant > 3) FAIL(ctx, FDTD_EINVAL, "variant must be naive, z-march or temporal blocking");
+    if (tile_ry != 1 && tile_ry != 2 && tile_ry != 4) FAIL(ctx, FDTD_EINVAL, "tile rows per thread must be 1, 2 or 4");
+    if (zchunk < 16 || zchunk > 4096) FAIL(ctx, FDTD_EINVAL, "z chunk must be in [16, 4096]");
+    if (variant == FDTD_VARIANT_TBLOCK && tblock_k != 2 && tblock_k != 4) FAIL(ctx, FDTD_EINVAL, "tblock_k must be 2 or 4");
+    ShotH &s = ctx->shots[shot];
+    s.variant = variant;
+    s.ry = tile_ry;
+    s.zchunk = zchunk;
+    s.tk = variant == FDTD_VARIANT_TBLOCK ? tblock_k : 1;
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    ctx->graphs.clear();
+    if (!ctx->ws) return FDTD_OK;
+    return write_work_lists(ctx);
+}
+
 int fdtd_get_plan(const fdtd_ctx *ctx, int32_t shot, int32_t *variant, int32_t *tile_ry, int32_t *tblock_k) {
     if (!ctx || shot < 0 || shot >= (int)ctx->shots.size()) return FDTD_EINVAL;
     const ShotH &s = ctx->shots[shot];
@@ -989,6 +1037,7 @@ void fdtd_destroy(fdtd_ctx *ctx) {
     if (!ctx) return;
     for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
 

@@ -72,6 +72,7 @@ template <> struct Store<__bf16> {
 // ---------------------------------------------------------------------------
 struct DevShot {
     void *u[2];            // level buffers (origin-adjusted), storage type T
+    void *dinc;            // 16-bit storage only: d^n = u^n - u^{n-1} (origin-adjusted); null for FP32
     const float *m;        // v^2 dt^2 (origin-adjusted), 0 in the frame
     float *psi[3];         // layer memory, compact slab layouts (see psi_index)
     float *zeta[3];
@@ -246,9 +247,54 @@ __device__ __forceinline__ float source_at(const DevShot &s, int n) {
     return (s.wav != nullptr && n >= 0 && n < s.src_nt) ? s.wav[n] * s.src_scale : 0.0f;
 }
 
+// coordinate folded back into [0, n) on a ghost (periodic loopback) axis
+__device__ __forceinline__ int wrap_ghost(const DevShot &s, int d, int c) {
+    const int n = coord_n(s, d);
+    if (s.ghost[d]) {
+        if (c < 0) c += n;
+        else if (c >= n) c -= n;
+    }
+    return c;
+}
+// the source node, or one of its periodic images in the ghost rows/planes
+__device__ __forceinline__ bool is_source(const DevShot &s, int x, int y, int z) {
+    return x == s.sx && wrap_ghost(s, 1, y) == s.sy && wrap_ghost(s, 2, z) == s.sz;
+}
+
 __device__ __forceinline__ bool any_band(const DevShot &s, int x, int y, int z) {
     return in_band(x, s.nx, s.Llo[0], s.Lhi[0]) || in_band(y, s.ny, s.Llo[1], s.Lhi[1]) ||
            in_band(z, s.nz, s.Llo[2], s.Lhi[2]);
+}
+
+// Time update of one point.  FP32 storage keeps (u^n, u^{n-1}) and writes
+// u^{n+1} = leapfrog(m, Lt, u^n, u^{n-1}) (+ m src) over u^{n-1}.  16-bit
+// storage keeps (u^n, d^n = u^n - u^{n-1}) and advances the same recurrence as
+//   d^{n+1} = d^n + m Lt (+ m src),   u^{n+1} = u^n + d^{n+1},
+// rounding d^{n+1} first and forming u^{n+1} from the stored d^{n+1}: a 16-bit
+// rounding of u then perturbs the position only, instead of acting as a
+// velocity error that the leapfrog amplifies by ~1/(omega dt).
+template <typename T> struct IsInc { static constexpr bool v = sizeof(T) == 2; };
+
+struct Upd {
+    float u;   // new u (u^{n+1})
+    float d;   // new d (16-bit path) -- equals the value stored
+};
+template <typename T>
+__device__ __forceinline__ Upd time_update(float m, float lt, float c, float second, bool add_src, float src) {
+    Upd r;
+    if constexpr (IsInc<T>::v) {
+        float dn = fmaf(m, lt, second);
+        if (add_src) dn = fmaf(m, src, dn);
+        const float dr = (float)(T)dn;
+        r.d = dr;
+        r.u = c + dr;
+    } else {
+        float un = leapfrog(m, lt, c, second);
+        if (add_src) un = fmaf(m, src, un);
+        r.u = un;
+        r.d = 0.0f;
+    }
+    return r;
 }
 
 // Full update of one point with every neighbour read from memory:
@@ -272,7 +318,8 @@ __device__ __forceinline__ void point_update_global(const DevShot &s, const T *_
     const float uc = Store<T>::ld(u + c);
     const float lt = lap_point(s, x, y, z, uc, xl, xh, yl, yh, zl, zh);
     const float mm = s.m[c];
-    float un = leapfrog(mm, lt, uc, Store<T>::ld(w + c));
-    if (x == s.sx && y == s.sy && z == s.sz) un = fmaf(mm, src, un);
-    Store<T>::st(w + c, un);
+    T *sec = IsInc<T>::v ? (T *)s.dinc : w;
+    const Upd r = time_update<T>(mm, lt, uc, Store<T>::ld(sec + c), is_source(s, x, y, z), src);
+    Store<T>::st(w + c, r.u);
+    if constexpr (IsInc<T>::v) Store<T>::st(sec + c, r.d);
 }

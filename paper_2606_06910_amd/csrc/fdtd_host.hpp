@@ -25,7 +25,7 @@ struct ShotH {
     int LX = 0, LY = 0, LZ = 0, nmax = 0;
     size_t psi_elems[3] = {0, 0, 0};
     // workspace offsets
-    size_t o_u[2] = {0, 0}, o_m = 0, o_psi[3] = {0, 0, 0}, o_zeta[3] = {0, 0, 0}, o_prof = 0;
+    size_t o_u[2] = {0, 0}, o_d = 0, o_m = 0, o_psi[3] = {0, 0, 0}, o_zeta[3] = {0, 0, 0}, o_prof = 0;
     size_t o_work = 0, o_xbuf = 0, xbuf_bytes = 0;
     size_t o_jobs[2][4] = {};
     int njobs[2][4] = {};
@@ -54,6 +54,7 @@ struct fdtd_ctx {
     std::vector<ShotH> shots;
     std::vector<DevShot> hdesc;
     hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
     char *ws = nullptr;
     size_t ws_bytes = 0, need = 0;
     size_t o_stepc = 0, o_scratch = 0, o_desc = 0, o_work_all = 0;

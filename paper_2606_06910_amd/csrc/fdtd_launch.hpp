@@ -19,5 +19,9 @@ void fdtd_launch_set_field(int stor, void *u, const float *src, int nx, int ny, 
                            hipStream_t st);
 void fdtd_launch_finite(int stor, const void *u, int nx, int ny, int nz, int P, int S, unsigned int *bad,
                         hipStream_t st);
+void fdtd_launch_get_prev(int stor, const void *u, const void *d, float *dst, int nx, int ny, int nz, int P, int S,
+                          float inv, hipStream_t st);
+void fdtd_launch_set_prev(int stor, const void *u, void *d, const float *src, int nx, int ny, int nz, int P, int S,
+                          float sc, hipStream_t st);
 void fdtd_launch_copy_jobs(const void *jobs, int njobs, long max_elems, hipStream_t st);
 void fdtd_launch_set_int(int *p, int v, hipStream_t st);

@@ -67,6 +67,24 @@ __global__ __launch_bounds__(256) void k_set_field(T *__restrict__ u, const floa
     Store<T>::st(u + (long)z * S + (long)y * P + x, src[((long)z * ny + y) * nx + x] * scale);
 }
 
+// 16-bit state (u^n, d^n): u^{n-1} = u^n - d^n
+template <typename T>
+__global__ __launch_bounds__(256) void k_get_prev(const T *__restrict__ u, const T *__restrict__ d, float *__restrict__ dst,
+                                                 int nx, int ny, int P, int S, float inv_scale) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    const long i = (long)blockIdx.z * S + (long)blockIdx.y * P + x;
+    dst[((long)blockIdx.z * ny + blockIdx.y) * nx + x] = (Store<T>::ld(u + i) - Store<T>::ld(d + i)) * inv_scale;
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_set_prev(const T *__restrict__ u, T *__restrict__ d, const float *__restrict__ src,
+                                                 int nx, int ny, int P, int S, float scale) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    const long i = (long)blockIdx.z * S + (long)blockIdx.y * P + x;
+    Store<T>::st(d + i, Store<T>::ld(u + i) - src[((long)blockIdx.z * ny + blockIdx.y) * nx + x] * scale);
+}
+
 // grid: (ceil(ex*ey*ez / 256), njobs)
 __global__ __launch_bounds__(256) void k_copy_jobs(const CopyJob *__restrict__ jobs) {
     const CopyJob j = jobs[blockIdx.y];
@@ -140,6 +158,24 @@ void fdtd_launch_set_field(int stor, void *u, const float *src, int nx, int ny, 
 void fdtd_launch_finite(int stor, const void *u, int nx, int ny, int nz, int P, int S, unsigned int *bad,
                         hipStream_t st) {
     MISC_DISPATCH(stor, fin, u, nx, ny, nz, P, S, bad, st);
+}
+template <typename T>
+static void gp(const void *u, const void *d, float *dst, int nx, int ny, int nz, int P, int S, float inv, hipStream_t st) {
+    hipLaunchKernelGGL(k_get_prev<T>, dim3((nx + 255) / 256, ny, nz), dim3(256), 0, st, (const T *)u, (const T *)d, dst,
+                       nx, ny, P, S, inv);
+}
+template <typename T>
+static void sp(const void *u, void *d, const float *src, int nx, int ny, int nz, int P, int S, float sc, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_prev<T>, dim3((nx + 255) / 256, ny, nz), dim3(256), 0, st, (const T *)u, (T *)d, src, nx,
+                       ny, P, S, sc);
+}
+void fdtd_launch_get_prev(int stor, const void *u, const void *d, float *dst, int nx, int ny, int nz, int P, int S,
+                          float inv, hipStream_t st) {
+    MISC_DISPATCH(stor, gp, u, d, dst, nx, ny, nz, P, S, inv, st);
+}
+void fdtd_launch_set_prev(int stor, const void *u, void *d, const float *src, int nx, int ny, int nz, int P, int S,
+                          float sc, hipStream_t st) {
+    MISC_DISPATCH(stor, sp, u, d, src, nx, ny, nz, P, S, sc, st);
 }
 void fdtd_launch_copy_jobs(const void *jobs, int njobs, long max_elems, hipStream_t st) {
     if (njobs <= 0 || max_elems <= 0) return;

@@ -115,7 +115,8 @@ template <typename T, int RY> struct ZCtx {
     static constexpr int NROW = TY + 8;
     const DevShot *s;
     const T *u;         // u^n
-    T *w;               // u^{n-1} in, u^{n+1} out
+    T *w;               // u^{n+1} out (FP32: u^{n-1} in, in place)
+    T *sec;             // second state field: FP32 u^{n-1} (== w), 16-bit d^n (updated in place)
     const float *m;
     int x0, y0, x, tx, ty;
     int yhi;
@@ -140,7 +141,7 @@ __device__ __forceinline__ void zbody(ZCtx<T, RY> &C, float4 (&q)[9][RY], float4
     float4 um1[RY], mv[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-        um1[r] = Store<T>::ld4(C.w + pz + C.rowoff[r]);
+        um1[r] = Store<T>::ld4(C.sec + pz + C.rowoff[r]);
         mv[r] = *(const float4 *)(C.m + pz + C.rowoff[r]);
     }
     float4 hv = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -158,7 +159,7 @@ __device__ __forceinline__ void zbody(ZCtx<T, RY> &C, float4 (&q)[9][RY], float4
         else ycol[j] = sm[(C.ty * RY + j) * 18 + 1 + C.tx];
     }
     const bool cpml = C.cpml_xy || z < C.zlo_band || z >= C.zhi_band;
-    const bool srcplane = (z == s.sz);
+    const bool srcplane = (wrap_ghost(s, 2, z) == s.sz);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const int y = C.y0 + C.ty * RY + r;
@@ -166,7 +167,7 @@ __device__ __forceinline__ void zbody(ZCtx<T, RY> &C, float4 (&q)[9][RY], float4
         const float4 R = sm[(4 + C.ty * RY + r) * 18 + C.tx + 2];
         const float4 Cc = q[slot(0)][r];
         const float xa[12] = {L.x, L.y, L.z, L.w, Cc.x, Cc.y, Cc.z, Cc.w, R.x, R.y, R.z, R.w};
-        float4 out;
+        float4 out, outd;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             float xl[4], xh[4], yl[4], yh[4], zl[4], zh[4];
@@ -181,20 +182,25 @@ __device__ __forceinline__ void zbody(ZCtx<T, RY> &C, float4 (&q)[9][RY], float4
             }
             const float c = xa[4 + k];
             const float lt = lap_interior(s, c, xl, xh, yl, yh, zl, zh);
-            const float mm = comp(mv[r], k);
-            float un = leapfrog(mm, lt, c, comp(um1[r], k));
-            if (srcplane && C.x + k == s.sx && y == s.sy) un = fmaf(mm, C.src, un);
-            set_comp(out, k, un);
+            const bool src = srcplane && C.x + k == s.sx && wrap_ghost(s, 1, y) == s.sy;
+            const Upd u = time_update<T>(comp(mv[r], k), lt, c, comp(um1[r], k), src, C.src);
+            set_comp(out, k, u.u);
+            set_comp(outd, k, u.d);
         }
         if (y < C.yhi) {
             T *dst = C.w + pz + C.rowoff[r];
+            T *dsd = C.sec + pz + C.rowoff[r];
             if (!cpml && C.x + 3 < s.nx) {
                 Store<T>::st4(dst, out);
+                if constexpr (IsInc<T>::v) Store<T>::st4(dsd, outd);
             } else {
-                // band points are written by the layer pass (it still needs u^{n-1} there)
+                // band points are written by the layer pass (it still needs the old state there)
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (C.x + k < s.nx && !(cpml && any_band(s, C.x + k, y, z))) Store<T>::st(dst + k, comp(out, k));
+                    if (C.x + k < s.nx && !(cpml && any_band(s, C.x + k, y, z))) {
+                        Store<T>::st(dst + k, comp(out, k));
+                        if constexpr (IsInc<T>::v) Store<T>::st(dsd + k, comp(outd, k));
+                    }
             }
         }
     }
@@ -231,6 +237,7 @@ __global__ __launch_bounds__(256) void k_zmarch(const DevShot *__restrict__ shot
     C.yhi = bx.yhi;
     C.u = (const T *)s.u[parity];
     C.w = (T *)s.u[parity ^ 1];
+    C.sec = IsInc<T>::v ? (T *)s.dinc : C.w;
     C.m = s.m;
     C.x0 = wi.tx * 64;
     C.tx = threadIdx.x & 15;

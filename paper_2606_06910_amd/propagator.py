@@ -140,6 +140,9 @@ class Propagator:
     def check_finite(self) -> None:
         check(self.L.fdtd_check_finite(self.ctx), self.ctx)
 
+    def set_plan(self, shot: int, variant: int, tile_ry: int = 2, zchunk: int = 64, tblock_k: int = 1) -> None:
+        check(self.L.fdtd_set_plan(self.ctx, shot, variant, tile_ry, zchunk, tblock_k), self.ctx)
+
     def plan(self, shot: int = 0):
         v, ry, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         check(self.L.fdtd_get_plan(self.ctx, shot, ctypes.byref(v), ctypes.byref(ry), ctypes.byref(k)), self.ctx)

@@ -29,7 +29,7 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def run_gpu(w, nt=None, snap_every=0, graph=False, **shot_kw):
+def run_gpu(w, nt=None, snap_every=0, graph=False, plan=None, **shot_kw):
     """Forward run on cuda:0.  Returns (traces, snaps, final u^n) as numpy float64."""
     import torch
 
@@ -42,6 +42,8 @@ def run_gpu(w, nt=None, snap_every=0, graph=False, **shot_kw):
                 1 if w.periodic[2] else 0, 1 if w.periodic[2] else 0]
     shot = Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, face=face, **shot_kw)
     p = Propagator([shot])
+    if plan is not None:
+        p.set_plan(0, *plan)
     p.set_velocity(0, torch.from_numpy(w.v.astype(np.float32)).cuda())
     p.inject_source(0, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)))
     p.set_receivers(0, w.rec)

@@ -46,13 +46,17 @@ def test_plain64_variants_bitwise(plain64_ref):
 
 
 def _ragged(n, h, cpml, nt, seed, nrec=12, src=None):
+    """Random model; receivers within 6 cells of the source (so that every
+    trace carries signal within the short runs) plus two anywhere."""
     rng = np.random.default_rng(seed)
     nx, ny, nz = n
     v = 1800.0 + 800.0 * rng.uniform(size=(nz, ny, nx))
     dt = synth.dt_from_courant(v.max(), h) * 0.9
     if src is None:
         src = (nx // 3, ny // 2 + 1, nz // 2 - 1)
-    rec = np.stack([rng.integers(0, nx, nrec), rng.integers(0, ny, nrec), rng.integers(0, nz, nrec)], 1)
+    near = np.array(src)[None, :] + rng.integers(-6, 7, size=(nrec - 2, 3))
+    far = np.stack([rng.integers(0, nx, 2), rng.integers(0, ny, 2), rng.integers(0, nz, 2)], 1)
+    rec = np.clip(np.concatenate([near, far]), 0, np.array(n) - 1)
     return synth.Workload("ragged", tuple(n), tuple(h), dt, nt, tuple(cpml), v,
                           np.array([src], np.int32), synth.ricker(nt, dt, 30.0), rec.astype(np.int32))
 
@@ -83,6 +87,16 @@ def test_cases_match_oracle_and_variants_agree(name):
     assert rel_l2(z[0], ref["traces"]) <= TOL
     assert rel_l2(z[1], ref["snaps"]) <= TOL
     assert np.array_equal(z[0], n[0]) and np.array_equal(z[1], n[1]) and np.array_equal(z[2], n[2])
+
+
+@pytest.mark.parametrize("ry,zc", [(1, 16), (2, 32), (4, 64), (1, 128), (4, 16), (2, 4096)])
+def test_zmarch_plans_bitwise_equal_naive(ry, zc):
+    """Every tile height / z-chunk plan gives the naive kernel's bits (several
+    x/y tiles with ragged tails, several z chunks, source inside a layer)."""
+    w = _ragged((100, 70, 150), (10.0, 10.0, 10.0), (10,) * 6, 30, 2, src=(6, 35, 75))
+    a = run_gpu(w, variant=NAIVE)
+    b = run_gpu(w, plan=(ZMARCH, ry, zc, 1))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
 
 
 def test_graph_replay_matches_eager():

@@ -55,3 +55,24 @@ def test_blob_crop_error_statement():
     print("blob160 x 1500 trace rel-L2: %s" % out, flush=True)
     assert out["f32"] <= 1e-5
     assert out["f16"] <= 1e-2
+
+
+@pytest.mark.parametrize("storage", [F16, BF16])
+def test_16bit_state_roundtrip(storage):
+    """The 16-bit state is (u^n, d^n = u^n - u^{n-1}); fdtd_set_field /
+    fdtd_get_field expose u^n and u^{n-1} and round-trip values that 16 bits hold."""
+    import torch
+
+    from paper_2606_06910_amd import Propagator, Shot
+
+    n = (20, 18, 16)
+    p = Propagator([Shot(n=n, h=(10.0,) * 3, dt=1e-3, storage=storage, field_scale=1.0)])
+    p.set_velocity(0, torch.full((16, 18, 20), 2000.0, device="cuda"))
+    g = torch.Generator().manual_seed(1)
+    a = (torch.randint(-512, 512, (16, 18, 20), generator=g).float() / 64).cuda()   # exact in 16 bits
+    b = a + (torch.randint(-64, 64, (16, 18, 20), generator=g).float() / 64).cuda()
+    p.set_field(0, 0, a)
+    p.set_field(0, 1, b)
+    assert torch.equal(p.get_field(0, 0), a)
+    assert torch.equal(p.get_field(0, 1), b)
+    p.close()
