@@ -82,6 +82,116 @@ def time_gpu(w, K, W, variant, storage=0, graph=True):
     return ms, upd, psi, rec
 
 
+def precision_leg(K=200):
+    """FP32 vs FP16 vs BF16 field storage on the 768^3 Gaussian-blob workload
+    (Mpts/s over K steps), with the error of each storage stated against the
+    stored FP64 oracle run of the central 160^3 crop (1500 steps)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2606_06910_amd import Propagator, Shot
+
+    n = 768
+    rng = np.random.default_rng(1003)
+    blobs = synth.blob_params((n, n, n), rng)
+    dt = synth.dt_from_courant(blobs.vmax, (10.0,) * 3)
+    v = synth.blob_model_torch((n, n, n), blobs)
+    wav = torch.from_numpy(synth.ricker(K + 20, dt, 12.0).astype(np.float32)).cuda()
+    out = {}
+    for name, st in (("f32", 0), ("f16", 1), ("bf16", 2)):
+        p = Propagator([Shot(n=(n, n, n), h=(10.0,) * 3, dt=dt, cpml=(20,) * 6, storage=st)])
+        p.set_velocity(0, v)
+        p.inject_source(0, (n // 2,) * 3, wav)
+        p.step(K, graph=True)
+        torch.cuda.synchronize()
+        p.reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(p.stream)
+        p.step(K, graph=True)
+        e1.record(p.stream)
+        torch.cuda.synchronize()
+        out[name] = {"mpts": round(n ** 3 * K / (e0.elapsed_time(e1) / 1e3) / 1e6, 1)}
+        p.close()
+    del v
+    torch.cuda.empty_cache()
+    # error statement: 160^3 crop, 1500 steps, vs the stored FP64 oracle traces
+    ref_path = os.path.join(ROOT, "tests", "golden", "blob160_oracle.npz")
+    if os.path.exists(ref_path):
+        ref = np.load(ref_path)
+        wc = synth.blob(crop=160, nt=1500)
+        for name, st in (("f32", 0), ("f16", 1), ("bf16", 2)):
+            p = Propagator([Shot(n=wc.n, h=wc.h, dt=wc.dt, cpml=wc.cpml, storage=st)])
+            p.set_velocity(0, torch.from_numpy(wc.v.astype(np.float32)).cuda())
+            p.inject_source(0, wc.src[0], torch.from_numpy(wc.wavelet.astype(np.float32)).cuda())
+            p.set_receivers(0, wc.rec)
+            tr = p.record(0, wc.nt)
+            p.step(wc.nt, graph=True)
+            torch.cuda.synchronize()
+            d = tr.cpu().double().numpy()
+            out[name]["trace_rel_l2_vs_fp64"] = float("%.3e" % (np.linalg.norm(d - ref["traces"]) /
+                                                              np.linalg.norm(ref["traces"])))
+            p.close()
+    out["workload"] = "blob 768^3, 20-cell CPML, Ricker 12 Hz; error on the central 160^3 crop over 1500 steps"
+    return out
+
+
+def batched_leg(K=600, nshots=24):
+    """24 shots of uneven shape (each axis uniform in [96, 288]), 15-cell CPML,
+    layered models: Mpts/s of all shots advanced together (one launch per kernel
+    class per step, HIP-graph time loop) vs the same shots one after another."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2606_06910_amd import Propagator, Shot
+
+    shapes = synth.batch_shapes(nshots)
+    shots, models, wavs = [], [], []
+    for i, sh in enumerate(shapes):
+        rng = np.random.default_rng([1004, i])
+        nx, ny, nz = sh
+        vt = synth.layered_model((nz, ny, nx), rng)
+        dt = synth.dt_from_courant(vt.max() * 1.03, (10.0,) * 3)
+        shots.append(Shot(n=sh, h=(10.0,) * 3, dt=dt, cpml=(15,) * 6))
+        models.append(torch.from_numpy(vt.astype(np.float32)).cuda())
+        wavs.append(torch.from_numpy(synth.ricker(K, dt, 10.0).astype(np.float32)).cuda())
+    npts = sum(a * b * c for a, b, c in shapes)
+
+    def setup(p, idx):
+        for j, i in enumerate(idx):
+            p.set_velocity(j, models[i])
+            nx, ny, nz = shapes[i]
+            p.inject_source(j, (nx // 2, ny // 2, nz // 2), wavs[i])
+
+    def timed(p, steps):
+        p.step(steps, graph=True)
+        torch.cuda.synchronize()
+        p.reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(p.stream)
+        p.step(steps, graph=True)
+        e1.record(p.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    pb = Propagator(shots)
+    setup(pb, range(nshots))
+    pb.autotune(os.path.join(ROOT, "paper_2606_06910_amd", "autotune_cache.json"))
+    setup(pb, range(nshots))
+    ms_b = timed(pb, K)
+    pb.close()
+    ms_s = 0.0
+    for i in range(nshots):
+        p = Propagator([shots[i]])
+        setup(p, [i])
+        ms_s += timed(p, K)
+        p.close()
+    return {"shots": nshots, "points": npts, "steps": K,
+            "batched_mpts": round(npts * K / (ms_b / 1e3) / 1e6, 1),
+            "sequential_mpts": round(npts * K / (ms_s / 1e3) / 1e6, 1)}
+
+
 def cpu_baseline(w, steps=2):
     """The FP64 oracle on the same workload: `steps` full steps after one untimed step."""
     import numpy as np
@@ -113,6 +223,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--compare", action="store_true", help="also time the other kernel variants")
     ap.add_argument("--eager", action="store_true", help="launch every step eagerly (no HIP graph)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage and batched-shot legs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration run)")
     args = ap.parse_args()
@@ -173,6 +284,11 @@ def main():
             m2, u2, _, _ = time_gpu(w, min(K, 200), W, vv, graph=not args.eager)
             var[name] = round(N * min(K, 200) / (m2 / 1e3) / 1e6, 1)
         out["variants_mpts"] = var
+    if not args.no_extra:
+        print("bench: 16-bit storage leg (768^3)", file=sys.stderr, flush=True)
+        out["storage_768"] = precision_leg()
+        print("bench: batched-shot leg (24 shots)", file=sys.stderr, flush=True)
+        out["batched_24"] = batched_leg()
     if not args.no_cpu:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)

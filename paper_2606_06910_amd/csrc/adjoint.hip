@@ -311,8 +311,7 @@ int fdtd_adjoint_workspace_size(const fdtd_ctx *ctx, int32_t shot, int32_t every
 int fdtd_set_checkpointing(fdtd_ctx *ctx, int32_t shot, int32_t every, void *buf_dev, size_t bytes) {
     if (!ctx || shot < 0 || shot >= (int)ctx->shots.size() || every < 0) return FDTD_EINVAL;
     ShotH &s = ctx->shots[shot];
-    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
-    ctx->graphs.clear();
+    fdtd_clear_graphs(ctx);
     if (every == 0) {
         s.ck_every = 0;
         s.ck_buf = nullptr;
@@ -402,13 +401,13 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
         fdtd_restore_state(ctx, shot, B + L.ck + (size_t)k * fdtd_state_bytes(s));
         fdtd_launch_set_int(stepc, s0, st);
         ctx->step = s0;
-        AHIP(ctx, hipMemcpyAsync(seg + fb, fdtd_ws(ctx, s.o_u[ctx->parity]), s.elems * s.esz,
+        AHIP(ctx, hipMemcpyAsync(seg + fb, fdtd_ws(ctx, s.o_u[ctx->iu]), s.elems * s.esz,
                                  hipMemcpyDeviceToDevice, st));
-        AHIP(ctx, hipMemcpyAsync(seg, fdtd_ws(ctx, s.o_u[ctx->parity ^ 1]), s.elems * s.esz,
+        AHIP(ctx, hipMemcpyAsync(seg, fdtd_ws(ctx, s.o_u[ctx->ium1]), s.elems * s.esz,
                                  hipMemcpyDeviceToDevice, st));
         for (int n = s0; n < s1; ++n) {
             fdtd_enqueue_step_shot(ctx, shot);
-            AHIP(ctx, hipMemcpyAsync(seg + (size_t)(n - s0 + 2) * fb, fdtd_ws(ctx, s.o_u[ctx->parity]),
+            AHIP(ctx, hipMemcpyAsync(seg + (size_t)(n - s0 + 2) * fb, fdtd_ws(ctx, s.o_u[ctx->iu]),
                                      s.elems * s.esz, hipMemcpyDeviceToDevice, st));
         }
         // reverse sweep over the segment

@@ -131,8 +131,7 @@ extern "C" int fdtd_autotune(fdtd_ctx *ctx, const char *cache_path) {
     (void)hipEventDestroy(e1);
     rc = fdtd_rewrite_work(ctx);
     if (rc) return rc;
-    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
-    ctx->graphs.clear();
+    fdtd_clear_graphs(ctx);
     write_cache(cache_path, cache);
     return fdtd_zero_state(ctx);
 }

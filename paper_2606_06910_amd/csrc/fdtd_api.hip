@@ -76,6 +76,40 @@ static void plan_shot(ShotH &s) {
     s.zchunk = 64;
     s.tk = c.tblock_k > 1 ? c.tblock_k : 1;
     if (s.variant == FDTD_VARIANT_TBLOCK && s.tk < 2) s.tk = 2;
+    // temporal blocking: four level buffers and the box B outside every band
+    s.tb_bufs = s.variant == FDTD_VARIANT_TBLOCK;
+    const int nn[3] = {s.nx, s.ny, s.nz};
+    for (int d = 0; d < 3; ++d) {
+        int lo = s.Llo[d] > 0 ? s.Llo[d] + 4 : 0;
+        int hi = s.Lhi[d] > 0 ? nn[d] - s.Lhi[d] - 4 : nn[d];
+        if (d == 0) {   // float4 columns: x bounds on multiples of 4
+            lo = (lo + 3) / 4 * 4;
+            hi = hi / 4 * 4;
+        }
+        s.blo[d] = lo;
+        s.bhi[d] = std::max(lo, hi);
+    }
+}
+
+static std::vector<WorkItem> tblock_tiles(const ShotH &s, int shot) {
+    std::vector<WorkItem> v;
+    const int K = s.tk;
+    if (!s.tb_bufs || K < 2) return v;
+    const int cx = fdtd_tblock_core(K, 0), cy = fdtd_tblock_core(K, 1);
+    const int wx = s.bhi[0] - s.blo[0] - 8 * K, wy = s.bhi[1] - s.blo[1] - 8 * K, wz = s.bhi[2] - s.blo[2] - 8 * K;
+    if (wx <= 0 || wy <= 0 || wz <= 0) return v;
+    const int ntx = (wx + cx - 1) / cx, nty = (wy + cy - 1) / cy, ntz = (wz + s.tb_zchunk - 1) / s.tb_zchunk;
+    for (int zc = 0; zc < ntz; ++zc)
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx) v.push_back(WorkItem{shot, tx, ty, zc});
+    return v;
+}
+
+static size_t tblock_capacity(const ShotH &s) {
+    // the smallest core (K = 4) and z chunk bound the tile count
+    if (!s.tb_bufs) return 0;
+    const int cx = fdtd_tblock_core(4, 0), cy = fdtd_tblock_core(4, 1);
+    return (size_t)((s.nx + cx - 1) / cx) * ((s.ny + cy - 1) / cy) * ((s.nz + s.tb_zchunk - 1) / s.tb_zchunk) + 8;
 }
 
 static int validate_shot(fdtd_ctx *ctx, const fdtd_shot_config &c, int i) {
@@ -109,9 +143,13 @@ static int validate_shot(fdtd_ctx *ctx, const fdtd_shot_config &c, int i) {
                 FAIL(ctx, FDTD_EINVAL, "shot %d: axis %d shorter than the ghost depth", i, d);
     }
     if (c.storage < 0 || c.storage > 2) FAIL(ctx, FDTD_EINVAL, "shot %d: unknown storage", i);
+    const bool ghost_faces = c.face[2] || c.face[4];
+    (void)ghost_faces;
     if (c.variant < 0 || c.variant > 3) FAIL(ctx, FDTD_EINVAL, "shot %d: unknown variant", i);
     if (c.variant == FDTD_VARIANT_TBLOCK && !(c.tblock_k == 2 || c.tblock_k == 4))
         FAIL(ctx, FDTD_EINVAL, "shot %d: tblock_k must be 2 or 4", i);
+    if (c.variant == FDTD_VARIANT_TBLOCK && (c.storage != FDTD_F32 || ghost_faces))
+        FAIL(ctx, FDTD_EINVAL, "shot %d: temporal blocking runs FP32 storage with Dirichlet faces", i);
     if (c.R < 0 || c.R >= 1 || c.kappa_max < 0 || c.alpha_frac < 0 || c.v_ref < 0)
         FAIL(ctx, FDTD_EINVAL, "shot %d: bad layer parameters", i);
     if (c.field_scale != 0) {
@@ -235,6 +273,8 @@ static void fill_desc(fdtd_ctx *ctx, int i) {
     memset(&D, 0, sizeof D);
     D.u[0] = field_origin(ctx, s, s.o_u[0]);
     D.u[1] = field_origin(ctx, s, s.o_u[1]);
+    D.u[2] = s.tb_bufs ? field_origin(ctx, s, s.o_u[2]) : nullptr;
+    D.u[3] = s.tb_bufs ? field_origin(ctx, s, s.o_u[3]) : nullptr;
     D.dinc = s.esz == 2 ? field_origin(ctx, s, s.o_d) : nullptr;
     D.m = m_origin(ctx, s);
     for (int d = 0; d < 3; ++d) {
@@ -446,30 +486,40 @@ static int ghost_ext(const fdtd_ctx *ctx, long step) {
 
 static void enqueue_exchange(fdtd_ctx *ctx, int i) {
     ShotH &s = ctx->shots[i];
-    const int p = ctx->parity;
+    const int p = ctx->iu;
     for (int ph = 0; ph < 4; ++ph) {
         if (s.njobs[p][ph] == 0) continue;
         fdtd_launch_copy_jobs(wsp(ctx, s.o_jobs[p][ph]), s.njobs[p][ph], s.jobmax[p][ph], ctx->stream);
     }
 }
 
+static Roles plain_roles(const fdtd_ctx *ctx, int ext) {
+    Roles R;
+    R.iu = ctx->iu;
+    R.ium1 = ctx->ium1;
+    R.iout = ctx->ium1;
+    R.ext = ext;
+    for (int d = 0; d < 3; ++d) R.lo[d] = R.hi[d] = 0;
+    return R;
+}
+
 // update launches of one shot or of all shots (shot < 0)
-static void enqueue_update(fdtd_ctx *ctx, int shot, int ext) {
+static void enqueue_update(fdtd_ctx *ctx, int shot, const Roles &R) {
     const DevShot *dd = (const DevShot *)wsp(ctx, ctx->o_desc);
     int *stepc = (int *)wsp(ctx, ctx->o_stepc);
-    const int p = ctx->parity;
     const int stor = ctx->storage;
+    const int ext = R.ext;
     int lo = shot < 0 ? 0 : shot, hi = shot < 0 ? (int)ctx->shots.size() : shot + 1;
     if (shot < 0 && !ctx->groups.empty()) {
         // every z-march shot, grouped by plan; naive shots below
         const WorkItem *wa = (const WorkItem *)wsp(ctx, ctx->o_work_all);
         for (const auto &g : ctx->groups)
-            fdtd_launch_zmarch(stor, dd, wa + g.off, g.nwork, g.ry, p, ext, g.zchunk, stepc, ctx->stream);
+            fdtd_launch_zmarch(stor, dd, wa + g.off, g.nwork, g.ry, R, g.zchunk, stepc, ctx->stream);
         for (int i = lo; i < hi; ++i) {
             const ShotH &s = ctx->shots[i];
             if (s.variant != FDTD_VARIANT_NAIVE) continue;
             int Ny = s.ny + (s.gy ? 2 * ext : 0), Nz = s.nz + (s.gz ? 2 * ext : 0);
-            fdtd_launch_naive(stor, dd, i, s.nx, Ny, Nz, p, ext, stepc, ctx->stream);
+            fdtd_launch_naive(stor, dd, i, s.nx, Ny, Nz, R, stepc, ctx->stream);
         }
         return;
     }
@@ -477,10 +527,10 @@ static void enqueue_update(fdtd_ctx *ctx, int shot, int ext) {
         const ShotH &s = ctx->shots[i];
         if (s.variant == FDTD_VARIANT_NAIVE) {
             int Ny = s.ny + (s.gy ? 2 * ext : 0), Nz = s.nz + (s.gz ? 2 * ext : 0);
-            fdtd_launch_naive(stor, dd, i, s.nx, Ny, Nz, p, ext, stepc, ctx->stream);
+            fdtd_launch_naive(stor, dd, i, s.nx, Ny, Nz, R, stepc, ctx->stream);
         } else {
-            fdtd_launch_zmarch(stor, dd, (const WorkItem *)wsp(ctx, s.o_work), s.nwork, s.ry, p, ext, s.zchunk,
-                               stepc, ctx->stream);
+            fdtd_launch_zmarch(stor, dd, (const WorkItem *)wsp(ctx, s.o_work), s.nwork, s.ry, R, s.zchunk, stepc,
+                               ctx->stream);
         }
     }
 }
@@ -504,17 +554,96 @@ static void enqueue_step(fdtd_ctx *ctx, int shot) {
     long maxc = 0;
     for (int i = lo; i < hi; ++i)
         for (int d = 0; d < 3; ++d) maxc = std::max(maxc, psi_count(ctx->shots[i], d, ext));
+    const Roles R = plain_roles(ctx, ext);
     hipEvent_t t0 = tic(ctx);
-    fdtd_launch_psi(ctx->storage, dd + lo, hi - lo, maxc, ctx->parity, ext, ctx->stream);
+    fdtd_launch_psi(ctx->storage, dd + lo, hi - lo, maxc, R.iu, ext, ctx->stream);
     toc(ctx, 1, t0);
     t0 = tic(ctx);
-    enqueue_update(ctx, shot, ext);
+    enqueue_update(ctx, shot, R);
     toc(ctx, 0, t0);
     t0 = tic(ctx);
-    fdtd_launch_record(ctx->storage, dd + lo, hi - lo, ctx->parity ^ 1, (int *)wsp(ctx, ctx->o_stepc), ctx->stream);
+    fdtd_launch_record(ctx->storage, dd + lo, hi - lo, R, (int *)wsp(ctx, ctx->o_stepc), ctx->stream);
     toc(ctx, 2, t0);
-    ctx->parity ^= 1;
+    std::swap(ctx->iu, ctx->ium1);
     ctx->step = n + 1;
+}
+
+// Temporal blocking applies to a single-shot context whose shot has the four
+// level buffers, a non-empty B_K, and no checkpoint saving in progress.
+static bool tblock_active(const fdtd_ctx *ctx) {
+    if (ctx->shots.size() != 1) return false;
+    const ShotH &s = ctx->shots[0];
+    if (s.variant != FDTD_VARIANT_TBLOCK || !s.tb_bufs || s.tk < 2 || s.ntbwork <= 0) return false;
+    if (s.ck_every > 0 && ctx->saving) return false;
+    return true;
+}
+
+// K steps: the interior kernel on B, then the shell level by level outside B_j
+static void enqueue_tblock(fdtd_ctx *ctx) {
+    ShotH &s = ctx->shots[0];
+    const int K = s.tk;
+    const int A = ctx->iu, Bf = ctx->ium1;
+    int spare[2], ns = 0;
+    for (int b = 0; b < 4; ++b)
+        if (b != A && b != Bf) spare[ns++] = b;
+    // level n+j lives in Lv[j+1]: n-1 -> Bf, n -> A, odd j -> spare[0], even j -> spare[1]
+    int Lv[6];
+    Lv[0] = Bf;
+    Lv[1] = A;
+    for (int j = 1; j <= 4; ++j) Lv[j + 1] = (j & 1) ? spare[0] : spare[1];
+    const DevShot *dd = (const DevShot *)wsp(ctx, ctx->o_desc);
+    int *stepc = (int *)wsp(ctx, ctx->o_stepc);
+    TBArgsHost a;
+    for (int d = 0; d < 3; ++d) {
+        a.blo[d] = s.blo[d];
+        a.bhi[d] = s.bhi[d];
+    }
+    for (int j = 0; j < 6; ++j) a.L[j] = Lv[j];
+    a.rec_zs = (const int *)wsp(ctx, s.o_reczs);
+    a.rec_ix = (const int *)wsp(ctx, s.o_recix);
+    hipEvent_t t0 = tic(ctx);
+    fdtd_launch_tblock(dd, (const WorkItem *)wsp(ctx, s.o_tbwork), s.ntbwork, K, &a, s.tb_zchunk, stepc, ctx->stream);
+    toc(ctx, 0, t0);
+    long maxc = 0;
+    for (int d = 0; d < 3; ++d) maxc = std::max(maxc, psi_count(s, d, 0));
+    for (int j = 1; j <= K; ++j) {
+        Roles R;
+        R.iu = Lv[j];
+        R.ium1 = Lv[j - 1];
+        R.iout = Lv[j + 1];
+        R.ext = 0;
+        for (int d = 0; d < 3; ++d) {
+            R.lo[d] = s.blo[d] + 4 * j;
+            R.hi[d] = s.bhi[d] - 4 * j;
+        }
+        t0 = tic(ctx);
+        fdtd_launch_psi(ctx->storage, dd, 1, maxc, R.iu, 0, ctx->stream);
+        toc(ctx, 1, t0);
+        t0 = tic(ctx);
+        fdtd_launch_zmarch(ctx->storage, dd, (const WorkItem *)wsp(ctx, s.o_work), s.nwork, s.ry, R, s.zchunk, stepc,
+                           ctx->stream);
+        toc(ctx, 0, t0);
+        t0 = tic(ctx);
+        fdtd_launch_record(ctx->storage, dd, 1, R, stepc, ctx->stream);
+        toc(ctx, 2, t0);
+    }
+    ctx->iu = Lv[K + 1];
+    ctx->ium1 = Lv[K];
+    ctx->step += K;
+}
+
+// nsteps steps of every shot (temporal blocks where they apply)
+static void enqueue_steps(fdtd_ctx *ctx, int nsteps) {
+    int k = 0;
+    while (k < nsteps) {
+        if (tblock_active(ctx) && nsteps - k >= ctx->shots[0].tk) {
+            enqueue_tblock(ctx);
+            k += ctx->shots[0].tk;
+        } else {
+            enqueue_step(ctx, -1);
+            ++k;
+        }
+    }
 }
 
 static int ready(fdtd_ctx *ctx) {
@@ -537,8 +666,8 @@ static void copy_state(fdtd_ctx *ctx, int i, char *ck, bool save) {
     ShotH &s = ctx->shots[i];
     size_t fb = s.elems * s.esz;
     // slot 0 of a checkpoint always holds u^n, slot 1 u^{n-1} (FP32) or d^n (16-bit)
-    char *un = wsp(ctx, s.o_u[ctx->parity]);
-    char *um = s.esz == 2 ? wsp(ctx, s.o_d) : wsp(ctx, s.o_u[ctx->parity ^ 1]);
+    char *un = wsp(ctx, s.o_u[ctx->iu]);
+    char *um = s.esz == 2 ? wsp(ctx, s.o_d) : wsp(ctx, s.o_u[ctx->ium1]);
     size_t off = 0;
     char *dsts[2] = {un, um};
     for (int k = 0; k < 2; ++k) {
@@ -616,6 +745,12 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
         ctx->shots.push_back(s);
     }
     ctx->storage = shots[0].storage;
+    for (auto &sh : ctx->shots)
+        if (sh.tb_bufs && nshots != 1) {
+            delete ctx;
+            fprintf(stderr, "fdtd_create: temporal blocking needs a single-shot context\n");
+            return FDTD_EINVAL;
+        }
     // workspace layout
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -632,6 +767,13 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
     for (auto &s : ctx->shots) {
         s.o_u[0] = take(s.elems * s.esz);
         s.o_u[1] = take(s.elems * s.esz);
+        if (s.tb_bufs) {
+            s.o_u[2] = take(s.elems * s.esz);
+            s.o_u[3] = take(s.elems * s.esz);
+            s.o_tbwork = take(sizeof(WorkItem) * tblock_capacity(s));
+            s.o_reczs = take(sizeof(int) * (size_t)(s.nz + 1));
+            s.o_recix = take(sizeof(int) * (size_t)kMaxRec);
+        }
         s.o_d = s.esz == 2 ? take(s.elems * s.esz) : 0;   // 16-bit: increment field
         s.o_m = take(s.elems * 4);
         for (int d = 0; d < 3; ++d) {
@@ -672,6 +814,18 @@ static int write_work_lists(fdtd_ctx *ctx) {
             auto &v = byplan[std::make_pair(s.ry, s.zchunk)];
             v.insert(v.end(), sp.begin(), sp.end());
         }
+        s.ntbwork = 0;
+        if (s.tb_bufs) {
+            std::vector<WorkItem> tb = tblock_tiles(s, (int)i);
+            if (!tb.empty()) {
+                std::vector<WorkItem> tw = xcd_order(tb);
+                if (tw.size() > tblock_capacity(s)) FAIL(ctx, FDTD_EINVAL, "tile list overflow");
+                s.ntbwork = (int)tw.size();
+                HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_tbwork), tw.data(), sizeof(WorkItem) * tw.size(),
+                                           hipMemcpyHostToDevice, ctx->stream));
+                HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            }
+        }
     }
     ctx->groups.clear();
     std::vector<WorkItem> all;
@@ -695,6 +849,8 @@ static int zero_state(fdtd_ctx *ctx) {
         fdtd_launch_fill_zero(wsp(ctx, s.o_u[0]), align256(s.elems * s.esz), ctx->stream);
         fdtd_launch_fill_zero(wsp(ctx, s.o_u[1]), align256(s.elems * s.esz), ctx->stream);
         if (s.esz == 2) fdtd_launch_fill_zero(wsp(ctx, s.o_d), align256(s.elems * s.esz), ctx->stream);
+        if (s.tb_bufs)
+            for (int b = 2; b < 4; ++b) fdtd_launch_fill_zero(wsp(ctx, s.o_u[b]), align256(s.elems * s.esz), ctx->stream);
         for (int d = 0; d < 3; ++d) {
             fdtd_launch_fill_zero(wsp(ctx, s.o_psi[d]), align256(s.psi_elems[d] * 4), ctx->stream);
             fdtd_launch_fill_zero(wsp(ctx, s.o_zeta[d]), align256(s.psi_elems[d] * 4), ctx->stream);
@@ -702,7 +858,8 @@ static int zero_state(fdtd_ctx *ctx) {
     }
     fdtd_launch_set_int((int *)wsp(ctx, ctx->o_stepc), 0, ctx->stream);
     HIPCHK(ctx, hipGetLastError());
-    ctx->parity = 0;
+    ctx->iu = 0;
+    ctx->ium1 = 1;
     ctx->step = 0;
     return FDTD_OK;
 }
@@ -713,8 +870,7 @@ int fdtd_bind_workspace(fdtd_ctx *ctx, void *dev_ptr, size_t bytes) {
     if (((uintptr_t)dev_ptr) & 255) FAIL(ctx, FDTD_EINVAL, "workspace must be 256-byte aligned");
     ctx->ws = (char *)dev_ptr;
     ctx->ws_bytes = bytes;
-    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
-    ctx->graphs.clear();
+    fdtd_clear_graphs(ctx);
     // m and profiles start at zero too (frame of m must stay zero)
     for (auto &s : ctx->shots) {
         fdtd_launch_fill_zero(wsp(ctx, s.o_m), align256(s.elems * 4), ctx->stream);
@@ -831,6 +987,24 @@ int fdtd_set_receivers(fdtd_ctx *ctx, int32_t shot, const int32_t *ijk_dev, int3
     }
     s.rec = nrec > 0 ? ijk_dev : nullptr;
     s.nrec = nrec;
+    if (s.tb_bufs && ctx->ws) {
+        // receivers sorted by z for the temporal-blocking kernel
+        if (nrec > kMaxRec) FAIL(ctx, FDTD_EINVAL, "at most %d receivers with temporal blocking", kMaxRec);
+        std::vector<int32_t> h((size_t)nrec * 3);
+        if (nrec > 0) {
+            HIPCHK(ctx, hipMemcpyAsync(h.data(), ijk_dev, h.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        }
+        std::vector<int> zs(s.nz + 1, 0), ix(std::max(nrec, 1));
+        for (int r = 0; r < nrec; ++r) zs[h[3 * r + 2] + 1]++;
+        for (int z = 0; z < s.nz; ++z) zs[z + 1] += zs[z];
+        std::vector<int> fill(zs.begin(), zs.end() - 1);
+        for (int r = 0; r < nrec; ++r) ix[fill[h[3 * r + 2]]++] = r;
+        HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_reczs), zs.data(), zs.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_recix), ix.data(), ix.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    fdtd_clear_graphs(ctx);
     return upload_desc(ctx);
 }
 
@@ -840,8 +1014,7 @@ int fdtd_record_receivers(fdtd_ctx *ctx, int32_t shot, float *traces_dev, int32_
     if (traces_dev && nt_capacity <= 0) return FDTD_EINVAL;
     s.traces = traces_dev;
     s.cap = traces_dev ? nt_capacity : 0;
-    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
-    ctx->graphs.clear();
+    fdtd_clear_graphs(ctx);
     return upload_desc(ctx);
 }
 
@@ -849,9 +1022,12 @@ int fdtd_step(fdtd_ctx *ctx, int32_t nsteps) {
     if (!ctx || nsteps < 0) return FDTD_EINVAL;
     int rc = ready(ctx);
     if (rc) return rc;
-    for (int k = 0; k < nsteps; ++k) {
-        enqueue_step(ctx, -1);
-        if (ctx->timing && ctx->ev_used > 4000) {
+    int done = 0;
+    while (done < nsteps) {
+        const int chunk = std::min(nsteps - done, 256);
+        enqueue_steps(ctx, chunk);
+        done += chunk;
+        if (ctx->timing && ctx->ev_used > 2000) {
             rc = drain_timing(ctx);
             if (rc) return rc;
         }
@@ -899,12 +1075,13 @@ int fdtd_step_graph(fdtd_ctx *ctx, int32_t nsteps) {
     // a graph embeds the checkpoint schedule only for its own start step
     bool ck = false;
     for (auto &s : ctx->shots) ck = ck || (s.ck_every > 0 && ctx->saving);
+    if (tblock_active(ctx)) period = std::max(period, (long)ctx->shots[0].tk * 4);
     long phase = ck ? ctx->step : ctx->step % period;
-    std::pair<long, long> key(nsteps, phase * 2 + ctx->parity);
+    std::pair<long, long> key(nsteps, phase * 16 + ctx->iu * 4 + ctx->ium1);
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         long step0 = ctx->step;
-        int par0 = ctx->parity;
+        int iu0 = ctx->iu, ium10 = ctx->ium1;
         // capture on a private stream (the caller's may be the null stream,
         // which cannot be captured); the graph is launched on the caller's
         if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
@@ -916,12 +1093,14 @@ int fdtd_step_graph(fdtd_ctx *ctx, int32_t nsteps) {
             (void)hipGetLastError();
             FAIL(ctx, FDTD_EHIP, "graph capture: %s", hipGetErrorString(e));
         }
-        for (int k = 0; k < nsteps; ++k) enqueue_step(ctx, -1);
+        enqueue_steps(ctx, nsteps);
+        const int end_iu = ctx->iu, end_ium1 = ctx->ium1;
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(ctx->stream, &g);
         ctx->stream = user;
         ctx->step = step0;
-        ctx->parity = par0;
+        ctx->iu = iu0;
+        ctx->ium1 = ium10;
         if (e != hipSuccess || !g) {
             (void)hipGetLastError();
             FAIL(ctx, FDTD_EHIP, "graph capture: %s", hipGetErrorString(e));
@@ -930,11 +1109,12 @@ int fdtd_step_graph(fdtd_ctx *ctx, int32_t nsteps) {
         e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) FAIL(ctx, FDTD_EHIP, "graph instantiate: %s", hipGetErrorString(e));
-        it = ctx->graphs.emplace(key, ge).first;
+        it = ctx->graphs.emplace(key, fdtd_ctx::GraphEntry{ge, end_iu, end_ium1}).first;
     }
-    HIPCHK(ctx, hipGraphLaunch(it->second, ctx->stream));
+    HIPCHK(ctx, hipGraphLaunch(it->second.exec, ctx->stream));
     ctx->step += nsteps;
-    ctx->parity ^= (nsteps & 1);
+    ctx->iu = it->second.end_iu;
+    ctx->ium1 = it->second.end_ium1;
     return FDTD_OK;
 }
 
@@ -945,12 +1125,12 @@ int fdtd_get_field(fdtd_ctx *ctx, int32_t shot, int32_t which, float *dst_dev) {
     ShotH &s = ctx->shots[shot];
     if (which == 1 && s.esz == 2) {
         // 16-bit state holds d^n = u^n - u^{n-1}
-        fdtd_launch_get_prev(ctx->storage, field_origin(ctx, s, s.o_u[ctx->parity]), field_origin(ctx, s, s.o_d),
+        fdtd_launch_get_prev(ctx->storage, field_origin(ctx, s, s.o_u[ctx->iu]), field_origin(ctx, s, s.o_d),
                              dst_dev, s.nx, s.ny, s.nz, s.P, s.S, (float)(1.0 / s.scale), ctx->stream);
         HIPCHK(ctx, hipGetLastError());
         return FDTD_OK;
     }
-    const void *u = field_origin(ctx, s, s.o_u[ctx->parity ^ which]);
+    const void *u = field_origin(ctx, s, s.o_u[which ? ctx->ium1 : ctx->iu]);
     fdtd_launch_get_field(ctx->storage, u, dst_dev, s.nx, s.ny, s.nz, s.P, s.S, (float)(1.0 / s.scale), ctx->stream);
     HIPCHK(ctx, hipGetLastError());
     return FDTD_OK;
@@ -962,12 +1142,12 @@ int fdtd_set_field(fdtd_ctx *ctx, int32_t shot, int32_t which, const float *src_
     if (!ctx->ws) FAIL(ctx, FDTD_ESTATE, "no workspace bound");
     ShotH &s = ctx->shots[shot];
     if (which == 1 && s.esz == 2) {
-        fdtd_launch_set_prev(ctx->storage, field_origin(ctx, s, s.o_u[ctx->parity]), field_origin(ctx, s, s.o_d),
+        fdtd_launch_set_prev(ctx->storage, field_origin(ctx, s, s.o_u[ctx->iu]), field_origin(ctx, s, s.o_d),
                              src_dev, s.nx, s.ny, s.nz, s.P, s.S, (float)s.scale, ctx->stream);
         HIPCHK(ctx, hipGetLastError());
         return FDTD_OK;
     }
-    void *u = field_origin(ctx, s, s.o_u[ctx->parity ^ which]);
+    void *u = field_origin(ctx, s, s.o_u[which ? ctx->ium1 : ctx->iu]);
     fdtd_launch_set_field(ctx->storage, u, src_dev, s.nx, s.ny, s.nz, s.P, s.S, (float)s.scale, ctx->stream);
     HIPCHK(ctx, hipGetLastError());
     return FDTD_OK;
@@ -1008,12 +1188,13 @@ int fdtd_set_plan(fdtd_ctx *ctx, int32_t shot, int32_t variant, int32_t tile_ry,
     if (zchunk < 16 || zchunk > 4096) FAIL(ctx, FDTD_EINVAL, "z chunk must be in [16, 4096]");
     if (variant == FDTD_VARIANT_TBLOCK && tblock_k != 2 && tblock_k != 4) FAIL(ctx, FDTD_EINVAL, "tblock_k must be 2 or 4");
     ShotH &s = ctx->shots[shot];
+    if (variant == FDTD_VARIANT_TBLOCK && !s.tb_bufs)
+        FAIL(ctx, FDTD_EINVAL, "create the shot with the temporal-blocking variant to switch to it");
     s.variant = variant;
     s.ry = tile_ry;
     s.zchunk = zchunk;
     s.tk = variant == FDTD_VARIANT_TBLOCK ? tblock_k : 1;
-    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
-    ctx->graphs.clear();
+    fdtd_clear_graphs(ctx);
     if (!ctx->ws) return FDTD_OK;
     return write_work_lists(ctx);
 }
@@ -1035,7 +1216,7 @@ int fdtd_get_scale(const fdtd_ctx *ctx, int32_t shot, double *scale) {
 
 void fdtd_destroy(fdtd_ctx *ctx) {
     if (!ctx) return;
-    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    fdtd_clear_graphs(ctx);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;

@@ -71,7 +71,7 @@ template <> struct Store<__bf16> {
 // is at  origin + z*S + y*P + x  in both level buffers and in m.
 // ---------------------------------------------------------------------------
 struct DevShot {
-    void *u[2];            // level buffers (origin-adjusted), storage type T
+    void *u[4];            // level buffers (origin-adjusted), storage type T; [2], [3] only with temporal blocking
     void *dinc;            // 16-bit storage only: d^n = u^n - u^{n-1} (origin-adjusted); null for FP32
     const float *m;        // v^2 dt^2 (origin-adjusted), 0 in the frame
     float *psi[3];         // layer memory, compact slab layouts (see psi_index)
@@ -101,6 +101,19 @@ struct CopyJob {
     int ex, ey, ez;       // box extent (elements)
     long sy, sz, dy, dz;  // row / plane strides (elements) of source and destination
 };
+
+// Roles of the level buffers in one launch and an optional box of points the
+// launch leaves alone (inner region advanced by the temporal-blocking kernel).
+struct Roles {
+    int iu;          // buffer holding u^n
+    int ium1;        // buffer holding u^{n-1} (FP32 storage)
+    int iout;        // buffer receiving u^{n+1} (== ium1 for the in-place step)
+    int ext;         // ghost-box extension of this sub-step
+    int lo[3], hi[3];  // exclusion box [lo, hi) per axis; empty when lo >= hi on any axis
+};
+__device__ __forceinline__ bool in_box(const Roles &R, int x, int y, int z) {
+    return x >= R.lo[0] && x < R.hi[0] && y >= R.lo[1] && y < R.hi[1] && z >= R.lo[2] && z < R.hi[2];
+}
 
 // Work item of the z-marching kernels: shot, x tile, y tile, z chunk.
 struct WorkItem {
@@ -302,8 +315,9 @@ __device__ __forceinline__ Upd time_update(float m, float lt, float c, float sec
 // written over u^{n-1}.  The naive kernel uses it for every point and the
 // z-marching kernels for the points of the layer bands.
 template <typename T>
-__device__ __forceinline__ void point_update_global(const DevShot &s, const T *__restrict__ u, T *__restrict__ w,
-                                                    int x, int y, int z, float src) {
+__device__ __forceinline__ void point_update_global(const DevShot &s, const T *__restrict__ u,
+                                                    const T *__restrict__ um, T *__restrict__ w, int x, int y, int z,
+                                                    float src) {
     const long c = (long)z * s.S + (long)y * s.P + x;
     float xl[4], xh[4], yl[4], yh[4], zl[4], zh[4];
 #pragma unroll
@@ -318,7 +332,7 @@ __device__ __forceinline__ void point_update_global(const DevShot &s, const T *_
     const float uc = Store<T>::ld(u + c);
     const float lt = lap_point(s, x, y, z, uc, xl, xh, yl, yh, zl, zh);
     const float mm = s.m[c];
-    T *sec = IsInc<T>::v ? (T *)s.dinc : w;
+    T *sec = IsInc<T>::v ? (T *)s.dinc : (T *)um;
     const Upd r = time_update<T>(mm, lt, uc, Store<T>::ld(sec + c), is_source(s, x, y, z), src);
     Store<T>::st(w + c, r.u);
     if constexpr (IsInc<T>::v) Store<T>::st(sec + c, r.d);

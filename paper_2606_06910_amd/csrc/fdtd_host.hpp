@@ -11,6 +11,7 @@
 
 constexpr int kOFF = 128;   // leading pad of every field (elements)
 constexpr int kTYMAX = 64;  // tallest y tile (rows) a kernel may overhang
+constexpr int kMaxRec = 65536;  // receivers per shot with temporal blocking
 
 struct ShotH {
     fdtd_shot_config c;
@@ -25,7 +26,7 @@ struct ShotH {
     int LX = 0, LY = 0, LZ = 0, nmax = 0;
     size_t psi_elems[3] = {0, 0, 0};
     // workspace offsets
-    size_t o_u[2] = {0, 0}, o_d = 0, o_m = 0, o_psi[3] = {0, 0, 0}, o_zeta[3] = {0, 0, 0}, o_prof = 0;
+    size_t o_u[4] = {0, 0, 0, 0}, o_d = 0, o_m = 0, o_psi[3] = {0, 0, 0}, o_zeta[3] = {0, 0, 0}, o_prof = 0;
     size_t o_work = 0, o_xbuf = 0, xbuf_bytes = 0;
     size_t o_jobs[2][4] = {};
     int njobs[2][4] = {};
@@ -44,6 +45,13 @@ struct ShotH {
     int cap = 0;
     // plan
     int variant = FDTD_VARIANT_ZMARCH, ry = 2, zchunk = 64, tk = 1;
+    // temporal blocking (FP32, Dirichlet, single-shot contexts): 4 level buffers,
+    // interior box B (outside every band, x bounds multiples of 4), tile list over B_K,
+    // receivers sorted by z
+    bool tb_bufs = false;
+    int blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0};
+    size_t o_tbwork = 0, o_reczs = 0, o_recix = 0;
+    int ntbwork = 0, tb_zchunk = 64;
     // checkpoints / adjoint
     int ck_every = 0, ck_count = 0, ck_nt = 0;
     char *ck_buf = nullptr;
@@ -67,11 +75,16 @@ struct fdtd_ctx {
     };
     std::vector<Group> groups;
     int storage = 0;
-    int parity = 0;     // level buffer u[parity] holds u^n
+    int iu = 0;         // level buffer holding u^n
+    int ium1 = 1;       // level buffer holding u^{n-1} (FP32) -- 16-bit keeps d^n in its own buffer
     long step = 0;
     bool saving = true; // checkpoint saving enabled (off during adjoint recomputation)
     std::string err;
-    std::map<std::pair<long, long>, hipGraphExec_t> graphs;
+    struct GraphEntry {
+        hipGraphExec_t exec;
+        int end_iu, end_ium1;
+    };
+    std::map<std::pair<long, long>, GraphEntry> graphs;
     // per-kernel-class event timing (eager stepping only)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -92,3 +105,8 @@ int fdtd_rewrite_work(fdtd_ctx *ctx);
 int fdtd_reupload(fdtd_ctx *ctx);
 int fdtd_ready(fdtd_ctx *ctx);
 int fdtd_zero_state(fdtd_ctx *ctx);
+
+inline void fdtd_clear_graphs(fdtd_ctx *ctx) {
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second.exec);
+    ctx->graphs.clear();
+}

@@ -2,13 +2,23 @@
 #pragma once
 #include "fdtd_dev.hpp"
 
-void fdtd_launch_psi(int stor, const DevShot *d_shots, int nshots, long max_count, int parity, int ext,
+void fdtd_launch_psi(int stor, const DevShot *d_shots, int nshots, long max_count, int iu, int ext,
                      hipStream_t st);
-void fdtd_launch_naive(int stor, const DevShot *d_shots, int shot, int nx, int Ny, int Nz, int parity, int ext,
+void fdtd_launch_naive(int stor, const DevShot *d_shots, int shot, int nx, int Ny, int Nz, const Roles &R,
                        const int *stepc, hipStream_t st);
-void fdtd_launch_zmarch(int stor, const DevShot *d_shots, const WorkItem *work, int nwork, int ry, int parity,
-                        int ext, int zchunk, const int *stepc, hipStream_t st);
-void fdtd_launch_record(int stor, const DevShot *d_shots, int nshots, int parity_new, int *stepc, hipStream_t st);
+void fdtd_launch_zmarch(int stor, const DevShot *d_shots, const WorkItem *work, int nwork, int ry, const Roles &R,
+                        int zchunk, const int *stepc, hipStream_t st);
+void fdtd_launch_record(int stor, const DevShot *d_shots, int nshots, const Roles &R, int *stepc, hipStream_t st);
+// temporal blocking: args points to a host TBArgs (kernels_tblock.hip); K = 2 or 4
+void fdtd_launch_tblock(const DevShot *d_shots, const WorkItem *work, int nwork, int K, const void *args, int zchunk,
+                        const int *stepc, hipStream_t st);
+int fdtd_tblock_core(int K, int axis);
+struct TBArgsHost {
+    int blo[3], bhi[3];
+    int L[6];
+    const int *rec_zs;
+    const int *rec_ix;
+};
 
 void fdtd_launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 void fdtd_launch_vel_to_m(const float *v, float *m, int nx, int ny, int nz, int P, int S, double dt2,

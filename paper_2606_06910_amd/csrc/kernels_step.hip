@@ -32,7 +32,7 @@ __device__ __forceinline__ Box shot_box(const DevShot &s, int ext) {
 // psi pre-pass.  grid: (blocks over the largest slab, 3 axes, shots)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_psi(const DevShot *__restrict__ shots, int parity, int ext) {
+__global__ __launch_bounds__(256) void k_psi(const DevShot *__restrict__ shots, int iu, int ext) {
     const DevShot &s = shots[blockIdx.z];
     const int d = blockIdx.y;
     const int lo = s.Llo[d], hi = s.Lhi[d];
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_psi(const DevShot *__restrict__ shots, 
         z = ks < lo ? ks : s.nz - hi + (ks - lo);
         k = z;
     }
-    const T *u = (const T *)s.u[parity];
+    const T *u = (const T *)s.u[iu];
     const long c = (long)z * s.S + (long)y * s.P + x;
     const long stride = d == 0 ? 1 : (d == 1 ? s.P : s.S);
     float fl[4], fh[4];
@@ -86,15 +86,16 @@ __global__ __launch_bounds__(256) void k_psi(const DevShot *__restrict__ shots, 
 // naive update: one thread per point.  grid: (ceil(nx/64), ceil(Ny/4), Nz)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_update_naive(const DevShot *__restrict__ shots, int shot, int parity,
-                                                     int ext, const int *__restrict__ stepc) {
+__global__ __launch_bounds__(256) void k_update_naive(const DevShot *__restrict__ shots, int shot, Roles R,
+                                                     const int *__restrict__ stepc) {
     const DevShot &s = shots[shot];
-    Box bx = shot_box(s, ext);
+    Box bx = shot_box(s, R.ext);
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = bx.ylo + blockIdx.y * 4 + threadIdx.y;
     const int z = bx.zlo + blockIdx.z;
-    if (x >= s.nx || y >= bx.yhi || z >= bx.zhi) return;
-    point_update_global<T>(s, (const T *)s.u[parity], (T *)s.u[parity ^ 1], x, y, z, source_at(s, *stepc));
+    if (x >= s.nx || y >= bx.yhi || z >= bx.zhi || in_box(R, x, y, z)) return;
+    point_update_global<T>(s, (const T *)s.u[R.iu], (const T *)s.u[R.ium1], (T *)s.u[R.iout], x, y, z,
+                           source_at(s, *stepc));
 }
 
 // ---------------------------------------------------------------------------
@@ -115,8 +116,10 @@ template <typename T, int RY> struct ZCtx {
     static constexpr int NROW = TY + 8;
     const DevShot *s;
     const T *u;         // u^n
-    T *w;               // u^{n+1} out (FP32: u^{n-1} in, in place)
-    T *sec;             // second state field: FP32 u^{n-1} (== w), 16-bit d^n (updated in place)
+    const T *um;        // u^{n-1} (FP32 storage)
+    T *w;               // u^{n+1} out (FP32: may equal um, in-place step)
+    T *sec;             // second state field: FP32 u^{n-1}, 16-bit d^n (updated in place)
+    const Roles *R;     // roles and exclusion box
     const float *m;
     int x0, y0, x, tx, ty;
     int yhi;
@@ -124,6 +127,7 @@ template <typename T, int RY> struct ZCtx {
     int halo_slot;      // LDS float4 index this thread fills, -1 if none
     long halo_off;      // element offset (within a plane) of that halo float4
     bool cpml_xy;       // tile touches an x or y band
+    bool partial;       // tile's xy footprint overlaps the exclusion box only partly
     int zlo_band, zhi_band; // z band: z < zlo_band || z >= zhi_band
     int step;
     float src;
@@ -190,14 +194,16 @@ __device__ __forceinline__ void zbody(ZCtx<T, RY> &C, float4 (&q)[9][RY], float4
         if (y < C.yhi) {
             T *dst = C.w + pz + C.rowoff[r];
             T *dsd = C.sec + pz + C.rowoff[r];
-            if (!cpml && C.x + 3 < s.nx) {
+            if (!cpml && !C.partial && C.x + 3 < s.nx) {
                 Store<T>::st4(dst, out);
                 if constexpr (IsInc<T>::v) Store<T>::st4(dsd, outd);
             } else {
-                // band points are written by the layer pass (it still needs the old state there)
+                // band points are written by the layer pass (it still needs the old state there);
+                // points of the exclusion box are left alone
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (C.x + k < s.nx && !(cpml && any_band(s, C.x + k, y, z))) {
+                    if (C.x + k < s.nx && !(cpml && any_band(s, C.x + k, y, z)) &&
+                        !(C.partial && in_box(*C.R, C.x + k, y, z))) {
                         Store<T>::st(dst + k, comp(out, k));
                         if constexpr (IsInc<T>::v) Store<T>::st(dsd + k, comp(outd, k));
                     }
@@ -214,18 +220,20 @@ __device__ __forceinline__ void zband_points(ZCtx<T, RY> &C, int z) {
     for (int i = 0; i < 4 * RY; ++i) {
         const int x = C.x + (i & 3);
         const int y = C.y0 + C.ty * RY + (i >> 2);
-        if (x < s.nx && y < C.yhi && any_band(s, x, y, z)) point_update_global<T>(s, C.u, C.w, x, y, z, C.src);
+        if (x < s.nx && y < C.yhi && any_band(s, x, y, z) && !in_box(*C.R, x, y, z))
+            point_update_global<T>(s, C.u, C.um, C.w, x, y, z, C.src);
     }
 }
 
 template <typename T, int RY>
 __global__ __launch_bounds__(256) void k_zmarch(const DevShot *__restrict__ shots, const WorkItem *__restrict__ work,
-                                               int parity, int ext, int zchunk, const int *__restrict__ stepc) {
+                                               Roles R, int zchunk, const int *__restrict__ stepc) {
     constexpr int TY = 16 * RY;
     constexpr int NROW = TY + 8;
     __shared__ float4 sm[NROW * 18];
     const WorkItem wi = work[blockIdx.x];
     const DevShot &s = shots[wi.shot];
+    const int ext = R.ext;
     Box bx = shot_box(s, ext);
     ZCtx<T, RY> C;
     C.s = &s;
@@ -235,9 +243,11 @@ __global__ __launch_bounds__(256) void k_zmarch(const DevShot *__restrict__ shot
     if (zb >= bx.zhi) return;
     const int ze = min(zb + zchunk, bx.zhi);
     C.yhi = bx.yhi;
-    C.u = (const T *)s.u[parity];
-    C.w = (T *)s.u[parity ^ 1];
-    C.sec = IsInc<T>::v ? (T *)s.dinc : C.w;
+    C.u = (const T *)s.u[R.iu];
+    C.um = (const T *)s.u[R.ium1];
+    C.w = (T *)s.u[R.iout];
+    C.sec = IsInc<T>::v ? (T *)s.dinc : (T *)s.u[R.ium1];
+    C.R = &R;
     C.m = s.m;
     C.x0 = wi.tx * 64;
     C.tx = threadIdx.x & 15;
@@ -272,27 +282,51 @@ __global__ __launch_bounds__(256) void k_zmarch(const DevShot *__restrict__ shot
     C.step = *stepc;
     C.src = source_at(s, C.step);
 
-    float4 q[9][RY];
-#pragma unroll
-    for (int o = -4; o < 4; ++o)
-#pragma unroll
-        for (int r = 0; r < RY; ++r) q[o + 4][r] = Store<T>::ld4(C.u + (long)(zb + o) * s.S + C.rowoff[r]);
-#pragma unroll
-    for (int r = 0; r < RY; ++r) q[8][r] = make_float4(0.f, 0.f, 0.f, 0.f);
-
-    for (int z = zb; z < ze; ++z) {
-        switch ((z - zb) % 9) {
-        case 0: zbody<T, RY, 0>(C, q, sm, z); break;
-        case 1: zbody<T, RY, 1>(C, q, sm, z); break;
-        case 2: zbody<T, RY, 2>(C, q, sm, z); break;
-        case 3: zbody<T, RY, 3>(C, q, sm, z); break;
-        case 4: zbody<T, RY, 4>(C, q, sm, z); break;
-        case 5: zbody<T, RY, 5>(C, q, sm, z); break;
-        case 6: zbody<T, RY, 6>(C, q, sm, z); break;
-        case 7: zbody<T, RY, 7>(C, q, sm, z); break;
-        default: zbody<T, RY, 8>(C, q, sm, z); break;
+    // exclusion box: a tile whose valid xy footprint lies inside it skips the
+    // planes it covers (two z segments); a tile overlapping it partly masks points
+    const int fx1 = min(C.x0 + 64, s.nx), fy1 = min(C.y0 + TY, bx.yhi);
+    const bool boxz = R.lo[2] < R.hi[2] && R.lo[2] < ze && R.hi[2] > zb;
+    const bool ovxy = C.x0 < R.hi[0] && fx1 > R.lo[0] && C.y0 < R.hi[1] && fy1 > R.lo[1];
+    const bool inxy = C.x0 >= R.lo[0] && fx1 <= R.hi[0] && C.y0 >= R.lo[1] && fy1 <= R.hi[1];
+    int seg_a[2] = {zb, 0}, seg_b[2] = {ze, 0};
+    int nseg = 1;
+    C.partial = false;
+    if (boxz && ovxy) {
+        if (inxy) {
+            seg_b[0] = min(ze, R.lo[2]);
+            seg_a[1] = max(zb, R.hi[2]);
+            seg_b[1] = ze;
+            nseg = 2;
+        } else {
+            C.partial = true;
         }
-        if (C.cpml_xy || z < C.zlo_band || z >= C.zhi_band) zband_points<T, RY>(C, z);
+    }
+
+    float4 q[9][RY];
+    for (int sg = 0; sg < nseg; ++sg) {
+        const int a = seg_a[sg], b = seg_b[sg];
+        if (a >= b) continue;
+#pragma unroll
+        for (int o = -4; o < 4; ++o)
+#pragma unroll
+            for (int r = 0; r < RY; ++r) q[o + 4][r] = Store<T>::ld4(C.u + (long)(a + o) * s.S + C.rowoff[r]);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) q[8][r] = make_float4(0.f, 0.f, 0.f, 0.f);
+
+        for (int z = a; z < b; ++z) {
+            switch ((z - a) % 9) {
+            case 0: zbody<T, RY, 0>(C, q, sm, z); break;
+            case 1: zbody<T, RY, 1>(C, q, sm, z); break;
+            case 2: zbody<T, RY, 2>(C, q, sm, z); break;
+            case 3: zbody<T, RY, 3>(C, q, sm, z); break;
+            case 4: zbody<T, RY, 4>(C, q, sm, z); break;
+            case 5: zbody<T, RY, 5>(C, q, sm, z); break;
+            case 6: zbody<T, RY, 6>(C, q, sm, z); break;
+            case 7: zbody<T, RY, 7>(C, q, sm, z); break;
+            default: zbody<T, RY, 8>(C, q, sm, z); break;
+            }
+            if (C.cpml_xy || z < C.zlo_band || z >= C.zhi_band) zband_points<T, RY>(C, z);
+        }
     }
 }
 
@@ -300,15 +334,16 @@ __global__ __launch_bounds__(256) void k_zmarch(const DevShot *__restrict__ shot
 // receivers of every shot, then advance the device step counter.  One block.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(1024) void k_record(const DevShot *__restrict__ shots, int nshots, int parity_new,
+__global__ __launch_bounds__(1024) void k_record(const DevShot *__restrict__ shots, int nshots, Roles R,
                                                  int *__restrict__ stepc) {
     const int n = *stepc;
     for (int si = 0; si < nshots; ++si) {
         const DevShot &s = shots[si];
         if (s.traces == nullptr || n >= s.trace_cap) continue;
-        const T *u = (const T *)s.u[parity_new];
+        const T *u = (const T *)s.u[R.iout];
         for (int r = threadIdx.x; r < s.nrec; r += blockDim.x) {
             const int32_t *q = s.rec + 3 * r;
+            if (in_box(R, q[0], q[1], q[2])) continue;   // recorded by the temporal-blocking kernel
             long c = (long)q[2] * s.S + (long)q[1] * s.P + q[0];
             s.traces[(long)n * s.nrec + r] = Store<T>::ld(u + c) * s.inv_scale;
         }
@@ -321,36 +356,36 @@ __global__ __launch_bounds__(1024) void k_record(const DevShot *__restrict__ sho
 // host-side launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-static void launch_psi_t(const DevShot *d_shots, int nshots, long max_count, int parity, int ext, hipStream_t st) {
+static void launch_psi_t(const DevShot *d_shots, int nshots, long max_count, int iu, int ext, hipStream_t st) {
     if (max_count <= 0) return;
     dim3 grid((unsigned)((max_count + 255) / 256), 3, nshots);
-    hipLaunchKernelGGL(k_psi<T>, grid, dim3(256), 0, st, d_shots, parity, ext);
+    hipLaunchKernelGGL(k_psi<T>, grid, dim3(256), 0, st, d_shots, iu, ext);
 }
 template <typename T>
-static void launch_naive_t(const DevShot *d_shots, int shot, int nx, int Ny, int Nz, int parity, int ext,
+static void launch_naive_t(const DevShot *d_shots, int shot, int nx, int Ny, int Nz, const Roles &R,
                            const int *stepc, hipStream_t st) {
     dim3 grid((nx + 63) / 64, (Ny + 3) / 4, Nz);
-    hipLaunchKernelGGL(k_update_naive<T>, grid, dim3(64, 4), 0, st, d_shots, shot, parity, ext, stepc);
+    hipLaunchKernelGGL(k_update_naive<T>, grid, dim3(64, 4), 0, st, d_shots, shot, R, stepc);
 }
 template <typename T>
-static void launch_zmarch_t(const DevShot *d_shots, const WorkItem *work, int nwork, int ry, int parity, int ext,
+static void launch_zmarch_t(const DevShot *d_shots, const WorkItem *work, int nwork, int ry, const Roles &R,
                             int zchunk, const int *stepc, hipStream_t st) {
     if (nwork <= 0) return;
     switch (ry) {
     case 1:
-        hipLaunchKernelGGL((k_zmarch<T, 1>), dim3(nwork), dim3(256), 0, st, d_shots, work, parity, ext, zchunk, stepc);
+        hipLaunchKernelGGL((k_zmarch<T, 1>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
         break;
     case 4:
-        hipLaunchKernelGGL((k_zmarch<T, 4>), dim3(nwork), dim3(256), 0, st, d_shots, work, parity, ext, zchunk, stepc);
+        hipLaunchKernelGGL((k_zmarch<T, 4>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
         break;
     default:
-        hipLaunchKernelGGL((k_zmarch<T, 2>), dim3(nwork), dim3(256), 0, st, d_shots, work, parity, ext, zchunk, stepc);
+        hipLaunchKernelGGL((k_zmarch<T, 2>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
         break;
     }
 }
 template <typename T>
-static void launch_record_t(const DevShot *d_shots, int nshots, int parity_new, int *stepc, hipStream_t st) {
-    hipLaunchKernelGGL(k_record<T>, dim3(1), dim3(1024), 0, st, d_shots, nshots, parity_new, stepc);
+static void launch_record_t(const DevShot *d_shots, int nshots, const Roles &R, int *stepc, hipStream_t st) {
+    hipLaunchKernelGGL(k_record<T>, dim3(1), dim3(1024), 0, st, d_shots, nshots, R, stepc);
 }
 
 #define FDTD_DISPATCH(stor, F, ...)                                                                      \
@@ -360,18 +395,18 @@ static void launch_record_t(const DevShot *d_shots, int nshots, int parity_new, 
         else F<float>(__VA_ARGS__);                                                                       \
     } while (0)
 
-void fdtd_launch_psi(int stor, const DevShot *d_shots, int nshots, long max_count, int parity, int ext,
+void fdtd_launch_psi(int stor, const DevShot *d_shots, int nshots, long max_count, int iu, int ext,
                      hipStream_t st) {
-    FDTD_DISPATCH(stor, launch_psi_t, d_shots, nshots, max_count, parity, ext, st);
+    FDTD_DISPATCH(stor, launch_psi_t, d_shots, nshots, max_count, iu, ext, st);
 }
-void fdtd_launch_naive(int stor, const DevShot *d_shots, int shot, int nx, int Ny, int Nz, int parity, int ext,
+void fdtd_launch_naive(int stor, const DevShot *d_shots, int shot, int nx, int Ny, int Nz, const Roles &R,
                        const int *stepc, hipStream_t st) {
-    FDTD_DISPATCH(stor, launch_naive_t, d_shots, shot, nx, Ny, Nz, parity, ext, stepc, st);
+    FDTD_DISPATCH(stor, launch_naive_t, d_shots, shot, nx, Ny, Nz, R, stepc, st);
 }
-void fdtd_launch_zmarch(int stor, const DevShot *d_shots, const WorkItem *work, int nwork, int ry, int parity,
-                        int ext, int zchunk, const int *stepc, hipStream_t st) {
-    FDTD_DISPATCH(stor, launch_zmarch_t, d_shots, work, nwork, ry, parity, ext, zchunk, stepc, st);
+void fdtd_launch_zmarch(int stor, const DevShot *d_shots, const WorkItem *work, int nwork, int ry, const Roles &R,
+                        int zchunk, const int *stepc, hipStream_t st) {
+    FDTD_DISPATCH(stor, launch_zmarch_t, d_shots, work, nwork, ry, R, zchunk, stepc, st);
 }
-void fdtd_launch_record(int stor, const DevShot *d_shots, int nshots, int parity_new, int *stepc, hipStream_t st) {
-    FDTD_DISPATCH(stor, launch_record_t, d_shots, nshots, parity_new, stepc, st);
+void fdtd_launch_record(int stor, const DevShot *d_shots, int nshots, const Roles &R, int *stepc, hipStream_t st) {
+    FDTD_DISPATCH(stor, launch_record_t, d_shots, nshots, R, stepc, st);
 }

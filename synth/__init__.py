@@ -129,6 +129,23 @@ def blob_model(n_xyz, blobs: Blobs, origin=(0, 0, 0), sub_xyz=None) -> np.ndarra
     return v
 
 
+def blob_model_torch(n_xyz, blobs: Blobs, device="cuda"):
+    """blob_model evaluated with torch on a device (float32), for large grids."""
+    import torch
+
+    nx, ny, nz = [int(x) for x in n_xyz]
+    xs = torch.arange(nx, dtype=torch.float64, device=device)
+    ys = torch.arange(ny, dtype=torch.float64, device=device)
+    zs = torch.arange(nz, dtype=torch.float64, device=device)
+    v = torch.full((nz, ny, nx), float(blobs.background), dtype=torch.float32, device=device)
+    for c, r, a in zip(blobs.centers, blobs.radii, blobs.amps):
+        gx = torch.exp(-0.5 * ((xs - float(c[0])) / float(r)) ** 2).float()
+        gy = torch.exp(-0.5 * ((ys - float(c[1])) / float(r)) ** 2).float()
+        gz = torch.exp(-0.5 * ((zs - float(c[2])) / float(r)) ** 2).float()
+        v += float(a) * (gz[:, None, None] * gy[None, :, None] * gx[None, None, :])
+    return v.clamp_(float(blobs.vmin), float(blobs.vmax))
+
+
 def smooth_field(shape_zyx, rng: np.random.Generator, sigma: float = 8.0) -> np.ndarray:
     """Seeded smooth random field with max |G| = 1 (separable Gaussian blur of noise)."""
     from scipy.ndimage import gaussian_filter
