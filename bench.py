@@ -44,18 +44,18 @@ def step_bytes(n, cpml, field_bytes=4):
     return (3 * field_bytes + 4) * N + 16 * slab_points(n, cpml)
 
 
-def time_gpu(w, K, W, variant, storage=0, graph=True):
+def time_gpu(w, K, W, variant, storage=0, graph=True, tblock_k=1):
     import numpy as np
     import torch
 
     from paper_2606_06910_amd import Propagator, Shot
 
-    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, variant=variant, storage=storage)])
+    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, variant=variant, storage=storage, tblock_k=tblock_k)])
     p.set_velocity(0, torch.from_numpy(w.v.astype(np.float32)).cuda())
     p.inject_source(0, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)).cuda())
     p.set_receivers(0, w.rec)
     p.record(0, K + W + 2)
-    W += W % 2
+    W += (-W) % 4
     if graph:
         p.step(K, graph=True)            # capture once (phase 0), untimed
         torch.cuda.synchronize()
@@ -280,9 +280,11 @@ def main():
     }
     if args.compare:
         var = {}
-        for name, vv in (("naive", 1), ("zmarch", 2)):
-            m2, u2, _, _ = time_gpu(w, min(K, 200), W, vv, graph=not args.eager)
-            var[name] = round(N * min(K, 200) / (m2 / 1e3) / 1e6, 1)
+        Kc = min(K, 200)
+        for name, vv, kk in (("naive", 1, 1), ("zmarch", 2, 1), ("tblock2", 3, 2), ("tblock4", 3, 4)):
+            print("bench: compare %s" % name, file=sys.stderr, flush=True)
+            m2, u2, _, _ = time_gpu(w, Kc, W, vv, graph=not args.eager, tblock_k=kk)
+            var[name] = round(N * Kc / (m2 / 1e3) / 1e6, 1)
         out["variants_mpts"] = var
     if not args.no_extra:
         print("bench: 16-bit storage leg (768^3)", file=sys.stderr, flush=True)

@@ -936,6 +936,42 @@ int fdtd_set_velocity(fdtd_ctx *ctx, int32_t shot, const float *v_dev) {
     }
     HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_prof), prof.data(), prof.size() * 4, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (s.gy || s.gz) {
+        // m is static: give the ghost rows/planes the opposite face's values once
+        // (two phases, y then z spanning the y ghosts, so corners are filled too)
+        float *mo = m_origin(ctx, s);
+        std::vector<CopyJob> jy, jz;
+        const int g = s.g;
+        if (s.gy) {
+            jy.push_back(CopyJob{mo, mo + (long)s.ny * s.P, 4, s.nx, g, s.nz, (long)s.P, (long)s.S, (long)s.P, (long)s.S});
+            jy.push_back(CopyJob{mo + (long)(s.ny - g) * s.P, mo - (long)g * s.P, 4, s.nx, g, s.nz, (long)s.P, (long)s.S,
+                                 (long)s.P, (long)s.S});
+        }
+        if (s.gz) {
+            const int dy = s.gy ? g : 0, Ny = s.ny + 2 * dy;
+            float *b = mo - (long)dy * s.P;
+            jz.push_back(CopyJob{b, b + (long)s.nz * s.S, 4, s.nx, Ny, g, (long)s.P, (long)s.S, (long)s.P, (long)s.S});
+            jz.push_back(CopyJob{b + (long)(s.nz - g) * s.S, b - (long)g * s.S, 4, s.nx, Ny, g, (long)s.P, (long)s.S,
+                                 (long)s.P, (long)s.S});
+        }
+        for (auto *jobs : {&jy, &jz}) {
+            if (jobs->empty()) continue;
+            long mx = 0;
+            for (auto &j : *jobs) mx = std::max(mx, (long)j.ex * j.ey * j.ez);
+            HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_jobs[0][0]), jobs->data(), sizeof(CopyJob) * jobs->size(),
+                                       hipMemcpyHostToDevice, ctx->stream));
+            fdtd_launch_copy_jobs(wsp(ctx, s.o_jobs[0][0]), (int)jobs->size(), mx, ctx->stream);
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        }
+        // restore the exchange table that slot held
+        std::vector<CopyJob> jobs[2][4];
+        long maxe[2][4];
+        build_jobs(ctx, shot, jobs, maxe);
+        if (!jobs[0][0].empty())
+            HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_jobs[0][0]), jobs[0][0].data(), sizeof(CopyJob) * jobs[0][0].size(),
+                                       hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
     s.vel_set = true;
     if (s.c.storage == FDTD_F32) s.scale = 1.0;
     else if (s.c.field_scale > 0) s.scale = s.c.field_scale;
