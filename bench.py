@@ -31,11 +31,35 @@ def slab_points(n, cpml):
     return tot
 
 
-def update_kernel_bytes(n, cpml, field_bytes=4):
-    """Algorithmic bytes of one update launch: read u^n, u^{n-1}, m and write
-    u^{n+1} per point; per layer point and axis read psi, read+write zeta."""
+def band_split(n, cpml):
+    """(points outside every band, band points); the band of an axis is its
+    layer plus the 4-cell margin the psi derivative reaches."""
+    inner = 1
+    for d in range(3):
+        lo, hi = cpml[2 * d], cpml[2 * d + 1]
+        a = min(lo + 4, n[d]) if lo > 0 else 0
+        b = max(n[d] - hi - 4, a) if hi > 0 else n[d]
+        inner *= b - a
     N = n[0] * n[1] * n[2]
-    return (3 * field_bytes + 4) * N + 12 * slab_points(n, cpml)
+    return inner, N - inner
+
+
+def interior_kernel_bytes(n, cpml, field_bytes=4):
+    """Algorithmic bytes of one z-march launch (points outside every band):
+    read u^n, u^{n-1}, m and write u^{n+1} per point."""
+    return (3 * field_bytes + 4) * band_split(n, cpml)[0]
+
+
+def band_kernel_bytes(n, cpml, field_bytes=4):
+    """Algorithmic bytes of one band launch: the four arrays per band point,
+    plus per layer point and axis a read of psi and a read + write of zeta."""
+    return (3 * field_bytes + 4) * band_split(n, cpml)[1] + 12 * slab_points(n, cpml)
+
+
+def psi_kernel_bytes(n, cpml, field_bytes=4):
+    """Algorithmic bytes of one psi pre-pass: per layer point and axis read u,
+    read and write psi."""
+    return (field_bytes + 8) * slab_points(n, cpml)
 
 
 def step_bytes(n, cpml, field_bytes=4):
@@ -74,12 +98,10 @@ def time_gpu(w, K, W, variant, storage=0, graph=True, tblock_k=1):
     Kt = min(K, 200)
     p.set_timing(True)
     p.step(Kt)
-    upd = p.timing(0)
-    psi = p.timing(1)
-    rec = p.timing(2)
+    tm = {name: p.timing(c) for c, name in enumerate(("update", "psi", "record", "exchange", "band", "tblock"))}
     p.set_timing(False)
     p.close()
-    return ms, upd, psi, rec
+    return ms, tm
 
 
 def precision_leg(K=200):
@@ -251,11 +273,17 @@ def main():
     n = (args.n, args.n, args.n)
     w = synth.layered(n_xyz=n, nt=K + W + 2)
     print("bench: layered %s, %d+%d steps" % (str(n), W, K), file=sys.stderr, flush=True)
-    ms, upd, psi, rec = time_gpu(w, K, W, args.variant, graph=not args.eager)
+    ms, tm = time_gpu(w, K, W, args.variant, graph=not args.eager)
     N = w.npts
     value = N * K / (ms / 1e3) / 1e6
-    upd_bytes = update_kernel_bytes(w.n, w.cpml)
+    upd = tm["update"]
+    upd_bytes = interior_kernel_bytes(w.n, w.cpml)
     achieved = upd_bytes / (upd[0] / 1e3) / 1e9
+    kgbs = {}
+    for name, nbytes in (("update", upd_bytes), ("band", band_kernel_bytes(w.n, w.cpml)),
+                         ("psi", psi_kernel_bytes(w.n, w.cpml))):
+        if tm[name][1] > 0:
+            kgbs[name] = round(nbytes / (tm[name][0] / 1e3) / 1e9, 1)
     out = {
         "metric": "Mpts/s (output points/sec) + % HBM peak, FP32 vs FP16-storage at stated error",
         "value": round(value, 1),
@@ -273,17 +301,18 @@ def main():
                    "grid": list(n), "cpml": 20, "variant": args.variant, "graph": not args.eager},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                     "kernel": "k_zmarch<float> (wavefield update)",
+                     "kernel": "k_zmarch<float, RY> (update of the points outside the layer bands)",
                      "kernel_ms": round(upd[0], 5), "algorithmic_bytes_per_launch": upd_bytes},
         "step_algorithmic_gbs": round(step_bytes(w.n, w.cpml) / (ms / K / 1e3) / 1e9, 1),
-        "kernel_ms": {"update": round(upd[0], 5), "psi": round(psi[0], 5), "record": round(rec[0], 5)},
+        "kernel_ms": {k: round(v[0], 5) for k, v in tm.items() if v[1] > 0},
+        "kernel_algorithmic_gbs": kgbs,
     }
     if args.compare:
         var = {}
         Kc = min(K, 200)
         for name, vv, kk in (("naive", 1, 1), ("zmarch", 2, 1), ("tblock2", 3, 2), ("tblock4", 3, 4)):
             print("bench: compare %s" % name, file=sys.stderr, flush=True)
-            m2, u2, _, _ = time_gpu(w, Kc, W, vv, graph=not args.eager, tblock_k=kk)
+            m2, _ = time_gpu(w, Kc, W, vv, graph=not args.eager, tblock_k=kk)
             var[name] = round(N * Kc / (m2 / 1e3) / 1e6, 1)
         out["variants_mpts"] = var
     if not args.no_extra:

@@ -202,8 +202,11 @@ int fdtd_get_scale(const fdtd_ctx *ctx, int32_t shot, double *scale);
  * classes below is bracketed by HIP events on the context's stream.
  * fdtd_get_timing synchronises, returns the mean duration (ms) and count of
  * one class since timing was enabled, and keeps accumulating.
- * Classes: 0 = wavefield update, 1 = psi pre-pass, 2 = receiver gather,
- * 3 = ghost pack/unpack.  Enabling again clears the counters. */
+ * Classes: 0 = single-step update of the points outside the layer bands
+ * (z-march kernel; the naive kernel updates every point), 1 = psi pre-pass,
+ * 2 = receiver gather, 3 = ghost pack/unpack, 4 = update of the layer-band
+ * points, 5 = temporal-blocking kernel (K steps of the interior box per
+ * launch).  Enabling again clears the counters. */
 int fdtd_set_timing(fdtd_ctx *ctx, int32_t enable);
 int fdtd_get_timing(fdtd_ctx *ctx, int32_t kernel_class, double *mean_ms, int64_t *count);
 

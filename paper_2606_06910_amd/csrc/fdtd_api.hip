@@ -162,18 +162,44 @@ static int validate_shot(fdtd_ctx *ctx, const fdtd_shot_config &c, int i) {
 
 // XCD-aware order: hardware hands workgroup b to XCD (b mod 8); give each XCD a
 // contiguous spatial range so that tiles sharing halos share an L2.
-static std::vector<WorkItem> xcd_order(const std::vector<WorkItem> &sp) {
+template <typename W> static W idle_item(const std::vector<W> &sp);
+template <> WorkItem idle_item(const std::vector<WorkItem> &sp) {
+    return WorkItem{sp.empty() ? 0 : sp[0].shot, 0, 1 << 20, 0};   // exits immediately
+}
+template <> BandItem idle_item(const std::vector<BandItem> &sp) {
+    return BandItem{sp.empty() ? 0 : sp[0].shot, 0, 1 << 20, 0, 0, 0, 0, 0};
+}
+template <typename W> static std::vector<W> xcd_order(const std::vector<W> &sp) {
     const int X = 8;
-    size_t W = (sp.size() + X - 1) / X * X;
-    std::vector<WorkItem> out(W);
-    size_t per = W / X;
-    for (size_t w = 0; w < W; ++w) {
+    size_t N = (sp.size() + X - 1) / X * X;
+    std::vector<W> out(N);
+    size_t per = N / X;
+    for (size_t w = 0; w < N; ++w) {
         size_t src = (w % X) * per + w / X;
-        if (src < sp.size()) out[w] = sp[src];
-        else out[w] = WorkItem{sp.empty() ? 0 : sp[0].shot, 0, 1 << 20, 0};   // exits immediately
+        out[w] = src < sp.size() ? sp[src] : idle_item(sp);
     }
     return out;
 }
+
+// band-kernel tiles of a shot, for the largest compute box it uses (smaller
+// boxes reuse the list; tiles past a box end exit at once)
+static std::vector<BandItem> band_tiles(const ShotH &s, int shot) {
+    const int ext = (s.gy || s.gz) ? s.g - 4 : 0;
+    const int n3[3] = {s.nx, s.ny, s.nz}, gh[3] = {0, s.gy, s.gz};
+    std::vector<BandItem> v;
+    for (int b = 0; b < 6; ++b) {
+        int lo[3], hi[3];
+        band_box(n3, s.Llo, s.Lhi, gh, ext, b, lo, hi);
+        const int wx = hi[0] - lo[0], wy = hi[1] - lo[1], wz = hi[2] - lo[2];
+        if (wx <= 0 || wy <= 0 || wz <= 0) continue;
+        const int nzc = (wz + kBandZ - 1) / kBandZ, nty = (wy + kBandTY - 1) / kBandTY, ntx = (wx + kBandTX - 1) / kBandTX;
+        for (int zc = 0; zc < nzc; ++zc)
+            for (int ty = 0; ty < nty; ++ty)
+                for (int tx = 0; tx < ntx; ++tx) v.push_back(BandItem{shot, b, tx, ty, zc, 0, 0, 0});
+    }
+    return v;
+}
+static size_t band_capacity(const ShotH &s) { return band_tiles(s, 0).size() + 8; }
 
 static std::vector<WorkItem> shot_tiles(const ShotH &s, int shot, int ry, int zchunk) {
     int ext = s.g - 4;
@@ -460,7 +486,7 @@ static void toc(fdtd_ctx *ctx, int cls, hipEvent_t start) {
 // fold recorded pairs into the sums (synchronises) and recycle the events
 static int drain_timing(fdtd_ctx *ctx) {
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < kTimingClasses; ++c) {
         for (auto &pr : ctx->ev_pairs[c]) {
             float ms = 0;
             HIPCHK(ctx, hipEventElapsedTime(&ms, pr.first, pr.second));
@@ -513,24 +539,38 @@ static void enqueue_update(fdtd_ctx *ctx, int shot, const Roles &R) {
     if (shot < 0 && !ctx->groups.empty()) {
         // every z-march shot, grouped by plan; naive shots below
         const WorkItem *wa = (const WorkItem *)wsp(ctx, ctx->o_work_all);
+        hipEvent_t t0 = tic(ctx);
         for (const auto &g : ctx->groups)
             fdtd_launch_zmarch(stor, dd, wa + g.off, g.nwork, g.ry, R, g.zchunk, stepc, ctx->stream);
+        toc(ctx, 0, t0);
+        t0 = tic(ctx);
+        fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, ctx->o_band_all), ctx->nband_all, R, kBandZ, stepc,
+                         ctx->stream);
+        toc(ctx, 4, t0);
         for (int i = lo; i < hi; ++i) {
             const ShotH &s = ctx->shots[i];
             if (s.variant != FDTD_VARIANT_NAIVE) continue;
             int Ny = s.ny + (s.gy ? 2 * ext : 0), Nz = s.nz + (s.gz ? 2 * ext : 0);
+            hipEvent_t t1 = tic(ctx);
             fdtd_launch_naive(stor, dd, i, s.nx, Ny, Nz, R, stepc, ctx->stream);
+            toc(ctx, 0, t1);
         }
         return;
     }
     for (int i = lo; i < hi; ++i) {
         const ShotH &s = ctx->shots[i];
+        hipEvent_t t0 = tic(ctx);
         if (s.variant == FDTD_VARIANT_NAIVE) {
             int Ny = s.ny + (s.gy ? 2 * ext : 0), Nz = s.nz + (s.gz ? 2 * ext : 0);
             fdtd_launch_naive(stor, dd, i, s.nx, Ny, Nz, R, stepc, ctx->stream);
+            toc(ctx, 0, t0);
         } else {
             fdtd_launch_zmarch(stor, dd, (const WorkItem *)wsp(ctx, s.o_work), s.nwork, s.ry, R, s.zchunk, stepc,
                                ctx->stream);
+            toc(ctx, 0, t0);
+            t0 = tic(ctx);
+            fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, s.o_band), s.nband, R, kBandZ, stepc, ctx->stream);
+            toc(ctx, 4, t0);
         }
     }
 }
@@ -558,9 +598,7 @@ static void enqueue_step(fdtd_ctx *ctx, int shot) {
     hipEvent_t t0 = tic(ctx);
     fdtd_launch_psi(ctx->storage, dd + lo, hi - lo, maxc, R.iu, ext, ctx->stream);
     toc(ctx, 1, t0);
-    t0 = tic(ctx);
     enqueue_update(ctx, shot, R);
-    toc(ctx, 0, t0);
     t0 = tic(ctx);
     fdtd_launch_record(ctx->storage, dd + lo, hi - lo, R, (int *)wsp(ctx, ctx->o_stepc), ctx->stream);
     toc(ctx, 2, t0);
@@ -603,7 +641,7 @@ static void enqueue_tblock(fdtd_ctx *ctx) {
     a.rec_ix = (const int *)wsp(ctx, s.o_recix);
     hipEvent_t t0 = tic(ctx);
     fdtd_launch_tblock(dd, (const WorkItem *)wsp(ctx, s.o_tbwork), s.ntbwork, K, &a, s.tb_zchunk, stepc, ctx->stream);
-    toc(ctx, 0, t0);
+    toc(ctx, 5, t0);
     long maxc = 0;
     for (int d = 0; d < 3; ++d) maxc = std::max(maxc, psi_count(s, d, 0));
     for (int j = 1; j <= K; ++j) {
@@ -623,6 +661,10 @@ static void enqueue_tblock(fdtd_ctx *ctx) {
         fdtd_launch_zmarch(ctx->storage, dd, (const WorkItem *)wsp(ctx, s.o_work), s.nwork, s.ry, R, s.zchunk, stepc,
                            ctx->stream);
         toc(ctx, 0, t0);
+        t0 = tic(ctx);
+        fdtd_launch_band(ctx->storage, dd, (const BandItem *)wsp(ctx, s.o_band), s.nband, R, kBandZ, stepc,
+                         ctx->stream);
+        toc(ctx, 4, t0);
         t0 = tic(ctx);
         fdtd_launch_record(ctx->storage, dd, 1, R, stepc, ctx->stream);
         toc(ctx, 2, t0);
@@ -764,6 +806,9 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
     size_t cap_all = 0;
     for (auto &s : ctx->shots) cap_all += work_capacity(s) + 8;
     ctx->o_work_all = take(sizeof(WorkItem) * cap_all);
+    size_t band_all = 0;
+    for (auto &s : ctx->shots) band_all += band_capacity(s);
+    ctx->o_band_all = take(sizeof(BandItem) * band_all);
     for (auto &s : ctx->shots) {
         s.o_u[0] = take(s.elems * s.esz);
         s.o_u[1] = take(s.elems * s.esz);
@@ -782,6 +827,7 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
         }
         s.o_prof = take((size_t)3 * 4 * s.nmax * 4);
         s.o_work = take(sizeof(WorkItem) * work_capacity(s));
+        s.o_band = take(sizeof(BandItem) * band_capacity(s));
         s.xbuf_bytes = xbuf_bytes(s);
         s.o_xbuf = take(s.xbuf_bytes);
         for (int p = 0; p < 2; ++p)
@@ -801,8 +847,19 @@ int fdtd_workspace_size(const fdtd_ctx *ctx, size_t *bytes) {
 
 static int write_work_lists(fdtd_ctx *ctx) {
     std::map<std::pair<int, int>, std::vector<WorkItem>> byplan;
+    std::vector<BandItem> band_all;
     for (size_t i = 0; i < ctx->shots.size(); ++i) {
         ShotH &s = ctx->shots[i];
+        {
+            std::vector<BandItem> bt = band_tiles(s, (int)i);
+            std::vector<BandItem> bw = xcd_order(bt);
+            if (bw.size() > band_capacity(s)) FAIL(ctx, FDTD_EINVAL, "band list overflow");
+            s.nband = (int)bw.size();
+            if (!bw.empty())
+                HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_band), bw.data(), sizeof(BandItem) * bw.size(),
+                                           hipMemcpyHostToDevice, ctx->stream));
+            if (s.variant != FDTD_VARIANT_NAIVE) band_all.insert(band_all.end(), bt.begin(), bt.end());
+        }
         std::vector<WorkItem> sp = shot_tiles(s, (int)i, s.ry, s.zchunk);
         std::vector<WorkItem> w = xcd_order(sp);
         if (w.size() > work_capacity(s)) FAIL(ctx, FDTD_EINVAL, "work list overflow");
@@ -836,6 +893,14 @@ static int write_work_lists(fdtd_ctx *ctx) {
         all.insert(all.end(), wa.begin(), wa.end());
     }
     ctx->nwork_all = (int)all.size();
+    {
+        std::vector<BandItem> bw = xcd_order(band_all);
+        ctx->nband_all = (int)bw.size();
+        if (!bw.empty())
+            HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, ctx->o_band_all), bw.data(), sizeof(BandItem) * bw.size(),
+                                       hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
     if (!all.empty()) {
         HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, ctx->o_work_all), all.data(), sizeof(WorkItem) * all.size(),
                                    hipMemcpyHostToDevice, ctx->stream));
@@ -1079,7 +1144,7 @@ int fdtd_set_timing(fdtd_ctx *ctx, int32_t enable) {
         if (rc) return rc;
     }
     ctx->timing = enable != 0;
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < kTimingClasses; ++c) {
         ctx->t_sum[c] = 0;
         ctx->t_cnt[c] = 0;
         ctx->ev_pairs[c].clear();
@@ -1089,7 +1154,7 @@ int fdtd_set_timing(fdtd_ctx *ctx, int32_t enable) {
 }
 
 int fdtd_get_timing(fdtd_ctx *ctx, int32_t cls, double *mean_ms, int64_t *count) {
-    if (!ctx || cls < 0 || cls > 3 || !mean_ms || !count) return FDTD_EINVAL;
+    if (!ctx || cls < 0 || cls >= kTimingClasses || !mean_ms || !count) return FDTD_EINVAL;
     int rc = drain_timing(ctx);
     if (rc) return rc;
     *count = ctx->t_cnt[cls];

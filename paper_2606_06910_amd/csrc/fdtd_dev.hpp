@@ -120,6 +120,56 @@ struct WorkItem {
     int shot, tx, ty, zc;
 };
 
+// Work item of the band kernel: shot, band box, x tile, y tile, z chunk.
+struct BandItem {
+    int shot, box, tx, ty, zc, pad0, pad1, pad2;
+};
+
+// The band region of a shot (layer slabs plus the 4-cell margin their psi
+// derivative reaches) within its compute box (extended by `ext` on ghost
+// axes) as six disjoint boxes [lo, hi), k = 0..5:
+//   0, 1  z below / above the non-band z range, all x and y
+//   2, 3  y below / above the non-band y range, inside the non-band z range
+//   4, 5  x below / above the non-band x range, inside the non-band y, z ranges
+// and k = 6, the non-band box itself.  Along each axis the non-band range is
+// [a, b): a = min(lo + 4, n) with a low layer (else the box start), b =
+// max(n - hi - 4, a) with a high layer (else the box end), so that c < a or
+// c >= b is exactly the band test.
+__host__ __device__ inline void band_box(const int n[3], const int Llo[3], const int Lhi[3], const int ghost[3],
+                                         int ext, int k, int lo[3], int hi[3]) {
+    int a[3], b[3];
+    for (int d = 0; d < 3; ++d) {
+        const int e0 = ghost[d] ? -ext : 0, e1 = n[d] + (ghost[d] ? ext : 0);
+        a[d] = Llo[d] > 0 ? (Llo[d] + FDTD_R < n[d] ? Llo[d] + FDTD_R : n[d]) : e0;
+        b[d] = Lhi[d] > 0 ? (n[d] - Lhi[d] - FDTD_R > a[d] ? n[d] - Lhi[d] - FDTD_R : a[d]) : e1;
+        lo[d] = e0;
+        hi[d] = e1;
+    }
+    if (k == 6) {
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = a[d];
+            hi[d] = b[d];
+        }
+    } else if (k == 0) {
+        hi[2] = a[2];
+    } else if (k == 1) {
+        lo[2] = b[2];
+    } else {
+        lo[2] = a[2];
+        hi[2] = b[2];
+        if (k == 2) {
+            hi[1] = a[1];
+        } else if (k == 3) {
+            lo[1] = b[1];
+        } else {
+            lo[1] = a[1];
+            hi[1] = b[1];
+            if (k == 4) hi[0] = a[0];
+            else lo[0] = b[0];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // layer geometry
 // ---------------------------------------------------------------------------

@@ -12,6 +12,8 @@
 constexpr int kOFF = 128;   // leading pad of every field (elements)
 constexpr int kTYMAX = 64;  // tallest y tile (rows) a kernel may overhang
 constexpr int kMaxRec = 65536;  // receivers per shot with temporal blocking
+constexpr int kTimingClasses = 6;   // update, psi, record, exchange, band update, temporal block
+constexpr int kBandTX = 32, kBandTY = 16, kBandZ = 64;   // band-kernel tile and z chunk
 
 struct ShotH {
     fdtd_shot_config c;
@@ -32,6 +34,8 @@ struct ShotH {
     int njobs[2][4] = {};
     long jobmax[2][4] = {};
     int nwork = 0;
+    size_t o_band = 0;         // band-kernel tile list (for the largest compute box)
+    int nband = 0;
     // model / source / receivers
     bool vel_set = false;
     double vmax = 0, vref = 0, scale = 1;
@@ -65,8 +69,8 @@ struct fdtd_ctx {
     hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
     char *ws = nullptr;
     size_t ws_bytes = 0, need = 0;
-    size_t o_stepc = 0, o_scratch = 0, o_desc = 0, o_work_all = 0;
-    int nwork_all = 0;
+    size_t o_stepc = 0, o_scratch = 0, o_desc = 0, o_work_all = 0, o_band_all = 0;
+    int nwork_all = 0, nband_all = 0;
     // multi-shot z-march launches: one per distinct (ry, zchunk) plan
     struct Group {
         int ry, zchunk;
@@ -89,9 +93,9 @@ struct fdtd_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[4];
-    double t_sum[4] = {0, 0, 0, 0};
-    long t_cnt[4] = {0, 0, 0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[kTimingClasses];
+    double t_sum[kTimingClasses] = {};
+    long t_cnt[kTimingClasses] = {};
 };
 
 // helpers exported by fdtd_api.hip for the other translation units

@@ -212,19 +212,6 @@ __device__ __forceinline__ void zbody(ZCtx<T, RY> &C, float4 (&q)[9][RY], float4
     }
 }
 
-// Layer-band points of this thread in plane z: full update from memory.
-template <typename T, int RY>
-__device__ __forceinline__ void zband_points(ZCtx<T, RY> &C, int z) {
-    const DevShot &s = *C.s;
-#pragma unroll 1
-    for (int i = 0; i < 4 * RY; ++i) {
-        const int x = C.x + (i & 3);
-        const int y = C.y0 + C.ty * RY + (i >> 2);
-        if (x < s.nx && y < C.yhi && any_band(s, x, y, z) && !in_box(*C.R, x, y, z))
-            point_update_global<T>(s, C.u, C.um, C.w, x, y, z, C.src);
-    }
-}
-
 template <typename T, int RY>
 __global__ __launch_bounds__(256) void k_zmarch(const DevShot *__restrict__ shots, const WorkItem *__restrict__ work,
                                                Roles R, int zchunk, const int *__restrict__ stepc) {
@@ -302,6 +289,18 @@ __global__ __launch_bounds__(256) void k_zmarch(const DevShot *__restrict__ shot
         }
     }
 
+    // band points are the band kernel's: planes of the z band are skipped, and
+    // a tile whose footprint lies inside the x or y band has nothing to do
+    {
+        int nlo[3], nhi[3];
+        const int n3[3] = {s.nx, s.ny, s.nz};
+        band_box(n3, s.Llo, s.Lhi, s.ghost, ext, 6, nlo, nhi);
+        if (C.x0 >= nhi[0] || fx1 <= nlo[0] || C.y0 >= nhi[1] || fy1 <= nlo[1]) return;
+        for (int sg = 0; sg < nseg; ++sg) {
+            seg_a[sg] = max(seg_a[sg], nlo[2]);
+            seg_b[sg] = min(seg_b[sg], nhi[2]);
+        }
+    }
     float4 q[9][RY];
     for (int sg = 0; sg < nseg; ++sg) {
         const int a = seg_a[sg], b = seg_b[sg];
@@ -325,7 +324,6 @@ __global__ __launch_bounds__(256) void k_zmarch(const DevShot *__restrict__ shot
             case 7: zbody<T, RY, 7>(C, q, sm, z); break;
             default: zbody<T, RY, 8>(C, q, sm, z); break;
             }
-            if (C.cpml_xy || z < C.zlo_band || z >= C.zhi_band) zband_points<T, RY>(C, z);
         }
     }
 }
