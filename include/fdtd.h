@@ -88,7 +88,9 @@ typedef struct {
 
 /* Create a context for nshots shots on hip_stream (a hipStream_t, may be NULL
  * for the null stream).  Validates every shot (EINVAL for bad shapes, layers
- * wider than half an axis, bad faces; EUNSTABLE is checked at
+ * wider than half an axis, bad faces, a field plane above 64 MiB (e.g.
+ * more than about 4000 x 4000 FP32 points) or a layer array above 1 GiB,
+ * which the kernels' 32-bit offsets cannot address; EUNSTABLE is checked at
  * fdtd_set_velocity, once the velocity is known).  *out receives the context
  * (host memory owned by the library; free with fdtd_destroy). */
 int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream, fdtd_ctx **out);
@@ -185,8 +187,8 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
 int fdtd_autotune(fdtd_ctx *ctx, const char *cache_path);
 
 /* Fix the kernel plan of one shot by hand (what fdtd_autotune chooses):
- * variant (naive / z-march / temporal blocking), z-march tile rows per thread
- * (1, 2 or 4: tiles of 64 x 16*rows points), z-chunk length (16..4096 planes
+ * variant (naive / z-march / temporal blocking), z-march tile size
+ * (1, 2 or 4: tiles of 64 x 8*tile_ry points), z-chunk length (16..4096 planes
  * per workgroup) and temporal depth (2 or 4, temporal blocking only).
  * Results do not depend on the plan (same bits). */
 int fdtd_set_plan(fdtd_ctx *ctx, int32_t shot, int32_t variant, int32_t tile_ry, int32_t zchunk, int32_t tblock_k);

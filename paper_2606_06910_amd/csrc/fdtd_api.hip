@@ -67,9 +67,12 @@ static void plan_shot(ShotH &s) {
     s.LX = s.Llo[0] + s.Lhi[0];
     s.LY = s.Llo[1] + s.Lhi[1];
     s.LZ = s.Llo[2] + s.Lhi[2];
-    s.psi_elems[0] = (size_t)(s.nz + 2 * s.fz) * s.PY * s.LX;
-    s.psi_elems[1] = (size_t)(s.nz + 2 * s.fz) * s.LY * s.nx;
-    s.psi_elems[2] = (size_t)s.LZ * s.PY * s.nx;
+    s.SX = s.LX ? s.LX + 1 : 0;
+    s.SY = s.LY ? s.LY + 1 : 0;
+    s.SZ = s.LZ ? s.LZ + 1 : 0;
+    s.psi_elems[0] = (size_t)(s.nz + 2 * s.fz) * s.PY * s.SX;
+    s.psi_elems[1] = (size_t)(s.nz + 2 * s.fz) * s.SY * s.nx;
+    s.psi_elems[2] = (size_t)s.SZ * s.PY * s.nx;
     s.nmax = std::max(s.nx, std::max(s.ny, s.nz));
     s.variant = c.variant == FDTD_VARIANT_AUTO ? FDTD_VARIANT_ZMARCH : c.variant;
     s.ry = 2;
@@ -183,11 +186,11 @@ template <typename W> static std::vector<W> xcd_order(const std::vector<W> &sp) 
 
 // band-kernel tiles of a shot, for the largest compute box it uses (smaller
 // boxes reuse the list; tiles past a box end exit at once)
-static std::vector<BandItem> band_tiles(const ShotH &s, int shot) {
+static std::vector<BandItem> band_tiles(const ShotH &s, int shot, int kind) {
     const int ext = (s.gy || s.gz) ? s.g - 4 : 0;
     const int n3[3] = {s.nx, s.ny, s.nz}, gh[3] = {0, s.gy, s.gz};
     std::vector<BandItem> v;
-    for (int b = 0; b < 6; ++b) {
+    for (int b = 2 * kind; b < 2 * kind + 2; ++b) {
         int lo[3], hi[3];
         band_box(n3, s.Llo, s.Lhi, gh, ext, b, lo, hi);
         const int wx = hi[0] - lo[0], wy = hi[1] - lo[1], wz = hi[2] - lo[2];
@@ -199,13 +202,13 @@ static std::vector<BandItem> band_tiles(const ShotH &s, int shot) {
     }
     return v;
 }
-static size_t band_capacity(const ShotH &s) { return band_tiles(s, 0).size() + 8; }
+static size_t band_capacity(const ShotH &s, int kind) { return band_tiles(s, 0, kind).size() + 8; }
 
 static std::vector<WorkItem> shot_tiles(const ShotH &s, int shot, int ry, int zchunk) {
     int ext = s.g - 4;
     int Ny = s.ny + (s.gy ? 2 * ext : 0);
     int Nz = s.nz + (s.gz ? 2 * ext : 0);
-    int TY = 16 * ry;
+    int TY = 8 * ry;   // z-march tile rows (64 x 8 ry points)
     int ntx = (s.nx + 63) / 64, nty = (Ny + TY - 1) / TY, ntz = (Nz + zchunk - 1) / zchunk;
     std::vector<WorkItem> v;
     v.reserve((size_t)ntx * nty * ntz);
@@ -219,7 +222,7 @@ static size_t work_capacity(const ShotH &s) {
     int ext = s.g - 4;
     int Ny = s.ny + (s.gy ? 2 * ext : 0);
     int Nz = s.nz + (s.gz ? 2 * ext : 0);
-    return (size_t)((s.nx + 63) / 64) * ((Ny + 15) / 16) * ((Nz + 15) / 16) + 8;
+    return (size_t)((s.nx + 63) / 64) * ((Ny + 7) / 8) * ((Nz + 15) / 16) + 8;
 }
 
 static long psi_count(const ShotH &s, int d, int ext) {
@@ -335,6 +338,9 @@ static void fill_desc(fdtd_ctx *ctx, int i) {
     D.LX = s.LX;
     D.LY = s.LY;
     D.LZ = s.LZ;
+    D.SX = s.SX;
+    D.SY = s.SY;
+    D.SZ = s.SZ;
     D.nmax = s.nmax;
     D.ghost[0] = 0;
     D.ghost[1] = s.gy;
@@ -389,8 +395,8 @@ static void build_jobs(fdtd_ctx *ctx, int i, std::vector<CopyJob> (&jobs)[2][4],
             if (s.LX > 0) {
                 for (int w = 0; w < 2; ++w) {
                     char *base = wsp(ctx, w == 0 ? s.o_psi[0] : s.o_zeta[0]);
-                    char *org = base + ((size_t)s.fz * s.PY + s.fy) * s.LX * 4;
-                    fs.push_back(F{org, 4, s.LX, (long)s.LX, (long)s.PY * s.LX, s.g - 4});
+                    char *org = base + ((size_t)s.fz * s.PY + s.fy) * s.SX * 4;
+                    fs.push_back(F{org, 4, s.LX, (long)s.SX, (long)s.PY * s.SX, s.g - 4});
                 }
             }
         }
@@ -544,8 +550,9 @@ static void enqueue_update(fdtd_ctx *ctx, int shot, const Roles &R) {
             fdtd_launch_zmarch(stor, dd, wa + g.off, g.nwork, g.ry, R, g.zchunk, stepc, ctx->stream);
         toc(ctx, 0, t0);
         t0 = tic(ctx);
-        fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, ctx->o_band_all), ctx->nband_all, R, kBandZ, stepc,
-                         ctx->stream);
+        for (int k = 0; k < 3; ++k)
+            fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, ctx->o_band_all[k]), ctx->nband_all[k], k, R, kBandZ,
+                             stepc, ctx->stream);
         toc(ctx, 4, t0);
         for (int i = lo; i < hi; ++i) {
             const ShotH &s = ctx->shots[i];
@@ -569,7 +576,9 @@ static void enqueue_update(fdtd_ctx *ctx, int shot, const Roles &R) {
                                ctx->stream);
             toc(ctx, 0, t0);
             t0 = tic(ctx);
-            fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, s.o_band), s.nband, R, kBandZ, stepc, ctx->stream);
+            for (int k = 0; k < 3; ++k)
+                fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, s.o_band[k]), s.nband[k], k, R, kBandZ, stepc,
+                                 ctx->stream);
             toc(ctx, 4, t0);
         }
     }
@@ -662,8 +671,9 @@ static void enqueue_tblock(fdtd_ctx *ctx) {
                            ctx->stream);
         toc(ctx, 0, t0);
         t0 = tic(ctx);
-        fdtd_launch_band(ctx->storage, dd, (const BandItem *)wsp(ctx, s.o_band), s.nband, R, kBandZ, stepc,
-                         ctx->stream);
+        for (int k = 0; k < 3; ++k)
+            fdtd_launch_band(ctx->storage, dd, (const BandItem *)wsp(ctx, s.o_band[k]), s.nband[k], k, R, kBandZ, stepc,
+                             ctx->stream);
         toc(ctx, 4, t0);
         t0 = tic(ctx);
         fdtd_launch_record(ctx->storage, dd, 1, R, stepc, ctx->stream);
@@ -777,6 +787,14 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
         ShotH s;
         s.c = shots[i];
         plan_shot(s);
+        // kernels address a field plane, and a layer array, with 32-bit offsets
+        bool big = (size_t)s.S * s.esz > ((size_t)1 << 26);
+        for (int d = 0; d < 3; ++d) big = big || 2 * s.psi_elems[d] * 4 > ((size_t)1 << 31) - 4096;
+        if (big) {
+            delete ctx;
+            fprintf(stderr, "fdtd_create: shot %d: a field plane above 64 MiB or a layer array above 1 GiB\n", i);
+            return FDTD_EINVAL;
+        }
         if (s.gy || s.gz) {
             if (ghost_s && ghost_s != s.s) {
                 delete ctx;
@@ -806,9 +824,11 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
     size_t cap_all = 0;
     for (auto &s : ctx->shots) cap_all += work_capacity(s) + 8;
     ctx->o_work_all = take(sizeof(WorkItem) * cap_all);
-    size_t band_all = 0;
-    for (auto &s : ctx->shots) band_all += band_capacity(s);
-    ctx->o_band_all = take(sizeof(BandItem) * band_all);
+    for (int k = 0; k < 3; ++k) {
+        size_t band_all = 0;
+        for (auto &s : ctx->shots) band_all += band_capacity(s, k);
+        ctx->o_band_all[k] = take(sizeof(BandItem) * band_all);
+    }
     for (auto &s : ctx->shots) {
         s.o_u[0] = take(s.elems * s.esz);
         s.o_u[1] = take(s.elems * s.esz);
@@ -827,7 +847,7 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
         }
         s.o_prof = take((size_t)3 * 4 * s.nmax * 4);
         s.o_work = take(sizeof(WorkItem) * work_capacity(s));
-        s.o_band = take(sizeof(BandItem) * band_capacity(s));
+        for (int k = 0; k < 3; ++k) s.o_band[k] = take(sizeof(BandItem) * band_capacity(s, k));
         s.xbuf_bytes = xbuf_bytes(s);
         s.o_xbuf = take(s.xbuf_bytes);
         for (int p = 0; p < 2; ++p)
@@ -847,18 +867,18 @@ int fdtd_workspace_size(const fdtd_ctx *ctx, size_t *bytes) {
 
 static int write_work_lists(fdtd_ctx *ctx) {
     std::map<std::pair<int, int>, std::vector<WorkItem>> byplan;
-    std::vector<BandItem> band_all;
+    std::vector<BandItem> band_all[3];
     for (size_t i = 0; i < ctx->shots.size(); ++i) {
         ShotH &s = ctx->shots[i];
-        {
-            std::vector<BandItem> bt = band_tiles(s, (int)i);
+        for (int k = 0; k < 3; ++k) {
+            std::vector<BandItem> bt = band_tiles(s, (int)i, k);
             std::vector<BandItem> bw = xcd_order(bt);
-            if (bw.size() > band_capacity(s)) FAIL(ctx, FDTD_EINVAL, "band list overflow");
-            s.nband = (int)bw.size();
+            if (bw.size() > band_capacity(s, k)) FAIL(ctx, FDTD_EINVAL, "band list overflow");
+            s.nband[k] = (int)bw.size();
             if (!bw.empty())
-                HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_band), bw.data(), sizeof(BandItem) * bw.size(),
+                HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_band[k]), bw.data(), sizeof(BandItem) * bw.size(),
                                            hipMemcpyHostToDevice, ctx->stream));
-            if (s.variant != FDTD_VARIANT_NAIVE) band_all.insert(band_all.end(), bt.begin(), bt.end());
+            if (s.variant != FDTD_VARIANT_NAIVE) band_all[k].insert(band_all[k].end(), bt.begin(), bt.end());
         }
         std::vector<WorkItem> sp = shot_tiles(s, (int)i, s.ry, s.zchunk);
         std::vector<WorkItem> w = xcd_order(sp);
@@ -893,14 +913,14 @@ static int write_work_lists(fdtd_ctx *ctx) {
         all.insert(all.end(), wa.begin(), wa.end());
     }
     ctx->nwork_all = (int)all.size();
-    {
-        std::vector<BandItem> bw = xcd_order(band_all);
-        ctx->nband_all = (int)bw.size();
+    for (int k = 0; k < 3; ++k) {
+        std::vector<BandItem> bw = xcd_order(band_all[k]);
+        ctx->nband_all[k] = (int)bw.size();
         if (!bw.empty())
-            HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, ctx->o_band_all), bw.data(), sizeof(BandItem) * bw.size(),
+            HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, ctx->o_band_all[k]), bw.data(), sizeof(BandItem) * bw.size(),
                                        hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     if (!all.empty()) {
         HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, ctx->o_work_all), all.data(), sizeof(WorkItem) * all.size(),
                                    hipMemcpyHostToDevice, ctx->stream));

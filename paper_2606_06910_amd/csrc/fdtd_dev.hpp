@@ -87,6 +87,7 @@ struct DevShot {
     int nx, ny, nz, P, PY, S, fy, fz;
     int Llo[3], Lhi[3];
     int LX, LY, LZ, nmax;
+    int SX, SY, SZ;        // layer-array strides along the slab axis: width + 1 slot that stays zero
     int ghost[3];          // 1 if the axis has ghost (loopback) faces
     float cc;              // sum_d (c0 + 2 c1) / h_d^2
     float w2[3][5];        // (c0 + 2 c1) / h_d^2, then c_l / h_d^2 for l = 1..4
@@ -121,6 +122,8 @@ struct WorkItem {
 };
 
 // Work item of the band kernel: shot, band box, x tile, y tile, z chunk.
+#define BAND_TX 32
+#define BAND_TY 8
 struct BandItem {
     int shot, box, tx, ty, zc, pad0, pad1, pad2;
 };
@@ -183,10 +186,12 @@ __device__ __forceinline__ bool in_band(int c, int n, int lo, int hi) {
 __device__ __forceinline__ int slab_pos(int c, int n, int lo, int hi) {
     return c < lo ? c : lo + (c - (n - hi));
 }
-// element index of (x, y, z) in the compact psi/zeta array of axis d
+// element index of (x, y, z) in the compact psi/zeta array of axis d: x
+// [z+fz][y+fy][SX], y [z+fz][SY][nx], z [SZ][y+fy][nx]; slab position LX (LY,
+// LZ) is an extra slot that is never written and reads zero
 __device__ __forceinline__ long psi_index(const DevShot &s, int d, int x, int y, int z) {
-    if (d == 0) return ((long)(z + s.fz) * s.PY + (y + s.fy)) * s.LX + slab_pos(x, s.nx, s.Llo[0], s.Lhi[0]);
-    if (d == 1) return ((long)(z + s.fz) * s.LY + slab_pos(y, s.ny, s.Llo[1], s.Lhi[1])) * s.nx + x;
+    if (d == 0) return ((long)(z + s.fz) * s.PY + (y + s.fy)) * s.SX + slab_pos(x, s.nx, s.Llo[0], s.Lhi[0]);
+    if (d == 1) return ((long)(z + s.fz) * s.SY + slab_pos(y, s.ny, s.Llo[1], s.Lhi[1])) * s.nx + x;
     return ((long)slab_pos(z, s.nz, s.Llo[2], s.Lhi[2]) * s.PY + (y + s.fy)) * s.nx + x;
 }
 __device__ __forceinline__ int coord_n(const DevShot &s, int d) { return d == 0 ? s.nx : (d == 1 ? s.ny : s.nz); }
@@ -232,6 +237,29 @@ __device__ __forceinline__ float d1_axis(const float *w, const float lo[4], cons
 }
 // interior points (outside every band): cc*c + x pairs + y pairs + z pairs,
 // cc = sum_d w2[d][0]
+// stencil weights of a shot held in registers (loaded once per kernel)
+struct Coef {
+    float cc;
+    float w2[3][5];
+};
+__device__ __forceinline__ Coef load_coef(const DevShot &s) {
+    Coef k;
+    k.cc = s.cc;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int l = 0; l < 5; ++l) k.w2[d][l] = s.w2[d][l];
+    return k;
+}
+__device__ __forceinline__ float lap_interior(const Coef &k, float c, const float xl[4], const float xh[4],
+                                              const float yl[4], const float yh[4], const float zl[4],
+                                              const float zh[4]) {
+    float acc = k.cc * c;
+    acc = pairs2(k.w2[0], c, xl, xh, acc);
+    acc = pairs2(k.w2[1], c, yl, yh, acc);
+    acc = pairs2(k.w2[2], c, zl, zh, acc);
+    return acc;
+}
 __device__ __forceinline__ float lap_interior(const DevShot &s, float c, const float xl[4], const float xh[4],
                                               const float yl[4], const float yh[4], const float zl[4],
                                               const float zh[4]) {
@@ -241,14 +269,48 @@ __device__ __forceinline__ float lap_interior(const DevShot &s, float c, const f
     acc = pairs2(s.w2[2], c, zl, zh, acc);
     return acc;
 }
-// layer term of one axis; zeta updated in place when the point is in the slab
+
+// Buffer-resource access: a uniform base (scalar descriptor), a 32-bit byte
+// offset per lane and a uniform 32-bit byte offset.  Offsets stay below 2^31.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc make_rsrc(const void *base) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, 0x7fffffff, 0x00020000);
+}
+template <typename T> struct Buf;
+template <> struct Buf<float> {
+    static __device__ __forceinline__ float ld(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void st(Rsrc r, uint32_t vo, uint32_t so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
+    }
+};
+template <> struct Buf<_Float16> {
+    static __device__ __forceinline__ float ld(Rsrc r, uint32_t vo, uint32_t so) {
+        return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void st(Rsrc r, uint32_t vo, uint32_t so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, vo, so, 0);
+    }
+};
+template <> struct Buf<__bf16> {
+    static __device__ __forceinline__ float ld(Rsrc r, uint32_t vo, uint32_t so) {
+        return (float)__builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void st(Rsrc r, uint32_t vo, uint32_t so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (__bf16)v), r, vo, so, 0);
+    }
+};
+
+// layer term of one axis given the old zeta (slab points); returns Lt_d and
+// the new zeta in *zeta_new (slab points only)
 __device__ __forceinline__ float cpml_axis(float d2, float d1, float dpsi, float kinv, float dkinv, float a,
-                                           float b, bool slab, float *zeta) {
+                                           float b, bool slab, float zeta_old, float *zeta_new) {
     float eta = fmaf(kinv, d2, fmaf(dkinv, d1, dpsi));
     float z = 0.0f;
     if (slab) {
-        z = fmaf(b, *zeta, a * eta);
-        *zeta = z;
+        z = fmaf(b, zeta_old, a * eta);
+        *zeta_new = z;
     }
     return fmaf(kinv, eta, z);
 }
@@ -260,47 +322,61 @@ __device__ __forceinline__ float psi_update(float b, float psi, float a, float d
 }
 
 // Layer-aware Laplacian of one point whose neighbours are given; reads psi
-// neighbours from memory.  Returns sum_d Lt_d (or lap_interior when the point
-// is outside every band).
+// neighbours, profiles and zeta from memory (all of them before any
+// arithmetic, so that the loads are in flight together) and writes zeta back.
+// Returns sum_d Lt_d (lap_interior when the point is outside every band).
 __device__ __forceinline__ float lap_point(const DevShot &s, int x, int y, int z, float c, const float xl[4],
                                            const float xh[4], const float yl[4], const float yh[4],
                                            const float zl[4], const float zh[4]) {
-    bool bx = in_band(x, s.nx, s.Llo[0], s.Lhi[0]);
-    bool by = in_band(y, s.ny, s.Llo[1], s.Lhi[1]);
-    bool bz = in_band(z, s.nz, s.Llo[2], s.Lhi[2]);
+    const bool bx = in_band(x, s.nx, s.Llo[0], s.Lhi[0]);
+    const bool by = in_band(y, s.ny, s.Llo[1], s.Lhi[1]);
+    const bool bz = in_band(z, s.nz, s.Llo[2], s.Lhi[2]);
     if (!(bx || by || bz)) return lap_interior(s, c, xl, xh, yl, yh, zl, zh);
-    float L[3];
     const float *lo[3] = {xl, yl, zl};
     const float *hi[3] = {xh, yh, zh};
     const bool band[3] = {bx, by, bz};
     const int cc[3] = {x, y, z};
+    float pl[3][4], ph[3][4], pb[3], pa[3], pk[3], pdk[3], zo[3];
+    float *zp[3];
+    bool slab[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        float d2 = d2_axis(s.w2[d], c, lo[d], hi[d]);
+        const int k = cc[d], n = coord_n(s, d);
+        slab[d] = band[d] && in_slab(k, n, s.Llo[d], s.Lhi[d]);
+        zp[d] = nullptr;
+        zo[d] = 0.0f;
+        pb[d] = pa[d] = pk[d] = pdk[d] = 0.0f;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) pl[d][l] = ph[d][l] = 0.0f;
+        if (band[d]) {
+#pragma unroll
+            for (int l = 1; l <= 4; ++l) {
+                pl[d][l - 1] = psi_at(s, d, x - (d == 0) * l, y - (d == 1) * l, z - (d == 2) * l);
+                ph[d][l - 1] = psi_at(s, d, x + (d == 0) * l, y + (d == 1) * l, z + (d == 2) * l);
+            }
+            pb[d] = prof_at(s, d, 0, k);
+            pa[d] = prof_at(s, d, 1, k);
+            pk[d] = prof_at(s, d, 2, k);
+            pdk[d] = prof_at(s, d, 3, k);
+            if (slab[d]) {
+                zp[d] = &s.zeta[d][psi_index(s, d, x, y, z)];
+                zo[d] = *zp[d];
+            }
+        }
+    }
+    float L[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float d2 = d2_axis(s.w2[d], c, lo[d], hi[d]);
         if (!band[d]) {
             L[d] = d2;
             continue;
         }
-        int n = coord_n(s, d);
-        int k = cc[d];
-        float d1 = d1_axis(s.w1[d], lo[d], hi[d]);
-        float pl[4], ph[4];
-#pragma unroll
-        for (int l = 1; l <= 4; ++l) {
-            int xm = x, ym = y, zm = z, xp = x, yp = y, zp = z;
-            if (d == 0) { xm -= l; xp += l; }
-            if (d == 1) { ym -= l; yp += l; }
-            if (d == 2) { zm -= l; zp += l; }
-            pl[l - 1] = psi_at(s, d, xm, ym, zm);
-            ph[l - 1] = psi_at(s, d, xp, yp, zp);
-        }
-        float dpsi = d1_axis(s.w1[d], pl, ph);
-        bool slab = in_slab(k, n, s.Llo[d], s.Lhi[d]);
-        float zv = 0.0f;
-        float *zptr = &zv;
-        if (slab) zptr = &s.zeta[d][psi_index(s, d, x, y, z)];
-        L[d] = cpml_axis(d2, d1, dpsi, prof_at(s, d, 2, k), prof_at(s, d, 3, k), prof_at(s, d, 1, k),
-                         prof_at(s, d, 0, k), slab, zptr);
+        const float d1 = d1_axis(s.w1[d], lo[d], hi[d]);
+        const float dpsi = d1_axis(s.w1[d], pl[d], ph[d]);
+        float zn = 0.0f;
+        L[d] = cpml_axis(d2, d1, dpsi, pk[d], pdk[d], pa[d], pb[d], slab[d], zo[d], &zn);
+        if (slab[d]) *zp[d] = zn;
     }
     return (L[0] + L[1]) + L[2];
 }
@@ -380,10 +456,11 @@ __device__ __forceinline__ void point_update_global(const DevShot &s, const T *_
         zh[l - 1] = Store<T>::ld(u + c + (long)l * s.S);
     }
     const float uc = Store<T>::ld(u + c);
-    const float lt = lap_point(s, x, y, z, uc, xl, xh, yl, yh, zl, zh);
     const float mm = s.m[c];
     T *sec = IsInc<T>::v ? (T *)s.dinc : (T *)um;
-    const Upd r = time_update<T>(mm, lt, uc, Store<T>::ld(sec + c), is_source(s, x, y, z), src);
+    const float second = Store<T>::ld(sec + c);
+    const float lt = lap_point(s, x, y, z, uc, xl, xh, yl, yh, zl, zh);
+    const Upd r = time_update<T>(mm, lt, uc, second, is_source(s, x, y, z), src);
     Store<T>::st(w + c, r.u);
     if constexpr (IsInc<T>::v) Store<T>::st(sec + c, r.d);
 }

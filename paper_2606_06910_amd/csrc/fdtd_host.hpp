@@ -13,7 +13,7 @@ constexpr int kOFF = 128;   // leading pad of every field (elements)
 constexpr int kTYMAX = 64;  // tallest y tile (rows) a kernel may overhang
 constexpr int kMaxRec = 65536;  // receivers per shot with temporal blocking
 constexpr int kTimingClasses = 6;   // update, psi, record, exchange, band update, temporal block
-constexpr int kBandTX = 32, kBandTY = 16, kBandZ = 64;   // band-kernel tile and z chunk
+constexpr int kBandTX = BAND_TX, kBandTY = BAND_TY, kBandZ = 32;   // band-kernel tile and z chunk
 
 struct ShotH {
     fdtd_shot_config c;
@@ -26,6 +26,7 @@ struct ShotH {
     size_t esz = 4;            // bytes per stored field element
     int Llo[3] = {0, 0, 0}, Lhi[3] = {0, 0, 0};
     int LX = 0, LY = 0, LZ = 0, nmax = 0;
+    int SX = 0, SY = 0, SZ = 0;   // psi/zeta strides: slab width + 1 zero slot (0 without layers)
     size_t psi_elems[3] = {0, 0, 0};
     // workspace offsets
     size_t o_u[4] = {0, 0, 0, 0}, o_d = 0, o_m = 0, o_psi[3] = {0, 0, 0}, o_zeta[3] = {0, 0, 0}, o_prof = 0;
@@ -34,8 +35,8 @@ struct ShotH {
     int njobs[2][4] = {};
     long jobmax[2][4] = {};
     int nwork = 0;
-    size_t o_band = 0;         // band-kernel tile list (for the largest compute box)
-    int nband = 0;
+    size_t o_band[3] = {0, 0, 0};   // band-kernel tile lists per box kind (for the largest compute box)
+    int nband[3] = {0, 0, 0};
     // model / source / receivers
     bool vel_set = false;
     double vmax = 0, vref = 0, scale = 1;
@@ -69,8 +70,8 @@ struct fdtd_ctx {
     hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
     char *ws = nullptr;
     size_t ws_bytes = 0, need = 0;
-    size_t o_stepc = 0, o_scratch = 0, o_desc = 0, o_work_all = 0, o_band_all = 0;
-    int nwork_all = 0, nband_all = 0;
+    size_t o_stepc = 0, o_scratch = 0, o_desc = 0, o_work_all = 0, o_band_all[3] = {0, 0, 0};
+    int nwork_all = 0, nband_all[3] = {0, 0, 0};
     // multi-shot z-march launches: one per distinct (ry, zchunk) plan
     struct Group {
         int ry, zchunk;

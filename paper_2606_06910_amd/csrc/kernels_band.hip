@@ -3,140 +3,261 @@
 // The band is the union of the absorbing-layer slabs and the 4-cell margin
 // their psi derivative reaches (paper, section "CPML Boundary Layers": the
 // stretched second derivative and its memory variables).  It is cut into six
-// disjoint boxes (band_box); each box is tiled in 32 x 16 xy tiles that
-// march along z.  Per tile and plane:
-//   * the plane of u^n (tile plus a 4-cell halo) is staged in LDS for the x
-//     and y neighbours; the z neighbours come from a per-thread register
-//     queue of 9 planes;
-//   * every owned point evaluates lap_point (the layer-aware Laplacian of
-//     fdtd_dev.hpp, psi neighbours and zeta from the slab arrays) and the
-//     time update, with the same operation order as the other kernels.
-// Points outside every band are left to the interior kernels.
+// disjoint boxes (band_box) of three kinds, one kernel instance per kind:
+//   kind 0, boxes 0/1: z band (x, y band at the edges);
+//   kind 1, boxes 2/3: y band (x band at the edges), z outside its band;
+//   kind 2, boxes 4/5: x band only.
+// Boxes are tiled in BAND_TX x BAND_TY columns and chunks of planes.  A thread
+// owns a column and walks its planes with a register queue of u^n (and, for
+// kind 0, of psi_z) along z; x and y neighbours are buffer loads (L1/L2).
+// The layer data of the thread's x and y coordinates are set up once, those
+// of each plane are uniform (scalar).  The arithmetic is lap_point's,
+// operation for operation, so the bits equal the naive kernel's.  Points
+// outside every band are left to the interior kernels.
 #include "fdtd_dev.hpp"
 
 namespace {
-constexpr int BTX = 32;               // tile width (x)
-constexpr int BTY = 16;               // tile height (y): 8 thread rows x 2 points
-constexpr int BLW = BTX + 2 * FDTD_R; // LDS row length
-constexpr int BLH = BTY + 2 * FDTD_R; // LDS rows
-constexpr int BHALO = 2 * FDTD_R * BTY + 2 * FDTD_R * BTX;   // 128 x-halo + 256 y-halo values
+// layer data of one coordinate along one axis
+struct AxisPt {
+    float b, a, kinv, dkinv;
+    int band, slab;
+    int pos;              // slab position of the coordinate (slab points)
+    int npos[8];          // slab positions of the neighbours c-1..c-4, c+1..c+4; the zero slot
+                          // (slab width) where a neighbour lies outside [0, n) or the slabs
+};
+__device__ __forceinline__ void axis_point(const DevShot &s, int d, int c, AxisPt &A) {
+    const int n = coord_n(s, d), lo = s.Llo[d], hi = s.Lhi[d];
+    const bool band = in_band(c, n, lo, hi);
+    const bool slab = band && in_slab(c, n, lo, hi);
+    A.band = band;
+    A.slab = slab;
+    A.pos = slab ? slab_pos(c, n, lo, hi) : 0;
+    A.b = band ? prof_at(s, d, 0, c) : 0.0f;
+    A.a = band ? prof_at(s, d, 1, c) : 0.0f;
+    A.kinv = band ? prof_at(s, d, 2, c) : 0.0f;
+    A.dkinv = band ? prof_at(s, d, 3, c) : 0.0f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int cn = j < 4 ? c - (j + 1) : c + (j - 3);
+        const bool ok = band && cn >= 0 && cn < n && in_slab(cn, n, lo, hi);
+        A.npos[j] = ok ? slab_pos(cn, n, lo, hi) : lo + hi;
+    }
+}
 }  // namespace
 
-template <typename T>
+template <typename T, int KIND>
 __global__ __launch_bounds__(256) void k_band(const DevShot *__restrict__ shots, const BandItem *__restrict__ work,
                                               Roles R, int zchunk, const int *__restrict__ stepc) {
-    __shared__ float sm[BLH * BLW];
+    constexpr bool HAS_Y = KIND <= 1, HAS_Z = KIND == 0;
     const BandItem wi = work[blockIdx.x];
     const DevShot &s = shots[wi.shot];
     int blo[3], bhi[3];
     const int n3[3] = {s.nx, s.ny, s.nz};
     band_box(n3, s.Llo, s.Lhi, s.ghost, R.ext, wi.box, blo, bhi);
-    const int x0 = blo[0] + wi.tx * BTX;
-    const int y0 = blo[1] + wi.ty * BTY;
+    const int x = blo[0] + wi.tx * BAND_TX + (int)(threadIdx.x % BAND_TX);
+    const int y = blo[1] + wi.ty * BAND_TY + (int)(threadIdx.x / BAND_TX);
     const int za = blo[2] + wi.zc * zchunk;
-    const int bx1 = bhi[0], by1 = bhi[1];
-    if (x0 >= bx1 || y0 >= by1 || za >= bhi[2]) return;
+    if (x >= bhi[0] || y >= bhi[1] || za >= bhi[2]) return;   // no barriers below
     const int zb = min(za + zchunk, bhi[2]);
 
-    const int lx = threadIdx.x & (BTX - 1);
-    const int ly = threadIdx.x / BTX;   // 0..7, rows 2 ly and 2 ly + 1
-    const int x = x0 + lx;
-    const T *u = (const T *)s.u[R.iu];
-    const T *um = (const T *)s.u[R.ium1];
-    T *w = (T *)s.u[R.iout];
-    const long S = s.S, P = s.P;
-    long rowoff[2];
-    rowoff[0] = (long)(y0 + 2 * ly) * P + x;
-    rowoff[1] = rowoff[0] + P;
-
-    // halo values this thread stages: items t and t + 256 of 384
-    // (0..127: x halo, row r = i / 8, side (i / 4) & 1, offset i & 3;
-    //  128..383: y halo, 8 rows of 32)
-    int hslot[2];
-    long hoff[2];
+    const Coef K = load_coef(s);
+    float w1[3][5];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const int i = threadIdx.x + 256 * k;
-        hslot[k] = -1;
-        hoff[k] = 0;
-        if (i < 2 * FDTD_R * BTY) {
-            const int r = i >> 3, side = (i >> 2) & 1, o = i & 3;
-            const int col = side ? BTX + FDTD_R + o : o;
-            hslot[k] = (FDTD_R + r) * BLW + col;
-            hoff[k] = (long)(y0 + r) * P + (x0 - FDTD_R + col);
-        } else if (i < BHALO) {
-            const int j = i - 2 * FDTD_R * BTY, r8 = j / BTX, c = j % BTX;
-            const int lrow = r8 < FDTD_R ? r8 : BTY + r8;
-            hslot[k] = lrow * BLW + FDTD_R + c;
-            hoff[k] = (long)(y0 - FDTD_R + lrow) * P + x0 + c;
-        }
-    }
-
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int l = 0; l < 5; ++l) w1[d][l] = s.w1[d][l];
     const float srcamp = source_at(s, *stepc);
-    float q[9][2];
+    const bool src_col = x == s.sx && wrap_ghost(s, 1, y) == s.sy;
+    const long P = s.P, S = s.S, esz = sizeof(T);
+    const int fy = s.fy, fz = s.fz, nx = s.nx;
+
+    // u^n, the second state and u^{n+1}: element (x + dx, y + dy, z') at
+    //   base + (z' - za + 4) S esz [scalar] + vo + ((dy + 4) P + dx + 4) esz [lane]
+    const long lead = (long)(za - 4) * S - (long)fy * P - 4;
+    const Rsrc ru = make_rsrc((const char *)s.u[R.iu] + lead * esz);
+    const Rsrc rw = make_rsrc((char *)s.u[R.iout] + lead * esz);
+    const Rsrc rs = make_rsrc((char *)(IsInc<T>::v ? s.dinc : s.u[R.ium1]) + lead * esz);
+    const Rsrc rm = make_rsrc((const char *)s.m + lead * 4);
+    const uint32_t vo = (uint32_t)(((long)(y + fy - 4) * P + x) * esz);
+    const uint32_t vc = vo + (uint32_t)((4 * P + 4) * esz);                 // the point itself
+    const uint32_t vcm = (uint32_t)(((long)(y + fy) * P + x + 4) * 4);      // the point in m
+    const uint32_t Sb = (uint32_t)(S * esz), Smb = (uint32_t)(S * 4), Pb = (uint32_t)(P * esz);
+
+    AxisPt AX, AY;
+    axis_point(s, 0, x, AX);
+    if constexpr (HAS_Y) axis_point(s, 1, y, AY);
+    // psi_d and zeta_d of an axis through one descriptor (zeta_d follows psi_d in the workspace)
+    const Rsrc rpx = make_rsrc(s.psi[0]);
+    const uint32_t zdx = (uint32_t)((const char *)s.zeta[0] - (const char *)s.psi[0]);
+    const uint32_t vx_row = (uint32_t)((long)(y + fy) * s.SX * 4);   // psi_x, zeta_x row (+ 4 slab pos)
+    const uint32_t Spx = (uint32_t)((long)s.PY * s.SX * 4);          // psi_x, zeta_x plane
+    uint32_t px_off[8], py_off[8];
 #pragma unroll
-    for (int o = 0; o < 8; ++o)
+    for (int j = 0; j < 8; ++j) px_off[j] = vx_row + 4 * (uint32_t)AX.npos[j];
+    const uint32_t zx_off = vx_row + 4 * (uint32_t)AX.pos;
+    Rsrc rpy = rpx, rpz = rpx, rpr = rpx;
+    uint32_t zy_off = 0, Spy = 0, vz_col = 0, Spz = 0, zdy = 0, zdz = 0;
+    if constexpr (HAS_Y) {
+        rpy = make_rsrc(s.psi[1]);
+        zdy = (uint32_t)((const char *)s.zeta[1] - (const char *)s.psi[1]);
 #pragma unroll
-        for (int r = 0; r < 2; ++r) q[o][r] = Store<T>::ld(u + (long)(za - FDTD_R + o) * S + rowoff[r]);
+        for (int j = 0; j < 8; ++j) py_off[j] = 4 * (uint32_t)(AY.npos[j] * nx + x);
+        zy_off = 4 * (uint32_t)(AY.pos * nx + x);
+        Spy = (uint32_t)((long)s.SY * nx * 4);
+    }
+    const int nz = s.nz, zlo = s.Llo[2], zhi = s.Lhi[2];
+    if constexpr (HAS_Z) {
+        rpz = make_rsrc(s.psi[2]);
+        rpr = make_rsrc(s.prof);
+        zdz = (uint32_t)((const char *)s.zeta[2] - (const char *)s.psi[2]);
+        vz_col = (uint32_t)(((long)(y + fy) * nx + x) * 4);
+        Spz = (uint32_t)((long)s.PY * nx * 4);
+    }
+    // psi_z of plane p at the column, 0 outside the z slabs (uniform condition)
+    auto psi_z_at = [&](int p) -> float {
+        if (p < 0 || p >= nz || !in_slab(p, nz, zlo, zhi)) return 0.0f;
+        return Buf<float>::ld(rpz, vz_col, (uint32_t)slab_pos(p, nz, zlo, zhi) * Spz);
+    };
+
+    // z queues at the column: q[o] = u(x, y, z - 4 + o); pq[o] = psi_z there (0 outside its slab)
+    float q[9], pq[9];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) q[o] = Buf<T>::ld(ru, vc, o * Sb);
+    if constexpr (HAS_Z) {
+#pragma unroll
+        for (int o = 0; o < 8; ++o) pq[o] = psi_z_at(za - 4 + o);
+    }
 
 #pragma unroll 1
     for (int z = za; z < zb; ++z) {
-        const long pz = (long)z * S;
+        const uint32_t pz = (uint32_t)(z - za + 4) * Sb;
+        q[8] = Buf<T>::ld(ru, vc, pz + 4 * Sb);
+        float xl[4], xh[4], yl[4], yh[4], zl[4], zh[4];
 #pragma unroll
-        for (int r = 0; r < 2; ++r) q[8][r] = Store<T>::ld(u + pz + FDTD_R * S + rowoff[r]);
-        float hv[2] = {0.0f, 0.0f};
+        for (int l = 1; l <= 4; ++l) {
+            xl[l - 1] = Buf<T>::ld(ru, vc - (uint32_t)(l * esz), pz);
+            xh[l - 1] = Buf<T>::ld(ru, vc + (uint32_t)(l * esz), pz);
+            yl[l - 1] = Buf<T>::ld(ru, vc - (uint32_t)l * Pb, pz);
+            yh[l - 1] = Buf<T>::ld(ru, vc + (uint32_t)l * Pb, pz);
+            zl[l - 1] = q[4 - l];
+            zh[l - 1] = q[4 + l];
+        }
+        const float c = q[4];
+        const float second = Buf<T>::ld(rs, vc, pz);
+        const float mm = Buf<float>::ld(rm, vcm, (uint32_t)(z - za + 4) * Smb);
+        // psi neighbours and zeta of every band axis
+        float pl[3][4], ph[3][4], zo[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
-            if (hslot[k] >= 0) hv[k] = Store<T>::ld(u + pz + hoff[k]);
-        __syncthreads();   // readers of the previous plane are done
+        for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int r = 0; r < 2; ++r) sm[(FDTD_R + 2 * ly + r) * BLW + FDTD_R + lx] = q[4][r];
+            for (int l = 0; l < 4; ++l) pl[d][l] = ph[d][l] = 0.0f;
+        // (a neighbour outside the slabs reads the zero slot of its row)
+        const uint32_t sox = (uint32_t)(z + fz) * Spx;
+        if (AX.band) {
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
-            if (hslot[k] >= 0) sm[hslot[k]] = hv[k];
-        __syncthreads();
+            for (int j = 0; j < 8; ++j) {
+                const float v = Buf<float>::ld(rpx, px_off[j], sox);
+                if (j < 4) pl[0][j] = v;
+                else ph[0][j - 4] = v;
+            }
+            if (AX.slab) zo[0] = Buf<float>::ld(rpx, zx_off, sox + zdx);
+        }
+        uint32_t soy = 0;
+        if constexpr (HAS_Y) {
+            soy = (uint32_t)(z + fz) * Spy;
+            if (AY.band) {
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int y = y0 + 2 * ly + r;
-            if (x < bx1 && y < by1 && !in_box(R, x, y, z)) {
-                const int row = FDTD_R + 2 * ly + r, col = FDTD_R + lx;
-                float xl[4], xh[4], yl[4], yh[4], zl[4], zh[4];
-#pragma unroll
-                for (int l = 1; l <= 4; ++l) {
-                    xl[l - 1] = sm[row * BLW + col - l];
-                    xh[l - 1] = sm[row * BLW + col + l];
-                    yl[l - 1] = sm[(row - l) * BLW + col];
-                    yh[l - 1] = sm[(row + l) * BLW + col];
-                    zl[l - 1] = q[4 - l][r];
-                    zh[l - 1] = q[4 + l][r];
+                for (int j = 0; j < 8; ++j) {
+                    const float v = Buf<float>::ld(rpy, py_off[j], soy);
+                    if (j < 4) pl[1][j] = v;
+                    else ph[1][j - 4] = v;
                 }
-                const float c = q[4][r];
-                const float lt = lap_point(s, x, y, z, c, xl, xh, yl, yh, zl, zh);
-                const long off = pz + rowoff[r];
-                T *sec = IsInc<T>::v ? (T *)s.dinc : (T *)um;
-                const Upd up = time_update<T>(s.m[off], lt, c, Store<T>::ld(sec + off), is_source(s, x, y, z),
-                                              srcamp);
-                Store<T>::st(w + off, up.u);
-                if constexpr (IsInc<T>::v) Store<T>::st(sec + off, up.d);
+                if (AY.slab) zo[1] = Buf<float>::ld(rpy, zy_off, soy + zdy);
             }
         }
+        // layer data of plane z (uniform; every plane of a kind-0 box is in the z band)
+        AxisPt AZ;
+        AZ.band = 0;
+        AZ.slab = 0;
+        AZ.pos = 0;
+        AZ.b = AZ.a = AZ.kinv = AZ.dkinv = 0.0f;
+        if constexpr (HAS_Z) {
+            AZ.band = in_band(z, nz, zlo, zhi);
+            AZ.slab = AZ.band && in_slab(z, nz, zlo, zhi);
+            AZ.pos = AZ.slab ? slab_pos(z, nz, zlo, zhi) : 0;
+            if (AZ.band) {
+                const uint32_t pr = (uint32_t)((8 * s.nmax + z) * 4), pn = (uint32_t)(s.nmax * 4);
+                AZ.b = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                                     __builtin_bit_cast(int, Buf<float>::ld(rpr, 0, pr))));
+                AZ.a = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                                     __builtin_bit_cast(int, Buf<float>::ld(rpr, 0, pr + pn))));
+                AZ.kinv = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                                        __builtin_bit_cast(int, Buf<float>::ld(rpr, 0, pr + 2 * pn))));
+                AZ.dkinv = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                                         __builtin_bit_cast(int, Buf<float>::ld(rpr, 0, pr + 3 * pn))));
+            }
+            pq[8] = psi_z_at(z + 4);
 #pragma unroll
-        for (int o = 0; o < 8; ++o)
+            for (int l = 1; l <= 4; ++l) {
+                pl[2][l - 1] = pq[4 - l];
+                ph[2][l - 1] = pq[4 + l];
+            }
+            if (AZ.slab) zo[2] = Buf<float>::ld(rpz, vz_col, (uint32_t)AZ.pos * Spz + zdz);
+        }
+        // arithmetic of lap_point (every point here lies in a band)
+        const float *lo[3] = {xl, yl, zl};
+        const float *hi[3] = {xh, yh, zh};
+        const AxisPt *A3[3] = {&AX, &AY, &AZ};
+        const bool bnd[3] = {(bool)AX.band, HAS_Y && AY.band, HAS_Z && AZ.band};
+        const bool slb[3] = {(bool)AX.slab, HAS_Y && AY.slab, HAS_Z && AZ.slab};
+        float L[3], zn[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int r = 0; r < 2; ++r) q[o][r] = q[o + 1][r];
+        for (int d = 0; d < 3; ++d) {
+            const float d2 = d2_axis(K.w2[d], c, lo[d], hi[d]);
+            if (!bnd[d]) {
+                L[d] = d2;
+                continue;
+            }
+            const float d1 = d1_axis(w1[d], lo[d], hi[d]);
+            const float dpsi = d1_axis(w1[d], pl[d], ph[d]);
+            L[d] = cpml_axis(d2, d1, dpsi, A3[d]->kinv, A3[d]->dkinv, A3[d]->a, A3[d]->b, slb[d], zo[d], &zn[d]);
+        }
+        const float lt = (L[0] + L[1]) + L[2];
+        const bool src = src_col && wrap_ghost(s, 2, z) == s.sz;
+        const Upd up = time_update<T>(mm, lt, c, second, src, srcamp);
+        if (!in_box(R, x, y, z)) {
+            Buf<T>::st(rw, vc, pz, up.u);
+            if constexpr (IsInc<T>::v) Buf<T>::st(rs, vc, pz, up.d);
+            if (slb[0]) Buf<float>::st(rpx, zx_off, sox + zdx, zn[0]);
+            if constexpr (HAS_Y)
+                if (slb[1]) Buf<float>::st(rpy, zy_off, soy + zdy, zn[1]);
+            if constexpr (HAS_Z)
+                if (slb[2]) Buf<float>::st(rpz, vz_col, (uint32_t)AZ.pos * Spz + zdz, zn[2]);
+        }
+#pragma unroll
+        for (int o = 0; o < 8; ++o) q[o] = q[o + 1];
+        if constexpr (HAS_Z) {
+#pragma unroll
+            for (int o = 0; o < 8; ++o) pq[o] = pq[o + 1];
+        }
     }
 }
 
 template <typename T>
-static void launch_band_t(const DevShot *d_shots, const BandItem *work, int nwork, const Roles &R, int zchunk,
-                          const int *stepc, hipStream_t st) {
+static void launch_band_t(const DevShot *d_shots, const BandItem *work, int nwork, int kind, const Roles &R,
+                          int zchunk, const int *stepc, hipStream_t st) {
     if (nwork <= 0) return;
-    hipLaunchKernelGGL(k_band<T>, dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
+    if (kind == 0)
+        hipLaunchKernelGGL((k_band<T, 0>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
+    else if (kind == 1)
+        hipLaunchKernelGGL((k_band<T, 1>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
+    else
+        hipLaunchKernelGGL((k_band<T, 2>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
 }
 
-void fdtd_launch_band(int stor, const DevShot *d_shots, const BandItem *work, int nwork, const Roles &R, int zchunk,
-                      const int *stepc, hipStream_t st) {
-    if (stor == 1) launch_band_t<_Float16>(d_shots, work, nwork, R, zchunk, stepc, st);
-    else if (stor == 2) launch_band_t<__bf16>(d_shots, work, nwork, R, zchunk, stepc, st);
-    else launch_band_t<float>(d_shots, work, nwork, R, zchunk, stepc, st);
+void fdtd_launch_band(int stor, const DevShot *d_shots, const BandItem *work, int nwork, int kind, const Roles &R,
+                      int zchunk, const int *stepc, hipStream_t st) {
+    if (stor == 1) launch_band_t<_Float16>(d_shots, work, nwork, kind, R, zchunk, stepc, st);
+    else if (stor == 2) launch_band_t<__bf16>(d_shots, work, nwork, kind, R, zchunk, stepc, st);
+    else launch_band_t<float>(d_shots, work, nwork, kind, R, zchunk, stepc, st);
 }

@@ -4,9 +4,9 @@
 //                 slab point (paper, section "CPML Boundary Layers": the memory
 //                 variable recursion, updated before it is used).
 //  k_update_naive one thread per grid point; all layer logic inline.
-//  k_zmarch       xy tile (64 x 16*RY points) staged through LDS with a 4-cell
-//                 halo, marching along z with a 9-plane register queue of u^n;
-//                 4 consecutive x points per lane (16-byte loads).
+//  k_zmarch       points outside the layer bands: xy tile (64 x 4*RY points)
+//                 staged through LDS with a 4-cell halo, marching along z with
+//                 a 9-plane register queue of u^n; one x point per lane.
 //  k_record       receiver gather for every shot and the device step counter.
 //
 // All kernels evaluate a point with the shared functions of fdtd_dev.hpp, so
@@ -99,182 +99,144 @@ __global__ __launch_bounds__(256) void k_update_naive(const DevShot *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// z-marching update
+// z-marching update of the points outside the layer bands.
+//
+// A 256-thread workgroup owns an xy tile of 64 x TY points (TY = 4 RY) and a
+// z chunk.  Lane l of wave w owns column x0 + l, rows w RY .. w RY + RY - 1.
+// Per thread, a register queue of u^n planes along z (the queue index is a
+// compile-time phase, so the queue never moves between registers); the
+// centre plane with a 4-cell halo goes to one of two LDS buffers (one
+// barrier per plane); x neighbours and y neighbours outside the thread's own
+// rows come from LDS, the others from registers.  Global loads run two planes
+// ahead of their use: u^n (queue of 11 planes, z - 4 .. z + 6), and u^{n-1}
+// (or d^n), m and the halo (two more planes held in registers).  Addresses
+// are a uniform plane base plus a loop-invariant 32-bit offset per lane.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float comp(const float4 &v, int k) {
-    return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
-}
-__device__ __forceinline__ void set_comp(float4 &v, int k, float f) {
-    if (k == 0) v.x = f;
-    else if (k == 1) v.y = f;
-    else if (k == 2) v.z = f;
-    else v.w = f;
-}
+constexpr int ZQ = 11;   // queue planes: 9 of the stencil + 2 in flight
+template <int RY> struct ZM {
+    static constexpr int TY = 4 * RY;                      // tile rows
+    static constexpr int LW = 64 + 2 * FDTD_R;             // LDS row length
+    static constexpr int LH = TY + 2 * FDTD_R;             // LDS rows
+    static constexpr int LB = LH * LW + 4;                 // one LDS buffer (+ a dummy slot)
+    static constexpr int NH = 2 * FDTD_R * TY + 2 * FDTD_R * 64;   // halo values per plane
+    static constexpr int HS = (NH + 255) / 256;            // halo values per thread
+};
 
 template <typename T, int RY> struct ZCtx {
-    static constexpr int TY = 16 * RY;
-    static constexpr int NROW = TY + 8;
-    const DevShot *s;
-    const T *u;         // u^n
-    const T *um;        // u^{n-1} (FP32 storage)
-    T *w;               // u^{n+1} out (FP32: may equal um, in-place step)
-    T *sec;             // second state field: FP32 u^{n-1}, 16-bit d^n (updated in place)
-    const Roles *R;     // roles and exclusion box
-    const float *m;
-    int x0, y0, x, tx, ty;
-    int yhi;
-    long rowoff[RY];    // y*P + x for own rows
-    int halo_slot;      // LDS float4 index this thread fills, -1 if none
-    long halo_off;      // element offset (within a plane) of that halo float4
-    bool cpml_xy;       // tile touches an x or y band
-    bool partial;       // tile's xy footprint overlaps the exclusion box only partly
-    int zlo_band, zhi_band; // z band: z < zlo_band || z >= zhi_band
-    int step;
+    Coef K;
+    // byte bases such that element (x, y, z) of a field is at base + z * Sb + off(x, y)
+    const char *u, *m;
+    char *w, *sec;       // u^{n+1} out; FP32: u^{n-1} (may be w: in-place step), 16-bit: d^n (in place)
+    uint32_t Sb, Smb;    // plane strides in bytes: field, m
+    Rsrc ru, rm, rw, rs; // descriptors based at the current round's first plane
+    uint32_t off[RY], offm[RY];   // own rows: field and m byte offsets within a plane
+    uint32_t hoff[ZM<RY>::HS];    // halo byte offsets (a lane without a halo value reads its own point)
+    int hslot[ZM<RY>::HS];        // halo LDS index (the dummy slot for a lane without one)
+    float hc[ZM<RY>::HS], umc[RY], mc[RY];   // halo, second state and m of plane z
+    float h1[ZM<RY>::HS], um1[RY], m1[RY];   // the same of plane z + 1
+    const Roles *R;
+    int x, y0, lane, r0; // column, tile origin row, lane, first own row (tile-local)
+    int nlo[3], nhi[3];  // box of points outside every band
+    int sx, sy, sz;      // source node
+    bool full;           // tile inside the non-band box and clear of the exclusion box
+    bool partial;        // tile overlaps the exclusion box partly
+    bool src_tile;       // the source column lies in this tile (or a ghost image of it)
     float src;
 };
 
+// plane z = z0 + PH of a round that started at plane z0 (descriptors based at z0)
 template <typename T, int RY, int PH>
-__device__ __forceinline__ void zbody(ZCtx<T, RY> &C, float4 (&q)[9][RY], float4 *sm, int z) {
-    constexpr int TY = ZCtx<T, RY>::TY;
-    const DevShot &s = *C.s;
-    auto slot = [](int o) { return (PH + 4 + o + 9) % 9; };
-    const long pz = (long)z * s.S;
-    // global loads for this plane
+__device__ __forceinline__ void zbody(ZCtx<T, RY> &C, const DevShot &s, float (&q)[ZQ][RY], float *L, int z) {
+    using G = ZM<RY>;
+    auto slot = [](int o) { return (PH + 4 + o + ZQ) % ZQ; };
+    // loads two planes ahead of their use: u^n plane z + 6, the rest plane z + 2
+    float hn[G::HS], umn[RY], mn[RY];
+    {
+        const uint32_t s6 = (PH + 6) * C.Sb, s2 = (PH + 2) * C.Sb, m2 = (PH + 2) * C.Smb;
 #pragma unroll
-    for (int r = 0; r < RY; ++r) q[slot(4)][r] = Store<T>::ld4(C.u + pz + 4 * (long)s.S + C.rowoff[r]);
-    float4 um1[RY], mv[RY];
+        for (int r = 0; r < RY; ++r) q[slot(6)][r] = Buf<T>::ld(C.ru, C.off[r], s6);
+#pragma unroll
+        for (int k = 0; k < G::HS; ++k) hn[k] = Buf<T>::ld(C.ru, C.hoff[k], s2);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            umn[r] = Buf<T>::ld(C.rs, C.off[r], s2);
+            mn[r] = Buf<float>::ld(C.rm, C.offm[r], m2);
+        }
+    }
+    // centre plane to LDS
+#pragma unroll
+    for (int r = 0; r < RY; ++r) L[(FDTD_R + C.r0 + r) * G::LW + FDTD_R + C.lane] = q[slot(0)][r];
+#pragma unroll
+    for (int k = 0; k < G::HS; ++k) L[C.hslot[k]] = C.hc[k];
+    __syncthreads();
+    const bool srcplane = C.src_tile && wrap_ghost(s, 2, z) == C.sz;
+    const uint32_t s0 = PH * C.Sb;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-        um1[r] = Store<T>::ld4(C.sec + pz + C.rowoff[r]);
-        mv[r] = *(const float4 *)(C.m + pz + C.rowoff[r]);
-    }
-    float4 hv = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (C.halo_slot >= 0) hv = Store<T>::ld4(C.u + pz + C.halo_off);
-    __syncthreads();
+        const int y = C.y0 + C.r0 + r;
+        const float *row = L + (FDTD_R + C.r0 + r) * G::LW + FDTD_R + C.lane;
+        float xl[4], xh[4], yl[4], yh[4], zl[4], zh[4];
 #pragma unroll
-    for (int r = 0; r < RY; ++r) sm[(4 + C.ty * RY + r) * 18 + 1 + C.tx] = q[slot(0)][r];
-    if (C.halo_slot >= 0) sm[C.halo_slot] = hv;
-    __syncthreads();
-    // y column of this lane's float4: rows ty*RY .. ty*RY+RY+7 (centre rows from registers)
-    float4 ycol[RY + 8];
-#pragma unroll
-    for (int j = 0; j < RY + 8; ++j) {
-        if (j >= 4 && j < 4 + RY) ycol[j] = q[slot(0)][j - 4];
-        else ycol[j] = sm[(C.ty * RY + j) * 18 + 1 + C.tx];
+        for (int l = 1; l <= 4; ++l) {
+            xl[l - 1] = row[-l];
+            xh[l - 1] = row[l];
+            yl[l - 1] = r - l >= 0 ? q[slot(0)][r - l >= 0 ? r - l : 0] : row[-l * G::LW];
+            yh[l - 1] = r + l < RY ? q[slot(0)][r + l < RY ? r + l : 0] : row[l * G::LW];
+            zl[l - 1] = q[slot(-l)][r];
+            zh[l - 1] = q[slot(l)][r];
+        }
+        const float c = q[slot(0)][r];
+        const float lt = lap_interior(C.K, c, xl, xh, yl, yh, zl, zh);
+        const bool src = srcplane && C.x == C.sx && wrap_ghost(s, 1, y) == C.sy;
+        const Upd up = time_update<T>(C.mc[r], lt, c, C.umc[r], src, C.src);
+        const bool ok = C.full || (C.x >= C.nlo[0] && C.x < C.nhi[0] && y >= C.nlo[1] && y < C.nhi[1] &&
+                                   !(C.partial && in_box(*C.R, C.x, y, z)));
+        if (ok) {
+            Buf<T>::st(C.rw, C.off[r], s0, up.u);
+            if constexpr (IsInc<T>::v) Buf<T>::st(C.rs, C.off[r], s0, up.d);
+        }
     }
-    const bool cpml = C.cpml_xy || z < C.zlo_band || z >= C.zhi_band;
-    const bool srcplane = (wrap_ghost(s, 2, z) == s.sz);
+#pragma unroll
+    for (int k = 0; k < G::HS; ++k) {
+        C.hc[k] = C.h1[k];
+        C.h1[k] = hn[k];
+    }
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-        const int y = C.y0 + C.ty * RY + r;
-        const float4 L = sm[(4 + C.ty * RY + r) * 18 + C.tx];
-        const float4 R = sm[(4 + C.ty * RY + r) * 18 + C.tx + 2];
-        const float4 Cc = q[slot(0)][r];
-        const float xa[12] = {L.x, L.y, L.z, L.w, Cc.x, Cc.y, Cc.z, Cc.w, R.x, R.y, R.z, R.w};
-        float4 out, outd;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            float xl[4], xh[4], yl[4], yh[4], zl[4], zh[4];
-#pragma unroll
-            for (int l = 1; l <= 4; ++l) {
-                xl[l - 1] = xa[4 + k - l];
-                xh[l - 1] = xa[4 + k + l];
-                yl[l - 1] = comp(ycol[4 + r - l], k);
-                yh[l - 1] = comp(ycol[4 + r + l], k);
-                zl[l - 1] = comp(q[slot(-l)][r], k);
-                zh[l - 1] = comp(q[slot(l)][r], k);
-            }
-            const float c = xa[4 + k];
-            const float lt = lap_interior(s, c, xl, xh, yl, yh, zl, zh);
-            const bool src = srcplane && C.x + k == s.sx && wrap_ghost(s, 1, y) == s.sy;
-            const Upd u = time_update<T>(comp(mv[r], k), lt, c, comp(um1[r], k), src, C.src);
-            set_comp(out, k, u.u);
-            set_comp(outd, k, u.d);
-        }
-        if (y < C.yhi) {
-            T *dst = C.w + pz + C.rowoff[r];
-            T *dsd = C.sec + pz + C.rowoff[r];
-            if (!cpml && !C.partial && C.x + 3 < s.nx) {
-                Store<T>::st4(dst, out);
-                if constexpr (IsInc<T>::v) Store<T>::st4(dsd, outd);
-            } else {
-                // band points are written by the layer pass (it still needs the old state there);
-                // points of the exclusion box are left alone
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (C.x + k < s.nx && !(cpml && any_band(s, C.x + k, y, z)) &&
-                        !(C.partial && in_box(*C.R, C.x + k, y, z))) {
-                        Store<T>::st(dst + k, comp(out, k));
-                        if constexpr (IsInc<T>::v) Store<T>::st(dsd + k, comp(outd, k));
-                    }
-            }
-        }
+        C.umc[r] = C.um1[r];
+        C.um1[r] = umn[r];
+        C.mc[r] = C.m1[r];
+        C.m1[r] = mn[r];
     }
 }
 
 template <typename T, int RY>
 __global__ __launch_bounds__(256) void k_zmarch(const DevShot *__restrict__ shots, const WorkItem *__restrict__ work,
                                                Roles R, int zchunk, const int *__restrict__ stepc) {
-    constexpr int TY = 16 * RY;
-    constexpr int NROW = TY + 8;
-    __shared__ float4 sm[NROW * 18];
+    using G = ZM<RY>;
+    __shared__ float sm[2 * G::LB];
     const WorkItem wi = work[blockIdx.x];
     const DevShot &s = shots[wi.shot];
     const int ext = R.ext;
-    Box bx = shot_box(s, ext);
+    const Box bx = shot_box(s, ext);
     ZCtx<T, RY> C;
-    C.s = &s;
-    C.y0 = bx.ylo + wi.ty * TY;
+    const int x0 = wi.tx * 64;
+    C.y0 = bx.ylo + wi.ty * G::TY;
     if (C.y0 >= bx.yhi) return;
     const int zb = bx.zlo + wi.zc * zchunk;
     if (zb >= bx.zhi) return;
     const int ze = min(zb + zchunk, bx.zhi);
-    C.yhi = bx.yhi;
-    C.u = (const T *)s.u[R.iu];
-    C.um = (const T *)s.u[R.ium1];
-    C.w = (T *)s.u[R.iout];
-    C.sec = IsInc<T>::v ? (T *)s.dinc : (T *)s.u[R.ium1];
-    C.R = &R;
-    C.m = s.m;
-    C.x0 = wi.tx * 64;
-    C.tx = threadIdx.x & 15;
-    C.ty = threadIdx.x >> 4;
-    C.x = C.x0 + 4 * C.tx;
-#pragma unroll
-    for (int r = 0; r < RY; ++r) C.rowoff[r] = (long)(C.y0 + C.ty * RY + r) * s.P + C.x;
-    // halo assignment: 2*TY x-halo float4s, then 8 rows x 16 float4 y-halo
-    const int t = threadIdx.x;
-    C.halo_slot = -1;
-    C.halo_off = 0;
-    if (t < 2 * TY) {
-        int row = t >> 1, side = t & 1;
-        C.halo_slot = (4 + row) * 18 + (side ? 17 : 0);
-        C.halo_off = (long)(C.y0 + row) * s.P + (side ? C.x0 + 64 : C.x0 - 4);
-    } else if (t < 2 * TY + 128) {
-        int k = t - 2 * TY, r8 = k >> 4, col = k & 15;
-        int lrow = r8 < 4 ? r8 : TY + r8;
-        int gy = r8 < 4 ? C.y0 - 4 + r8 : C.y0 + TY + (r8 - 4);
-        C.halo_slot = lrow * 18 + 1 + col;
-        C.halo_off = (long)gy * s.P + C.x0 + 4 * col;
-    }
-    // tile/plane layer classification
-    bool cx = false, cy = false;
-    if (s.Llo[0] > 0 && C.x0 < s.Llo[0] + FDTD_R) cx = true;
-    if (s.Lhi[0] > 0 && C.x0 + 63 >= s.nx - s.Lhi[0] - FDTD_R) cx = true;
-    if (s.Llo[1] > 0 && C.y0 < s.Llo[1] + FDTD_R) cy = true;
-    if (s.Lhi[1] > 0 && C.y0 + TY - 1 >= s.ny - s.Lhi[1] - FDTD_R) cy = true;
-    C.cpml_xy = cx || cy;
-    C.zlo_band = s.Llo[2] > 0 ? s.Llo[2] + FDTD_R : -(1 << 30);
-    C.zhi_band = s.Lhi[2] > 0 ? s.nz - s.Lhi[2] - FDTD_R : (1 << 30);
-    C.step = *stepc;
-    C.src = source_at(s, C.step);
+    const int n3[3] = {s.nx, s.ny, s.nz};
+    band_box(n3, s.Llo, s.Lhi, s.ghost, ext, 6, C.nlo, C.nhi);
+    const int fx1 = min(x0 + 64, s.nx), fy1 = min(C.y0 + G::TY, bx.yhi);
+    // a tile whose footprint lies inside the band has nothing to do (the band kernel's points)
+    if (x0 >= C.nhi[0] || fx1 <= C.nlo[0] || C.y0 >= C.nhi[1] || fy1 <= C.nlo[1]) return;
 
-    // exclusion box: a tile whose valid xy footprint lies inside it skips the
-    // planes it covers (two z segments); a tile overlapping it partly masks points
-    const int fx1 = min(C.x0 + 64, s.nx), fy1 = min(C.y0 + TY, bx.yhi);
+    // exclusion box: a tile whose footprint lies inside it skips the planes it
+    // covers (two z segments); a tile overlapping it partly masks points
     const bool boxz = R.lo[2] < R.hi[2] && R.lo[2] < ze && R.hi[2] > zb;
-    const bool ovxy = C.x0 < R.hi[0] && fx1 > R.lo[0] && C.y0 < R.hi[1] && fy1 > R.lo[1];
-    const bool inxy = C.x0 >= R.lo[0] && fx1 <= R.hi[0] && C.y0 >= R.lo[1] && fy1 <= R.hi[1];
+    const bool ovxy = x0 < R.hi[0] && fx1 > R.lo[0] && C.y0 < R.hi[1] && fy1 > R.lo[1];
+    const bool inxy = x0 >= R.lo[0] && fx1 <= R.hi[0] && C.y0 >= R.lo[1] && fy1 <= R.hi[1];
     int seg_a[2] = {zb, 0}, seg_b[2] = {ze, 0};
     int nseg = 1;
     C.partial = false;
@@ -288,42 +250,108 @@ __global__ __launch_bounds__(256) void k_zmarch(const DevShot *__restrict__ shot
             C.partial = true;
         }
     }
+    for (int sg = 0; sg < nseg; ++sg) {   // planes of the z band are the band kernel's
+        seg_a[sg] = max(seg_a[sg], C.nlo[2]);
+        seg_b[sg] = min(seg_b[sg], C.nhi[2]);
+    }
+    C.full = !C.partial && x0 >= C.nlo[0] && x0 + 64 <= C.nhi[0] && C.y0 >= C.nlo[1] && C.y0 + G::TY <= C.nhi[1];
 
-    // band points are the band kernel's: planes of the z band are skipped, and
-    // a tile whose footprint lies inside the x or y band has nothing to do
+    C.K = load_coef(s);
+    const long P = s.P, esz = sizeof(T);
+    const long lead = (long)s.fy * P + FDTD_R;     // elements before (x = -4, y = -fy) within a plane
+    C.Sb = (uint32_t)((long)s.S * esz);
+    C.Smb = (uint32_t)((long)s.S * 4);
+    C.u = (const char *)s.u[R.iu] - lead * esz;
+    C.w = (char *)s.u[R.iout] - lead * esz;
+    C.sec = (char *)(IsInc<T>::v ? s.dinc : s.u[R.ium1]) - lead * esz;
+    C.m = (const char *)s.m - lead * 4;
+    C.R = &R;
+    C.lane = threadIdx.x & 63;
+    C.r0 = (threadIdx.x >> 6) * RY;
+    C.x = x0 + C.lane;
+    C.sx = s.sx;
+    C.sy = s.sy;
+    C.sz = s.sz;
+    // the source column (or a ghost image of it) in this tile?
     {
-        int nlo[3], nhi[3];
-        const int n3[3] = {s.nx, s.ny, s.nz};
-        band_box(n3, s.Llo, s.Lhi, s.ghost, ext, 6, nlo, nhi);
-        if (C.x0 >= nhi[0] || fx1 <= nlo[0] || C.y0 >= nhi[1] || fy1 <= nlo[1]) return;
-        for (int sg = 0; sg < nseg; ++sg) {
-            seg_a[sg] = max(seg_a[sg], nlo[2]);
-            seg_b[sg] = min(seg_b[sg], nhi[2]);
+        bool iny = false;
+        for (int o = -1; o <= 1; ++o) {
+            if (o != 0 && !s.ghost[1]) continue;
+            const int yy = s.sy + o * s.ny;
+            iny = iny || (yy >= C.y0 && yy < C.y0 + G::TY);
+        }
+        C.src_tile = s.wav != nullptr && s.sx >= x0 && s.sx < x0 + 64 && iny;
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const long e = (long)(C.y0 + C.r0 + r + s.fy) * P + C.x + FDTD_R;
+        C.off[r] = (uint32_t)(e * esz);
+        C.offm[r] = (uint32_t)(e * 4);
+    }
+    // halo: values 0 .. 8 TY - 1 are the x halo (row i / 8, column i % 8: 4 left, 4
+    // right), then 8 rows of 64 (4 above, 4 below the tile)
+#pragma unroll
+    for (int k = 0; k < G::HS; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        C.hslot[k] = G::LH * G::LW;     // dummy
+        C.hoff[k] = C.off[0];
+        if (i < 2 * FDTD_R * G::TY) {
+            const int row = i >> 3, c8 = i & 7;
+            const int col = c8 < 4 ? c8 : 64 + c8;     // LDS column
+            C.hslot[k] = (FDTD_R + row) * G::LW + col;
+            C.hoff[k] = (uint32_t)(((long)(C.y0 + row + s.fy) * P + x0 + col) * esz);
+        } else if (i < G::NH) {
+            const int j = i - 2 * FDTD_R * G::TY, r8 = j >> 6, c = j & 63;
+            const int lrow = r8 < FDTD_R ? r8 : G::TY + r8;
+            C.hslot[k] = lrow * G::LW + FDTD_R + c;
+            C.hoff[k] = (uint32_t)(((long)(C.y0 - FDTD_R + lrow + s.fy) * P + x0 + FDTD_R + c) * esz);
         }
     }
-    float4 q[9][RY];
+    C.src = source_at(s, *stepc);
+
+    float q[ZQ][RY];
+    int it = 0;
     for (int sg = 0; sg < nseg; ++sg) {
         const int a = seg_a[sg], b = seg_b[sg];
         if (a >= b) continue;
+        {
+            // planes a - 4 .. a + 5 (phase 0: slot o + 4); plane a + 6 is the first body's
+            const Rsrc ru = make_rsrc(C.u + (long)(a - 4) * C.Sb);
 #pragma unroll
-        for (int o = -4; o < 4; ++o)
+            for (int o = -4; o < 6; ++o)
 #pragma unroll
-            for (int r = 0; r < RY; ++r) q[o + 4][r] = Store<T>::ld4(C.u + (long)(a + o) * s.S + C.rowoff[r]);
+                for (int r = 0; r < RY; ++r) q[o + 4][r] = Buf<T>::ld(ru, C.off[r], (o + 4) * C.Sb);
+            const Rsrc rs = make_rsrc(C.sec + (long)a * C.Sb);
+            const Rsrc rm = make_rsrc(C.m + (long)a * C.Smb);
+            const uint32_t u4 = 4 * C.Sb, u5 = 5 * C.Sb;
 #pragma unroll
-        for (int r = 0; r < RY; ++r) q[8][r] = make_float4(0.f, 0.f, 0.f, 0.f);
-
-        for (int z = a; z < b; ++z) {
-            switch ((z - a) % 9) {
-            case 0: zbody<T, RY, 0>(C, q, sm, z); break;
-            case 1: zbody<T, RY, 1>(C, q, sm, z); break;
-            case 2: zbody<T, RY, 2>(C, q, sm, z); break;
-            case 3: zbody<T, RY, 3>(C, q, sm, z); break;
-            case 4: zbody<T, RY, 4>(C, q, sm, z); break;
-            case 5: zbody<T, RY, 5>(C, q, sm, z); break;
-            case 6: zbody<T, RY, 6>(C, q, sm, z); break;
-            case 7: zbody<T, RY, 7>(C, q, sm, z); break;
-            default: zbody<T, RY, 8>(C, q, sm, z); break;
+            for (int r = 0; r < RY; ++r) {
+                q[ZQ - 1][r] = 0.0f;
+                C.umc[r] = Buf<T>::ld(rs, C.off[r], 0);
+                C.mc[r] = Buf<float>::ld(rm, C.offm[r], 0);
+                C.um1[r] = Buf<T>::ld(rs, C.off[r], C.Sb);
+                C.m1[r] = Buf<float>::ld(rm, C.offm[r], C.Smb);
             }
+#pragma unroll
+            for (int k = 0; k < G::HS; ++k) {
+                C.hc[k] = Buf<T>::ld(ru, C.hoff[k], u4);
+                C.h1[k] = Buf<T>::ld(ru, C.hoff[k], u5);
+            }
+        }
+        for (int z0 = a; z0 < b; z0 += ZQ) {
+            C.ru = make_rsrc(C.u + (long)z0 * C.Sb);
+            C.rs = make_rsrc(C.sec + (long)z0 * C.Sb);
+            C.rm = make_rsrc(C.m + (long)z0 * C.Smb);
+            C.rw = make_rsrc(C.w + (long)z0 * C.Sb);
+            const int n = b - z0;
+#define ZSTEP(PH)                                                                 \
+    if (n > PH) {                                                                 \
+        zbody<T, RY, PH>(C, s, q, sm + (it & 1) * G::LB, z0 + PH);                \
+        ++it;                                                                     \
+    }
+            ZSTEP(0) ZSTEP(1) ZSTEP(2) ZSTEP(3) ZSTEP(4) ZSTEP(5)
+            ZSTEP(6) ZSTEP(7) ZSTEP(8) ZSTEP(9) ZSTEP(10)
+#undef ZSTEP
         }
     }
 }
@@ -369,15 +397,16 @@ template <typename T>
 static void launch_zmarch_t(const DevShot *d_shots, const WorkItem *work, int nwork, int ry, const Roles &R,
                             int zchunk, const int *stepc, hipStream_t st) {
     if (nwork <= 0) return;
+    // plan rows ry = 1, 2, 4: tiles of 64 x 8 ry points (2 ry rows per thread)
     switch (ry) {
     case 1:
-        hipLaunchKernelGGL((k_zmarch<T, 1>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
+        hipLaunchKernelGGL((k_zmarch<T, 2>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
         break;
     case 4:
-        hipLaunchKernelGGL((k_zmarch<T, 4>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
+        hipLaunchKernelGGL((k_zmarch<T, 8>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
         break;
     default:
-        hipLaunchKernelGGL((k_zmarch<T, 2>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
+        hipLaunchKernelGGL((k_zmarch<T, 4>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
         break;
     }
 }

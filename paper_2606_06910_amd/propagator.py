@@ -161,7 +161,8 @@ class Propagator:
         check(self.L.fdtd_set_timing(self.ctx, 1 if enable else 0), self.ctx)
 
     def timing(self, kernel_class: int = 0):
-        """(mean ms, count) of one kernel class: 0 update, 1 psi, 2 receivers, 3 exchange."""
+        """(mean ms, count) of one kernel class: 0 update outside the layer bands,
+        1 psi, 2 receivers, 3 exchange, 4 band update, 5 temporal block."""
         ms, n = ctypes.c_double(), ctypes.c_int64()
         check(self.L.fdtd_get_timing(self.ctx, kernel_class, ctypes.byref(ms), ctypes.byref(n)), self.ctx)
         return float(ms.value), int(n.value)
