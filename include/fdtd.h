@@ -29,8 +29,11 @@
  *    tensor).  The caller owns them; the library only borrows them and never
  *    frees them.  The library never allocates device memory on the data
  *    path: all of its state lives in the caller-provided workspace.
- *  - All GPU work is enqueued on the stream given to fdtd_create; no entry
- *    point synchronises unless stated.
+ *  - All GPU work is ordered on the stream given to fdtd_create; no entry
+ *    point synchronises unless stated.  Inside a step the library forks part
+ *    of the work onto a second stream of its own (created by
+ *    fdtd_bind_workspace) and joins it back before the step ends, with
+ *    events, so the caller's stream still sees every step complete in order.
  *  - One host thread per context at a time.
  */
 #ifndef FDTD_H
@@ -188,7 +191,7 @@ int fdtd_autotune(fdtd_ctx *ctx, const char *cache_path);
 
 /* Fix the kernel plan of one shot by hand (what fdtd_autotune chooses):
  * variant (naive / z-march / temporal blocking), z-march tile size
- * (1, 2 or 4: tiles of 64 x 8*tile_ry points), z-chunk length (16..4096 planes
+ * (1, 2, 4 or 8: tiles of 64 x 8*tile_ry points), z-chunk length (16..4096 planes
  * per workgroup) and temporal depth (2 or 4, temporal blocking only).
  * Results do not depend on the plan (same bits). */
 int fdtd_set_plan(fdtd_ctx *ctx, int32_t shot, int32_t variant, int32_t tile_ry, int32_t zchunk, int32_t tblock_k);
@@ -201,7 +204,10 @@ int fdtd_get_scale(const fdtd_ctx *ctx, int32_t shot, double *scale);
 
 /* Per-kernel timing for measurement: while enabled (eager fdtd_step only;
  * fdtd_step_graph returns FDTD_EUNSUPPORTED), every launch of the kernel
- * classes below is bracketed by HIP events on the context's stream.
+ * classes below is bracketed by HIP events on the context's stream, and the
+ * kernels of a step run one after another (otherwise the interior update
+ * runs on a second stream, concurrently with the psi pass and the band
+ * kernels), so that each duration is the kernel's own.
  * fdtd_get_timing synchronises, returns the mean duration (ms) and count of
  * one class since timing was enabled, and keeps accumulating.
  * Classes: 0 = single-step update of the points outside the layer bands

@@ -75,8 +75,20 @@ static void plan_shot(ShotH &s) {
     s.psi_elems[2] = (size_t)s.SZ * s.PY * s.nx;
     s.nmax = std::max(s.nx, std::max(s.ny, s.nz));
     s.variant = c.variant == FDTD_VARIANT_AUTO ? FDTD_VARIANT_ZMARCH : c.variant;
+    // default z-march plan: tiles of 64 x 16, whole z columns per workgroup when
+    // the xy tiles alone give a workgroup per compute unit (the band kernels
+    // run beside them on the other units), else chunks short enough to reach
+    // that (at least 32 planes)
     s.ry = 2;
-    s.zchunk = 64;
+    {
+        const int Ny = s.ny + (s.gy ? 2 * (s.g - 4) : 0), Nz = s.nz + (s.gz ? 2 * (s.g - 4) : 0);
+        const long nxy = (long)((s.nx + 63) / 64) * ((Ny + 15) / 16);
+        const long want = 256;
+        long nchunk = nxy >= want ? 1 : (want + nxy - 1) / nxy;
+        int zc = (int)((Nz + nchunk - 1) / nchunk);
+        zc = std::max(32, (zc + 15) / 16 * 16);
+        s.zchunk = std::min(zc, 4096);
+    }
     s.tk = c.tblock_k > 1 ? c.tblock_k : 1;
     if (s.variant == FDTD_VARIANT_TBLOCK && s.tk < 2) s.tk = 2;
     // temporal blocking: four level buffers and the box B outside every band
@@ -476,19 +488,21 @@ static hipEvent_t take_event(fdtd_ctx *ctx) {
     }
     return ctx->ev_pool[ctx->ev_used++];
 }
-static hipEvent_t tic(fdtd_ctx *ctx) {
+static hipEvent_t tic(fdtd_ctx *ctx, hipStream_t st) {
     if (!ctx->timing) return nullptr;
     hipEvent_t e = take_event(ctx);
-    if (e) (void)hipEventRecord(e, ctx->stream);
+    if (e) (void)hipEventRecord(e, st);
     return e;
 }
-static void toc(fdtd_ctx *ctx, int cls, hipEvent_t start) {
+static void toc(fdtd_ctx *ctx, int cls, hipEvent_t start, hipStream_t st) {
     if (!ctx->timing || !start) return;
     hipEvent_t e = take_event(ctx);
     if (!e) return;
-    (void)hipEventRecord(e, ctx->stream);
+    (void)hipEventRecord(e, st);
     ctx->ev_pairs[cls].push_back(std::make_pair(start, e));
 }
+static hipEvent_t tic(fdtd_ctx *ctx) { return tic(ctx, ctx->stream); }
+static void toc(fdtd_ctx *ctx, int cls, hipEvent_t start) { toc(ctx, cls, start, ctx->stream); }
 // fold recorded pairs into the sums (synchronises) and recycle the events
 static int drain_timing(fdtd_ctx *ctx) {
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -535,52 +549,76 @@ static Roles plain_roles(const fdtd_ctx *ctx, int ext) {
     return R;
 }
 
-// update launches of one shot or of all shots (shot < 0)
-static void enqueue_update(fdtd_ctx *ctx, int shot, const Roles &R) {
+// psi pre-pass and update of one shot or of all shots (shot < 0).  The
+// z-march of the points outside the bands runs on the side stream, forked
+// from and joined back to the main one, concurrently with the psi pass and
+// the band kernels: the two sets of points are disjoint and both read only
+// u^n (and their own points' second state).  Naive shots update every point
+// after the psi pass, on the main stream.  With per-kernel timing enabled
+// everything stays on the main stream, so that each timed duration is the
+// kernel's own.
+static void enqueue_psi_update(fdtd_ctx *ctx, int shot, const Roles &R, long maxc_psi) {
     const DevShot *dd = (const DevShot *)wsp(ctx, ctx->o_desc);
     int *stepc = (int *)wsp(ctx, ctx->o_stepc);
     const int stor = ctx->storage;
     const int ext = R.ext;
-    int lo = shot < 0 ? 0 : shot, hi = shot < 0 ? (int)ctx->shots.size() : shot + 1;
-    if (shot < 0 && !ctx->groups.empty()) {
-        // every z-march shot, grouped by plan; naive shots below
-        const WorkItem *wa = (const WorkItem *)wsp(ctx, ctx->o_work_all);
-        hipEvent_t t0 = tic(ctx);
-        for (const auto &g : ctx->groups)
-            fdtd_launch_zmarch(stor, dd, wa + g.off, g.nwork, g.ry, R, g.zchunk, stepc, ctx->stream);
-        toc(ctx, 0, t0);
-        t0 = tic(ctx);
-        for (int k = 0; k < 3; ++k)
-            fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, ctx->o_band_all[k]), ctx->nband_all[k], k, R, kBandZ,
-                             stepc, ctx->stream);
-        toc(ctx, 4, t0);
-        for (int i = lo; i < hi; ++i) {
-            const ShotH &s = ctx->shots[i];
-            if (s.variant != FDTD_VARIANT_NAIVE) continue;
-            int Ny = s.ny + (s.gy ? 2 * ext : 0), Nz = s.nz + (s.gz ? 2 * ext : 0);
-            hipEvent_t t1 = tic(ctx);
-            fdtd_launch_naive(stor, dd, i, s.nx, Ny, Nz, R, stepc, ctx->stream);
-            toc(ctx, 0, t1);
+    const int lo = shot < 0 ? 0 : shot, hi = shot < 0 ? (int)ctx->shots.size() : shot + 1;
+    const bool grouped = shot < 0 && !ctx->groups.empty();
+    bool any_zm = false;
+    for (int i = lo; i < hi; ++i) any_zm = any_zm || ctx->shots[i].variant != FDTD_VARIANT_NAIVE;
+    hipStream_t side = ctx->stream;
+    if (any_zm && ctx->side && !ctx->timing) {
+        (void)hipEventRecord(ctx->ev_fork, ctx->stream);
+        (void)hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+        side = ctx->side;
+    }
+    if (any_zm) {
+        hipEvent_t t0 = tic(ctx, side);
+        if (grouped) {
+            const WorkItem *wa = (const WorkItem *)wsp(ctx, ctx->o_work_all);
+            for (const auto &g : ctx->groups)
+                fdtd_launch_zmarch(stor, dd, wa + g.off, g.nwork, g.ry, R, g.zchunk, stepc, side);
+        } else {
+            for (int i = lo; i < hi; ++i) {
+                const ShotH &s = ctx->shots[i];
+                if (s.variant == FDTD_VARIANT_NAIVE) continue;
+                fdtd_launch_zmarch(stor, dd, (const WorkItem *)wsp(ctx, s.o_work), s.nwork, s.ry, R, s.zchunk, stepc,
+                                   side);
+            }
         }
-        return;
+        toc(ctx, 0, t0, side);
+    }
+    hipEvent_t t0 = tic(ctx);
+    fdtd_launch_psi(stor, dd + lo, hi - lo, maxc_psi, R.iu, ext, ctx->stream);
+    toc(ctx, 1, t0);
+    if (any_zm) {
+        t0 = tic(ctx);
+        if (grouped) {
+            for (int k = 0; k < 3; ++k)
+                fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, ctx->o_band_all[k]), ctx->nband_all[k], k, R,
+                                 kBandZ, stepc, ctx->stream);
+        } else {
+            for (int i = lo; i < hi; ++i) {
+                const ShotH &s = ctx->shots[i];
+                if (s.variant == FDTD_VARIANT_NAIVE) continue;
+                for (int k = 0; k < 3; ++k)
+                    fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, s.o_band[k]), s.nband[k], k, R, kBandZ,
+                                     stepc, ctx->stream);
+            }
+        }
+        toc(ctx, 4, t0);
     }
     for (int i = lo; i < hi; ++i) {
         const ShotH &s = ctx->shots[i];
-        hipEvent_t t0 = tic(ctx);
-        if (s.variant == FDTD_VARIANT_NAIVE) {
-            int Ny = s.ny + (s.gy ? 2 * ext : 0), Nz = s.nz + (s.gz ? 2 * ext : 0);
-            fdtd_launch_naive(stor, dd, i, s.nx, Ny, Nz, R, stepc, ctx->stream);
-            toc(ctx, 0, t0);
-        } else {
-            fdtd_launch_zmarch(stor, dd, (const WorkItem *)wsp(ctx, s.o_work), s.nwork, s.ry, R, s.zchunk, stepc,
-                               ctx->stream);
-            toc(ctx, 0, t0);
-            t0 = tic(ctx);
-            for (int k = 0; k < 3; ++k)
-                fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, s.o_band[k]), s.nband[k], k, R, kBandZ, stepc,
-                                 ctx->stream);
-            toc(ctx, 4, t0);
-        }
+        if (s.variant != FDTD_VARIANT_NAIVE) continue;
+        const int Ny = s.ny + (s.gy ? 2 * ext : 0), Nz = s.nz + (s.gz ? 2 * ext : 0);
+        t0 = tic(ctx);
+        fdtd_launch_naive(stor, dd, i, s.nx, Ny, Nz, R, stepc, ctx->stream);
+        toc(ctx, 0, t0);
+    }
+    if (side != ctx->stream) {
+        (void)hipEventRecord(ctx->ev_join, side);
+        (void)hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
     }
 }
 
@@ -604,11 +642,8 @@ static void enqueue_step(fdtd_ctx *ctx, int shot) {
     for (int i = lo; i < hi; ++i)
         for (int d = 0; d < 3; ++d) maxc = std::max(maxc, psi_count(ctx->shots[i], d, ext));
     const Roles R = plain_roles(ctx, ext);
+    enqueue_psi_update(ctx, shot, R, maxc);
     hipEvent_t t0 = tic(ctx);
-    fdtd_launch_psi(ctx->storage, dd + lo, hi - lo, maxc, R.iu, ext, ctx->stream);
-    toc(ctx, 1, t0);
-    enqueue_update(ctx, shot, R);
-    t0 = tic(ctx);
     fdtd_launch_record(ctx->storage, dd + lo, hi - lo, R, (int *)wsp(ctx, ctx->o_stepc), ctx->stream);
     toc(ctx, 2, t0);
     std::swap(ctx->iu, ctx->ium1);
@@ -663,18 +698,7 @@ static void enqueue_tblock(fdtd_ctx *ctx) {
             R.lo[d] = s.blo[d] + 4 * j;
             R.hi[d] = s.bhi[d] - 4 * j;
         }
-        t0 = tic(ctx);
-        fdtd_launch_psi(ctx->storage, dd, 1, maxc, R.iu, 0, ctx->stream);
-        toc(ctx, 1, t0);
-        t0 = tic(ctx);
-        fdtd_launch_zmarch(ctx->storage, dd, (const WorkItem *)wsp(ctx, s.o_work), s.nwork, s.ry, R, s.zchunk, stepc,
-                           ctx->stream);
-        toc(ctx, 0, t0);
-        t0 = tic(ctx);
-        for (int k = 0; k < 3; ++k)
-            fdtd_launch_band(ctx->storage, dd, (const BandItem *)wsp(ctx, s.o_band[k]), s.nband[k], k, R, kBandZ, stepc,
-                             ctx->stream);
-        toc(ctx, 4, t0);
+        enqueue_psi_update(ctx, 0, R, maxc);
         t0 = tic(ctx);
         fdtd_launch_record(ctx->storage, dd, 1, R, stepc, ctx->stream);
         toc(ctx, 2, t0);
@@ -951,6 +975,11 @@ static int zero_state(fdtd_ctx *ctx) {
 
 int fdtd_bind_workspace(fdtd_ctx *ctx, void *dev_ptr, size_t bytes) {
     if (!ctx || !dev_ptr) return FDTD_EINVAL;
+    if (!ctx->side) {
+        HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+        HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    }
     if (bytes < ctx->need) FAIL(ctx, FDTD_ENOMEM, "workspace of %zu bytes, need %zu", bytes, ctx->need);
     if (((uintptr_t)dev_ptr) & 255) FAIL(ctx, FDTD_EINVAL, "workspace must be 256-byte aligned");
     ctx->ws = (char *)dev_ptr;
@@ -1305,7 +1334,8 @@ int fdtd_check_finite(fdtd_ctx *ctx) {
 int fdtd_set_plan(fdtd_ctx *ctx, int32_t shot, int32_t variant, int32_t tile_ry, int32_t zchunk, int32_t tblock_k) {
     if (!ctx || shot < 0 || shot >= (int)ctx->shots.size()) return FDTD_EINVAL;
     if (variant < 1 || variant > 3) FAIL(ctx, FDTD_EINVAL, "variant must be naive, z-march or temporal blocking");
-    if (tile_ry != 1 && tile_ry != 2 && tile_ry != 4) FAIL(ctx, FDTD_EINVAL, "tile rows per thread must be 1, 2 or 4");
+    if (tile_ry != 1 && tile_ry != 2 && tile_ry != 4 && tile_ry != 8)
+        FAIL(ctx, FDTD_EINVAL, "tile size must be 1, 2, 4 or 8 (64 x 8 tile_ry points)");
     if (zchunk < 16 || zchunk > 4096) FAIL(ctx, FDTD_EINVAL, "z chunk must be in [16, 4096]");
     if (variant == FDTD_VARIANT_TBLOCK && tblock_k != 2 && tblock_k != 4) FAIL(ctx, FDTD_EINVAL, "tblock_k must be 2 or 4");
     ShotH &s = ctx->shots[shot];
@@ -1340,6 +1370,9 @@ void fdtd_destroy(fdtd_ctx *ctx) {
     fdtd_clear_graphs(ctx);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     delete ctx;
 }
 

@@ -68,6 +68,8 @@ struct fdtd_ctx {
     std::vector<DevShot> hdesc;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
+    hipStream_t side = nullptr;         // second stream: interior update concurrent with psi + band
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0, need = 0;
     size_t o_stepc = 0, o_scratch = 0, o_desc = 0, o_work_all = 0, o_band_all[3] = {0, 0, 0};

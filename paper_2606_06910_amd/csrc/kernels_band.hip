@@ -128,53 +128,65 @@ __global__ __launch_bounds__(256) void k_band(const DevShot *__restrict__ shots,
         for (int o = 0; o < 8; ++o) pq[o] = psi_z_at(za - 4 + o);
     }
 
-#pragma unroll 1
-    for (int z = za; z < zb; ++z) {
+    // loads of one plane (issued a plane ahead of their use)
+    struct PL {
+        float xl[4], xh[4], yl[4], yh[4];
+        float qn, second, mm;         // u^n four planes ahead, second state, m
+        float px[8], zx, py[8], zy;   // psi_x / psi_y neighbours, zeta_x / zeta_y
+        float pqn, zz;                // psi_z four planes ahead, zeta_z
+    };
+    auto load = [&](int z, PL &p) {
         const uint32_t pz = (uint32_t)(z - za + 4) * Sb;
-        q[8] = Buf<T>::ld(ru, vc, pz + 4 * Sb);
-        float xl[4], xh[4], yl[4], yh[4], zl[4], zh[4];
+        p.qn = Buf<T>::ld(ru, vc, pz + 4 * Sb);
 #pragma unroll
         for (int l = 1; l <= 4; ++l) {
-            xl[l - 1] = Buf<T>::ld(ru, vc - (uint32_t)(l * esz), pz);
-            xh[l - 1] = Buf<T>::ld(ru, vc + (uint32_t)(l * esz), pz);
-            yl[l - 1] = Buf<T>::ld(ru, vc - (uint32_t)l * Pb, pz);
-            yh[l - 1] = Buf<T>::ld(ru, vc + (uint32_t)l * Pb, pz);
+            p.xl[l - 1] = Buf<T>::ld(ru, vc - (uint32_t)(l * esz), pz);
+            p.xh[l - 1] = Buf<T>::ld(ru, vc + (uint32_t)(l * esz), pz);
+            p.yl[l - 1] = Buf<T>::ld(ru, vc - (uint32_t)l * Pb, pz);
+            p.yh[l - 1] = Buf<T>::ld(ru, vc + (uint32_t)l * Pb, pz);
+        }
+        p.second = Buf<T>::ld(rs, vc, pz);
+        p.mm = Buf<float>::ld(rm, vcm, (uint32_t)(z - za + 4) * Smb);
+        // (a neighbour outside the slabs reads the zero slot of its row)
+        if (AX.band) {
+            const uint32_t sox = (uint32_t)(z + fz) * Spx;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) p.px[j] = Buf<float>::ld(rpx, px_off[j], sox);
+            if (AX.slab) p.zx = Buf<float>::ld(rpx, zx_off, sox + zdx);
+        }
+        if constexpr (HAS_Y) {
+            if (AY.band) {
+                const uint32_t soy = (uint32_t)(z + fz) * Spy;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) p.py[j] = Buf<float>::ld(rpy, py_off[j], soy);
+                if (AY.slab) p.zy = Buf<float>::ld(rpy, zy_off, soy + zdy);
+            }
+        }
+        if constexpr (HAS_Z) {
+            p.pqn = psi_z_at(z + 4);
+            if (in_slab(z, nz, zlo, zhi))
+                p.zz = Buf<float>::ld(rpz, vz_col, (uint32_t)slab_pos(z, nz, zlo, zhi) * Spz + zdz);
+        }
+    };
+    auto compute = [&](int z, const PL &p) {
+        q[8] = p.qn;
+        float zl[4], zh[4];
+#pragma unroll
+        for (int l = 1; l <= 4; ++l) {
             zl[l - 1] = q[4 - l];
             zh[l - 1] = q[4 + l];
         }
         const float c = q[4];
-        const float second = Buf<T>::ld(rs, vc, pz);
-        const float mm = Buf<float>::ld(rm, vcm, (uint32_t)(z - za + 4) * Smb);
-        // psi neighbours and zeta of every band axis
         float pl[3][4], ph[3][4], zo[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-            for (int l = 0; l < 4; ++l) pl[d][l] = ph[d][l] = 0.0f;
-        // (a neighbour outside the slabs reads the zero slot of its row)
-        const uint32_t sox = (uint32_t)(z + fz) * Spx;
-        if (AX.band) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float v = Buf<float>::ld(rpx, px_off[j], sox);
-                if (j < 4) pl[0][j] = v;
-                else ph[0][j - 4] = v;
-            }
-            if (AX.slab) zo[0] = Buf<float>::ld(rpx, zx_off, sox + zdx);
+        for (int l = 0; l < 4; ++l) {
+            pl[0][l] = p.px[l];
+            ph[0][l] = p.px[4 + l];
+            pl[1][l] = p.py[l];
+            ph[1][l] = p.py[4 + l];
         }
-        uint32_t soy = 0;
-        if constexpr (HAS_Y) {
-            soy = (uint32_t)(z + fz) * Spy;
-            if (AY.band) {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const float v = Buf<float>::ld(rpy, py_off[j], soy);
-                    if (j < 4) pl[1][j] = v;
-                    else ph[1][j - 4] = v;
-                }
-                if (AY.slab) zo[1] = Buf<float>::ld(rpy, zy_off, soy + zdy);
-            }
-        }
+        zo[0] = p.zx;
+        zo[1] = p.zy;
         // layer data of plane z (uniform; every plane of a kind-0 box is in the z band)
         AxisPt AZ;
         AZ.band = 0;
@@ -182,6 +194,7 @@ __global__ __launch_bounds__(256) void k_band(const DevShot *__restrict__ shots,
         AZ.pos = 0;
         AZ.b = AZ.a = AZ.kinv = AZ.dkinv = 0.0f;
         if constexpr (HAS_Z) {
+            pq[8] = p.pqn;
             AZ.band = in_band(z, nz, zlo, zhi);
             AZ.slab = AZ.band && in_slab(z, nz, zlo, zhi);
             AZ.pos = AZ.slab ? slab_pos(z, nz, zlo, zhi) : 0;
@@ -196,17 +209,16 @@ __global__ __launch_bounds__(256) void k_band(const DevShot *__restrict__ shots,
                 AZ.dkinv = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
                                                          __builtin_bit_cast(int, Buf<float>::ld(rpr, 0, pr + 3 * pn))));
             }
-            pq[8] = psi_z_at(z + 4);
 #pragma unroll
             for (int l = 1; l <= 4; ++l) {
                 pl[2][l - 1] = pq[4 - l];
                 ph[2][l - 1] = pq[4 + l];
             }
-            if (AZ.slab) zo[2] = Buf<float>::ld(rpz, vz_col, (uint32_t)AZ.pos * Spz + zdz);
+            zo[2] = p.zz;
         }
         // arithmetic of lap_point (every point here lies in a band)
-        const float *lo[3] = {xl, yl, zl};
-        const float *hi[3] = {xh, yh, zh};
+        const float *lo[3] = {p.xl, p.yl, zl};
+        const float *hi[3] = {p.xh, p.yh, zh};
         const AxisPt *A3[3] = {&AX, &AY, &AZ};
         const bool bnd[3] = {(bool)AX.band, HAS_Y && AY.band, HAS_Z && AZ.band};
         const bool slb[3] = {(bool)AX.slab, HAS_Y && AY.slab, HAS_Z && AZ.slab};
@@ -224,13 +236,14 @@ __global__ __launch_bounds__(256) void k_band(const DevShot *__restrict__ shots,
         }
         const float lt = (L[0] + L[1]) + L[2];
         const bool src = src_col && wrap_ghost(s, 2, z) == s.sz;
-        const Upd up = time_update<T>(mm, lt, c, second, src, srcamp);
+        const Upd up = time_update<T>(p.mm, lt, c, p.second, src, srcamp);
         if (!in_box(R, x, y, z)) {
+            const uint32_t pz = (uint32_t)(z - za + 4) * Sb;
             Buf<T>::st(rw, vc, pz, up.u);
             if constexpr (IsInc<T>::v) Buf<T>::st(rs, vc, pz, up.d);
-            if (slb[0]) Buf<float>::st(rpx, zx_off, sox + zdx, zn[0]);
+            if (slb[0]) Buf<float>::st(rpx, zx_off, (uint32_t)(z + fz) * Spx + zdx, zn[0]);
             if constexpr (HAS_Y)
-                if (slb[1]) Buf<float>::st(rpy, zy_off, soy + zdy, zn[1]);
+                if (slb[1]) Buf<float>::st(rpy, zy_off, (uint32_t)(z + fz) * Spy + zdy, zn[1]);
             if constexpr (HAS_Z)
                 if (slb[2]) Buf<float>::st(rpz, vz_col, (uint32_t)AZ.pos * Spz + zdz, zn[2]);
         }
@@ -240,6 +253,19 @@ __global__ __launch_bounds__(256) void k_band(const DevShot *__restrict__ shots,
 #pragma unroll
             for (int o = 0; o < 8; ++o) pq[o] = pq[o + 1];
         }
+    };
+
+    // two plane buffers in alternation: the loads of plane z + 1 are in flight
+    // while plane z is computed and stored
+    PL A, B;
+    load(za, A);
+#pragma unroll 1
+    for (int z = za; z < zb; z += 2) {
+        if (z + 1 < zb) load(z + 1, B);
+        compute(z, A);
+        if (z + 1 >= zb) break;
+        if (z + 2 < zb) load(z + 2, A);
+        compute(z + 1, B);
     }
 }
 

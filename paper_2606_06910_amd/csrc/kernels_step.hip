@@ -33,53 +33,50 @@ __device__ __forceinline__ Box shot_box(const DevShot &s, int ext) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_psi(const DevShot *__restrict__ shots, int iu, int ext) {
+    typedef __attribute__((address_space(1))) const T gT;
+    typedef __attribute__((address_space(1))) float gf;
     const DevShot &s = shots[blockIdx.z];
     const int d = blockIdx.y;
     const int lo = s.Llo[d], hi = s.Lhi[d];
     if (lo + hi == 0) return;
-    Box bx = shot_box(s, ext);
-    const int Ny = bx.yhi - bx.ylo, Nz = bx.zhi - bx.zlo;
-    long count;
-    if (d == 0) count = (long)s.LX * Ny * Nz;
-    else if (d == 1) count = (long)s.nx * s.LY * Nz;
-    else count = (long)s.nx * Ny * s.LZ;
-    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count) return;
+    const Box bx = shot_box(s, ext);
+    const unsigned Ny = bx.yhi - bx.ylo, Nz = bx.zhi - bx.zlo;
+    // slab points as (a fastest, b, c): x-slab (is, y, z), y-slab (x, js, z), z-slab (x, y, ks)
+    const unsigned W = d == 0 ? (unsigned)s.LX : (unsigned)s.nx;
+    const unsigned M = d == 1 ? (unsigned)s.LY : Ny;
+    const unsigned N = d == 2 ? (unsigned)s.LZ : Nz;
+    const unsigned t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= W * M * N) return;
+    const unsigned r = t / W, a = t - r * W;
+    const unsigned c = r / M, b = r - c * M;
     int x, y, z, k;
     if (d == 0) {
-        int is = (int)(t % s.LX);
-        long r = t / s.LX;
-        y = bx.ylo + (int)(r % Ny);
-        z = bx.zlo + (int)(r / Ny);
-        x = is < lo ? is : s.nx - hi + (is - lo);
+        x = (int)a < lo ? (int)a : s.nx - hi + ((int)a - lo);
+        y = bx.ylo + (int)b;
+        z = bx.zlo + (int)c;
         k = x;
     } else if (d == 1) {
-        x = (int)(t % s.nx);
-        long r = t / s.nx;
-        int js = (int)(r % s.LY);
-        z = bx.zlo + (int)(r / s.LY);
-        y = js < lo ? js : s.ny - hi + (js - lo);
+        x = (int)a;
+        y = (int)b < lo ? (int)b : s.ny - hi + ((int)b - lo);
+        z = bx.zlo + (int)c;
         k = y;
     } else {
-        x = (int)(t % s.nx);
-        long r = t / s.nx;
-        y = bx.ylo + (int)(r % Ny);
-        int ks = (int)(r / Ny);
-        z = ks < lo ? ks : s.nz - hi + (ks - lo);
+        x = (int)a;
+        y = bx.ylo + (int)b;
+        z = (int)c < lo ? (int)c : s.nz - hi + ((int)c - lo);
         k = z;
     }
-    const T *u = (const T *)s.u[iu];
-    const long c = (long)z * s.S + (long)y * s.P + x;
+    gT *u = (gT *)s.u[iu] + ((long)z * s.S + (long)y * s.P + x);
     const long stride = d == 0 ? 1 : (d == 1 ? s.P : s.S);
     float fl[4], fh[4];
 #pragma unroll
     for (int l = 1; l <= 4; ++l) {
-        fl[l - 1] = Store<T>::ld(u + c - l * stride);
-        fh[l - 1] = Store<T>::ld(u + c + l * stride);
+        fl[l - 1] = (float)u[-l * stride];
+        fh[l - 1] = (float)u[l * stride];
     }
-    float d1 = d1_axis(s.w1[d], fl, fh);
-    float *p = &s.psi[d][psi_index(s, d, x, y, z)];
-    *p = psi_update(prof_at(s, d, 0, k), *p, prof_at(s, d, 1, k), d1);
+    const float d1 = d1_axis(s.w1[d], fl, fh);
+    gf *pp = (gf *)s.psi[d] + psi_index(s, d, x, y, z);
+    *pp = psi_update(prof_at(s, d, 0, k), *pp, prof_at(s, d, 1, k), d1);
 }
 
 // ---------------------------------------------------------------------------
@@ -101,7 +98,7 @@ __global__ __launch_bounds__(256) void k_update_naive(const DevShot *__restrict_
 // ---------------------------------------------------------------------------
 // z-marching update of the points outside the layer bands.
 //
-// A 256-thread workgroup owns an xy tile of 64 x TY points (TY = 4 RY) and a
+// A workgroup of NW waves owns an xy tile of 64 x TY points (TY = NW RY) and a
 // z chunk.  Lane l of wave w owns column x0 + l, rows w RY .. w RY + RY - 1.
 // Per thread, a register queue of u^n planes along z (the queue index is a
 // compile-time phase, so the queue never moves between registers); the
@@ -113,16 +110,17 @@ __global__ __launch_bounds__(256) void k_update_naive(const DevShot *__restrict_
 // are a uniform plane base plus a loop-invariant 32-bit offset per lane.
 // ---------------------------------------------------------------------------
 constexpr int ZQ = 11;   // queue planes: 9 of the stencil + 2 in flight
-template <int RY> struct ZM {
-    static constexpr int TY = 4 * RY;                      // tile rows
+template <int NW, int RY> struct ZM {
+    static constexpr int NT = 64 * NW;                     // threads
+    static constexpr int TY = NW * RY;                     // tile rows
     static constexpr int LW = 64 + 2 * FDTD_R;             // LDS row length
     static constexpr int LH = TY + 2 * FDTD_R;             // LDS rows
     static constexpr int LB = LH * LW + 4;                 // one LDS buffer (+ a dummy slot)
     static constexpr int NH = 2 * FDTD_R * TY + 2 * FDTD_R * 64;   // halo values per plane
-    static constexpr int HS = (NH + 255) / 256;            // halo values per thread
+    static constexpr int HS = (NH + NT - 1) / NT;          // halo values per thread
 };
 
-template <typename T, int RY> struct ZCtx {
+template <typename T, int NW, int RY> struct ZCtx {
     Coef K;
     // byte bases such that element (x, y, z) of a field is at base + z * Sb + off(x, y)
     const char *u, *m;
@@ -130,10 +128,10 @@ template <typename T, int RY> struct ZCtx {
     uint32_t Sb, Smb;    // plane strides in bytes: field, m
     Rsrc ru, rm, rw, rs; // descriptors based at the current round's first plane
     uint32_t off[RY], offm[RY];   // own rows: field and m byte offsets within a plane
-    uint32_t hoff[ZM<RY>::HS];    // halo byte offsets (a lane without a halo value reads its own point)
-    int hslot[ZM<RY>::HS];        // halo LDS index (the dummy slot for a lane without one)
-    float hc[ZM<RY>::HS], umc[RY], mc[RY];   // halo, second state and m of plane z
-    float h1[ZM<RY>::HS], um1[RY], m1[RY];   // the same of plane z + 1
+    uint32_t hoff[ZM<NW, RY>::HS];    // halo byte offsets (a lane without a halo value reads its own point)
+    int hslot[ZM<NW, RY>::HS];        // halo LDS index (the dummy slot for a lane without one)
+    float hc[ZM<NW, RY>::HS], umc[RY], mc[RY];   // halo, second state and m of plane z
+    float h1[ZM<NW, RY>::HS], um1[RY], m1[RY];   // the same of plane z + 1
     const Roles *R;
     int x, y0, lane, r0; // column, tile origin row, lane, first own row (tile-local)
     int nlo[3], nhi[3];  // box of points outside every band
@@ -145,9 +143,9 @@ template <typename T, int RY> struct ZCtx {
 };
 
 // plane z = z0 + PH of a round that started at plane z0 (descriptors based at z0)
-template <typename T, int RY, int PH>
-__device__ __forceinline__ void zbody(ZCtx<T, RY> &C, const DevShot &s, float (&q)[ZQ][RY], float *L, int z) {
-    using G = ZM<RY>;
+template <typename T, int NW, int RY, int PH>
+__device__ __forceinline__ void zbody(ZCtx<T, NW, RY> &C, const DevShot &s, float (&q)[ZQ][RY], float *L, int z) {
+    using G = ZM<NW, RY>;
     auto slot = [](int o) { return (PH + 4 + o + ZQ) % ZQ; };
     // loads two planes ahead of their use: u^n plane z + 6, the rest plane z + 2
     float hn[G::HS], umn[RY], mn[RY];
@@ -210,16 +208,16 @@ __device__ __forceinline__ void zbody(ZCtx<T, RY> &C, const DevShot &s, float (&
     }
 }
 
-template <typename T, int RY>
-__global__ __launch_bounds__(256) void k_zmarch(const DevShot *__restrict__ shots, const WorkItem *__restrict__ work,
-                                               Roles R, int zchunk, const int *__restrict__ stepc) {
-    using G = ZM<RY>;
+template <typename T, int NW, int RY>
+__global__ __launch_bounds__(64 * NW) void k_zmarch(const DevShot *__restrict__ shots, const WorkItem *__restrict__ work,
+                                                    Roles R, int zchunk, const int *__restrict__ stepc) {
+    using G = ZM<NW, RY>;
     __shared__ float sm[2 * G::LB];
     const WorkItem wi = work[blockIdx.x];
     const DevShot &s = shots[wi.shot];
     const int ext = R.ext;
     const Box bx = shot_box(s, ext);
-    ZCtx<T, RY> C;
+    ZCtx<T, NW, RY> C;
     const int x0 = wi.tx * 64;
     C.y0 = bx.ylo + wi.ty * G::TY;
     if (C.y0 >= bx.yhi) return;
@@ -292,7 +290,7 @@ __global__ __launch_bounds__(256) void k_zmarch(const DevShot *__restrict__ shot
     // right), then 8 rows of 64 (4 above, 4 below the tile)
 #pragma unroll
     for (int k = 0; k < G::HS; ++k) {
-        const int i = threadIdx.x + 256 * k;
+        const int i = threadIdx.x + G::NT * k;
         C.hslot[k] = G::LH * G::LW;     // dummy
         C.hoff[k] = C.off[0];
         if (i < 2 * FDTD_R * G::TY) {
@@ -346,7 +344,7 @@ __global__ __launch_bounds__(256) void k_zmarch(const DevShot *__restrict__ shot
             const int n = b - z0;
 #define ZSTEP(PH)                                                                 \
     if (n > PH) {                                                                 \
-        zbody<T, RY, PH>(C, s, q, sm + (it & 1) * G::LB, z0 + PH);                \
+        zbody<T, NW, RY, PH>(C, s, q, sm + (it & 1) * G::LB, z0 + PH);            \
         ++it;                                                                     \
     }
             ZSTEP(0) ZSTEP(1) ZSTEP(2) ZSTEP(3) ZSTEP(4) ZSTEP(5)
@@ -397,16 +395,20 @@ template <typename T>
 static void launch_zmarch_t(const DevShot *d_shots, const WorkItem *work, int nwork, int ry, const Roles &R,
                             int zchunk, const int *stepc, hipStream_t st) {
     if (nwork <= 0) return;
-    // plan rows ry = 1, 2, 4: tiles of 64 x 8 ry points (2 ry rows per thread)
+    // plan rows ry = 1, 2, 4, 8: tiles of 64 x 8 ry points; (waves, rows per thread)
+    // = (4, 2), (4, 4), (8, 4), (16, 4)
     switch (ry) {
     case 1:
-        hipLaunchKernelGGL((k_zmarch<T, 2>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
+        hipLaunchKernelGGL((k_zmarch<T, 4, 2>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
         break;
     case 4:
-        hipLaunchKernelGGL((k_zmarch<T, 8>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
+        hipLaunchKernelGGL((k_zmarch<T, 8, 4>), dim3(nwork), dim3(512), 0, st, d_shots, work, R, zchunk, stepc);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_zmarch<T, 16, 4>), dim3(nwork), dim3(1024), 0, st, d_shots, work, R, zchunk, stepc);
         break;
     default:
-        hipLaunchKernelGGL((k_zmarch<T, 4>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
+        hipLaunchKernelGGL((k_zmarch<T, 4, 4>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
         break;
     }
 }

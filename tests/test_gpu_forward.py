@@ -89,7 +89,7 @@ def test_cases_match_oracle_and_variants_agree(name):
     assert np.array_equal(z[0], n[0]) and np.array_equal(z[1], n[1]) and np.array_equal(z[2], n[2])
 
 
-@pytest.mark.parametrize("ry,zc", [(1, 16), (2, 32), (4, 64), (1, 128), (4, 16), (2, 4096)])
+@pytest.mark.parametrize("ry,zc", [(1, 16), (2, 32), (4, 64), (1, 128), (4, 16), (2, 4096), (8, 32), (8, 4096)])
 def test_zmarch_plans_bitwise_equal_naive(ry, zc):
     """Every tile height / z-chunk plan gives the naive kernel's bits (several
     x/y tiles with ragged tails, several z chunks, source inside a layer)."""
