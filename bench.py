@@ -68,7 +68,10 @@ def step_bytes(n, cpml, field_bytes=4):
     return (3 * field_bytes + 4) * N + 16 * slab_points(n, cpml)
 
 
-def time_gpu(w, K, W, variant, storage=0, graph=True, tblock_k=1):
+KERNEL_CLASSES = ("update", "psi", "record", "exchange", "band", "tblock")
+
+
+def make_propagator(w, K, W, variant, storage=0, tblock_k=1):
     import numpy as np
     import torch
 
@@ -79,6 +82,32 @@ def time_gpu(w, K, W, variant, storage=0, graph=True, tblock_k=1):
     p.inject_source(0, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)).cuda())
     p.set_receivers(0, w.rec)
     p.record(0, K + W + 2)
+    return p
+
+
+def kernel_timing(w, K, W, variant=0):
+    """Per-kernel mean durations (ms, count) from an eager pass of K steps with
+    HIP events around every launch on the stream it runs on; the library runs
+    the kernels of a step one after another while timing is on."""
+    import torch
+
+    p = make_propagator(w, K, W, variant)
+    p.set_timing(True)     # warm-up launches run like the timed ones
+    p.step(W)
+    torch.cuda.synchronize()
+    p.set_timing(True)     # clears the counters
+    p.step(K)
+    tm = {name: p.timing(c) for c, name in enumerate(KERNEL_CLASSES)}
+    p.set_timing(False)
+    plan = p.plan(0)
+    p.close()
+    return tm, plan
+
+
+def time_gpu(w, K, W, variant, storage=0, graph=True, tblock_k=1):
+    import torch
+
+    p = make_propagator(w, K, W, variant, storage, tblock_k)
     W += (-W) % 4
     if graph:
         p.step(K, graph=True)            # capture once (phase 0), untimed
@@ -94,14 +123,46 @@ def time_gpu(w, K, W, variant, storage=0, graph=True, tblock_k=1):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     p.check_finite()
-    # per-kernel timing pass (eager; HIP events around every launch on the library's stream)
-    Kt = min(K, 200)
-    p.set_timing(True)
-    p.step(Kt)
-    tm = {name: p.timing(c) for c, name in enumerate(("update", "psi", "record", "exchange", "band", "tblock"))}
-    p.set_timing(False)
     p.close()
-    return ms, tm
+    return ms
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "zmarch_layered512_counters.txt")
+ZMARCH_SOURCES = ("paper_2606_06910_amd/csrc/kernels_step.hip", "paper_2606_06910_amd/csrc/fdtd_dev.hpp")
+
+
+def sources_digest():
+    """sha256 over the z-march kernel's source files (identifies the kernel the counters were taken on)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ZMARCH_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n, plan):
+    """HBM bytes per z-march launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE KiB per dispatch times their copy-kernel
+    calibration factors), or None when that summary is missing or was taken on
+    other kernel sources, another grid or another plan."""
+    try:
+        kv = {}
+        with open(COUNTERS) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("sources_sha256") != sources_digest():
+            return None
+        if kv.get("grid") != "%dx%dx%d" % tuple(n) or kv.get("tile_ry") != str(plan[1]):
+            return None
+        fetch = float(kv["fetch_kib_per_launch"]) * 1024 * float(kv["fetch_factor"])
+        write = float(kv["write_kib_per_launch"]) * 1024 * float(kv["write_factor"])
+        return int(round(fetch + write))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def precision_leg(K=200):
@@ -248,6 +309,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage and batched-shot legs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration run)")
+    ap.add_argument("--kernel-timing", action="store_true",
+                    help="only run the per-kernel timing pass (the launches a profiler summary is taken over)")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -273,7 +336,14 @@ def main():
     n = (args.n, args.n, args.n)
     w = synth.layered(n_xyz=n, nt=K + W + 2)
     print("bench: layered %s, %d+%d steps" % (str(n), W, K), file=sys.stderr, flush=True)
-    ms, tm = time_gpu(w, K, W, args.variant, graph=not args.eager)
+    Kt = min(K, 200)
+    if args.kernel_timing:
+        tm, plan = kernel_timing(w, Kt, W, args.variant)
+        print(json.dumps({"kernel_ms": {k: round(v[0], 5) for k, v in tm.items() if v[1] > 0},
+                          "launches": {k: v[1] for k, v in tm.items() if v[1] > 0}, "plan": plan}), flush=True)
+        return
+    ms = time_gpu(w, K, W, args.variant, graph=not args.eager)
+    tm, plan = kernel_timing(w, Kt, W, args.variant)
     N = w.npts
     value = N * K / (ms / 1e3) / 1e6
     upd = tm["update"]
@@ -300,7 +370,7 @@ def main():
         "config": {"workload": "layered %dx%dx%d, 20-cell CPML on 6 faces, Ricker 10 Hz, FP32 fields" % n,
                    "grid": list(n), "cpml": 20, "variant": args.variant, "graph": not args.eager},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(w.n, plan),
                      "kernel": "k_zmarch<float, RY> (update of the points outside the layer bands)",
                      "kernel_ms": round(upd[0], 5), "algorithmic_bytes_per_launch": upd_bytes},
         "step_algorithmic_gbs": round(step_bytes(w.n, w.cpml) / (ms / K / 1e3) / 1e9, 1),
@@ -312,7 +382,7 @@ def main():
         Kc = min(K, 200)
         for name, vv, kk in (("naive", 1, 1), ("zmarch", 2, 1), ("tblock2", 3, 2), ("tblock4", 3, 4)):
             print("bench: compare %s" % name, file=sys.stderr, flush=True)
-            m2, _ = time_gpu(w, Kc, W, vv, graph=not args.eager, tblock_k=kk)
+            m2 = time_gpu(w, Kc, W, vv, graph=not args.eager, tblock_k=kk)
             var[name] = round(N * Kc / (m2 / 1e3) / 1e6, 1)
         out["variants_mpts"] = var
     if not args.no_extra:
