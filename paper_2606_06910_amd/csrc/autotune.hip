@@ -54,7 +54,7 @@ std::map<std::string, Plan> read_cache(const char *path) {
             size_t q1 = q0 == std::string::npos ? q0 : obj.find('"', q0 + 1);
             if (q0 != std::string::npos && q1 != std::string::npos) {
                 Plan p{(int)num(obj, "ry", 2), (int)num(obj, "zchunk", 64), (int)num(obj, "tk", 1), num(obj, "ms", 0)};
-                if ((p.ry == 1 || p.ry == 2 || p.ry == 4) && p.zchunk >= 16 && p.zchunk <= 512)
+                if ((p.ry == 1 || p.ry == 2 || p.ry == 4 || p.ry == 8) && p.zchunk >= 16 && p.zchunk <= 4096)
                     out[obj.substr(q0 + 1, q1 - q0 - 1)] = p;
             }
         }
@@ -90,8 +90,9 @@ extern "C" int fdtd_autotune(fdtd_ctx *ctx, const char *cache_path) {
         ctx->err = "hipEventCreate failed";
         return FDTD_EHIP;
     }
-    const int ry_c[3] = {1, 2, 4};
-    const int zc_c[3] = {32, 64, 128};
+    // candidates: the default plan, then tile sizes x z-chunk lengths (4096: whole columns)
+    const int ry_c[4] = {1, 2, 4, 8};
+    const int zc_c[4] = {32, 64, 128, 4096};
     for (size_t i = 0; i < ctx->shots.size(); ++i) {
         ShotH &s = ctx->shots[i];
         if (s.variant == FDTD_VARIANT_NAIVE) continue;
@@ -103,10 +104,11 @@ extern "C" int fdtd_autotune(fdtd_ctx *ctx, const char *cache_path) {
             continue;
         }
         Plan best{s.ry, s.zchunk, 1, 1e30};
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) {
-                s.ry = ry_c[a];
-                s.zchunk = zc_c[b];
+        const int ry0 = s.ry, zc0 = s.zchunk;
+        for (int c = -1; c < 16; ++c) {
+            s.ry = c < 0 ? ry0 : ry_c[c / 4];
+            s.zchunk = c < 0 ? zc0 : zc_c[c % 4];
+            {
                 rc = fdtd_rewrite_work(ctx);
                 if (rc) return rc;
                 for (int k = 0; k < 2; ++k) fdtd_enqueue_step_shot(ctx, (int)i);
@@ -121,8 +123,9 @@ extern "C" int fdtd_autotune(fdtd_ctx *ctx, const char *cache_path) {
                 float ms = 0;
                 (void)hipEventElapsedTime(&ms, e0, e1);
                 double per = ms / reps;
-                if (per < best.ms) best = Plan{ry_c[a], zc_c[b], 1, per};
+                if (per < best.ms) best = Plan{s.ry, s.zchunk, 1, per};
             }
+        }
         s.ry = best.ry;
         s.zchunk = best.zchunk;
         cache[key] = best;
