@@ -75,15 +75,15 @@ static void plan_shot(ShotH &s) {
     s.psi_elems[2] = (size_t)s.SZ * s.PY * s.nx;
     s.nmax = std::max(s.nx, std::max(s.ny, s.nz));
     s.variant = c.variant == FDTD_VARIANT_AUTO ? FDTD_VARIANT_ZMARCH : c.variant;
-    // default z-march plan: tiles of 64 x 16, whole z columns per workgroup when
-    // the xy tiles alone give a workgroup per compute unit (the band kernels
-    // run beside them on the other units), else chunks short enough to reach
-    // that (at least 32 planes)
-    s.ry = 2;
+    // default z-march plan: tiles of 64 x 32 (8 waves), whole z columns per
+    // workgroup when the xy tiles alone give a workgroup per two compute units
+    // (the psi and band kernels run beside them), else chunks short enough to
+    // reach that (at least 32 planes)
+    s.ry = 4;
     {
         const int Ny = s.ny + (s.gy ? 2 * (s.g - 4) : 0), Nz = s.nz + (s.gz ? 2 * (s.g - 4) : 0);
-        const long nxy = (long)((s.nx + 63) / 64) * ((Ny + 15) / 16);
-        const long want = 256;
+        const long nxy = (long)((s.nx + 63) / 64) * ((Ny + 31) / 32);
+        const long want = 128;
         long nchunk = nxy >= want ? 1 : (want + nxy - 1) / nxy;
         int zc = (int)((Nz + nchunk - 1) / nchunk);
         zc = std::max(32, (zc + 15) / 16 * 16);
@@ -553,10 +553,12 @@ static Roles plain_roles(const fdtd_ctx *ctx, int ext) {
 // z-march of the points outside the bands runs on the side stream, forked
 // from and joined back to the main one, concurrently with the psi pass and
 // the band kernels: the two sets of points are disjoint and both read only
-// u^n (and their own points' second state).  Naive shots update every point
-// after the psi pass, on the main stream.  With per-kernel timing enabled
-// everything stays on the main stream, so that each timed duration is the
-// kernel's own.
+// u^n (and their own points' second state).  After the psi pass the three
+// band kinds (z, y and x slabs: disjoint boxes, reading u^n and psi) run
+// concurrently too, kinds 1 and 2 on streams of their own.  Naive shots
+// update every point after the psi pass, on the main stream.  With
+// per-kernel timing enabled everything stays on the main stream, so that
+// each timed duration is the kernel's own.
 static void enqueue_psi_update(fdtd_ctx *ctx, int shot, const Roles &R, long maxc_psi) {
     const DevShot *dd = (const DevShot *)wsp(ctx, ctx->o_desc);
     int *stepc = (int *)wsp(ctx, ctx->o_stepc);
@@ -592,21 +594,35 @@ static void enqueue_psi_update(fdtd_ctx *ctx, int shot, const Roles &R, long max
     fdtd_launch_psi(stor, dd + lo, hi - lo, maxc_psi, R.iu, ext, ctx->stream);
     toc(ctx, 1, t0);
     if (any_zm) {
+        // the stream of each band kind: the main one for kind 0, its own for kinds 1 and 2
+        hipStream_t bst[3] = {ctx->stream, ctx->stream, ctx->stream};
+        if (side != ctx->stream && ctx->bside[0]) {
+            (void)hipEventRecord(ctx->ev_psi, ctx->stream);
+            for (int k = 1; k < 3; ++k) {
+                (void)hipStreamWaitEvent(ctx->bside[k - 1], ctx->ev_psi, 0);
+                bst[k] = ctx->bside[k - 1];
+            }
+        }
         t0 = tic(ctx);
-        if (grouped) {
-            for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 3; ++k) {
+            if (grouped) {
                 fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, ctx->o_band_all[k]), ctx->nband_all[k], k, R,
-                                 kBandZ, stepc, ctx->stream);
-        } else {
-            for (int i = lo; i < hi; ++i) {
-                const ShotH &s = ctx->shots[i];
-                if (s.variant == FDTD_VARIANT_NAIVE) continue;
-                for (int k = 0; k < 3; ++k)
+                                 kBandZ, stepc, bst[k]);
+            } else {
+                for (int i = lo; i < hi; ++i) {
+                    const ShotH &s = ctx->shots[i];
+                    if (s.variant == FDTD_VARIANT_NAIVE) continue;
                     fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, s.o_band[k]), s.nband[k], k, R, kBandZ,
-                                     stepc, ctx->stream);
+                                     stepc, bst[k]);
+                }
             }
         }
         toc(ctx, 4, t0);
+        for (int k = 1; k < 3; ++k)
+            if (bst[k] != ctx->stream) {
+                (void)hipEventRecord(ctx->ev_bjoin[k - 1], bst[k]);
+                (void)hipStreamWaitEvent(ctx->stream, ctx->ev_bjoin[k - 1], 0);
+            }
     }
     for (int i = lo; i < hi; ++i) {
         const ShotH &s = ctx->shots[i];
@@ -979,6 +995,11 @@ int fdtd_bind_workspace(fdtd_ctx *ctx, void *dev_ptr, size_t bytes) {
         HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
         HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
         HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+        HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_psi, hipEventDisableTiming));
+        for (int k = 0; k < 2; ++k) {
+            HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->bside[k], hipStreamNonBlocking));
+            HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_bjoin[k], hipEventDisableTiming));
+        }
     }
     if (bytes < ctx->need) FAIL(ctx, FDTD_ENOMEM, "workspace of %zu bytes, need %zu", bytes, ctx->need);
     if (((uintptr_t)dev_ptr) & 255) FAIL(ctx, FDTD_EINVAL, "workspace must be 256-byte aligned");
@@ -1373,6 +1394,11 @@ void fdtd_destroy(fdtd_ctx *ctx) {
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->ev_psi) (void)hipEventDestroy(ctx->ev_psi);
+    for (int k = 0; k < 2; ++k) {
+        if (ctx->bside[k]) (void)hipStreamDestroy(ctx->bside[k]);
+        if (ctx->ev_bjoin[k]) (void)hipEventDestroy(ctx->ev_bjoin[k]);
+    }
     delete ctx;
 }
 

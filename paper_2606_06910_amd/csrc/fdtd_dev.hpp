@@ -273,6 +273,10 @@ __device__ __forceinline__ float lap_interior(const DevShot &s, float c, const f
 // Buffer-resource access: a uniform base (scalar descriptor), a 32-bit byte
 // offset per lane and a uniform 32-bit byte offset.  Offsets stay below 2^31.
 typedef __amdgpu_buffer_rsrc_t Rsrc;
+// A lane offset at or past a descriptor's record count reads zero and drops a
+// store without touching memory; lanes that need no data use this one (any
+// scalar offset the kernels add keeps the sum below 2^32).
+constexpr uint32_t kBufSkip = 0x80000000u;
 __device__ __forceinline__ Rsrc make_rsrc(const void *base) {
     return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, 0x7fffffff, 0x00020000);
 }

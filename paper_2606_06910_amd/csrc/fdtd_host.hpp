@@ -69,7 +69,8 @@ struct fdtd_ctx {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
     hipStream_t side = nullptr;         // second stream: interior update concurrent with psi + band
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t bside[2] = {nullptr, nullptr};   // y-slab and x-slab band kernels beside the z-slab one
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_psi = nullptr, ev_bjoin[2] = {nullptr, nullptr};
     char *ws = nullptr;
     size_t ws_bytes = 0, need = 0;
     size_t o_stepc = 0, o_scratch = 0, o_desc = 0, o_work_all = 0, o_band_all[3] = {0, 0, 0};

@@ -127,11 +127,12 @@ template <typename T, int NW, int RY> struct ZCtx {
     char *w, *sec;       // u^{n+1} out; FP32: u^{n-1} (may be w: in-place step), 16-bit: d^n (in place)
     uint32_t Sb, Smb;    // plane strides in bytes: field, m
     Rsrc ru, rm, rw, rs; // descriptors based at the current round's first plane
-    uint32_t off[RY], offm[RY];   // own rows: field and m byte offsets within a plane
+    uint32_t off[RY];             // own rows: u^n byte offsets within a plane (kBufSkip where not needed)
+    uint32_t offs[RY], offm[RY];  // own rows: second-state / u^{n+1} and m offsets (kBufSkip off the box)
     uint32_t hoff[ZM<NW, RY>::HS];    // halo byte offsets (a lane without a halo value reads its own point)
     int hslot[ZM<NW, RY>::HS];        // halo LDS index (the dummy slot for a lane without one)
-    float hc[ZM<NW, RY>::HS], umc[RY], mc[RY];   // halo, second state and m of plane z
-    float h1[ZM<NW, RY>::HS], um1[RY], m1[RY];   // the same of plane z + 1
+    float umc[RY], mc[RY];       // second state and m of plane z
+    float um1[RY], m1[RY];       // the same of plane z + 1
     const Roles *R;
     int x, y0, lane, r0; // column, tile origin row, lane, first own row (tile-local)
     int nlo[3], nhi[3];  // box of points outside every band
@@ -144,20 +145,23 @@ template <typename T, int NW, int RY> struct ZCtx {
 
 // plane z = z0 + PH of a round that started at plane z0 (descriptors based at z0)
 template <typename T, int NW, int RY, int PH>
-__device__ __forceinline__ void zbody(ZCtx<T, NW, RY> &C, const DevShot &s, float (&q)[ZQ][RY], float *L, int z) {
+__device__ __forceinline__ void zbody(ZCtx<T, NW, RY> &C, const DevShot &s, float (&q)[ZQ][RY],
+                                      float (&hq)[ZQ][ZM<NW, RY>::HS], float *L, int z) {
     using G = ZM<NW, RY>;
     auto slot = [](int o) { return (PH + 4 + o + ZQ) % ZQ; };
-    // loads two planes ahead of their use: u^n plane z + 6, the rest plane z + 2
-    float hn[G::HS], umn[RY], mn[RY];
+    // loads ahead of their use: u^n and its halo plane z + 6 (the halo in step with the
+    // neighbouring tiles' own rows, which they load as part of their u^n queue, so
+    // that it is found in L2), u^{n-1} (or d^n) and m plane z + 2
+    float umn[RY], mn[RY];
     {
         const uint32_t s6 = (PH + 6) * C.Sb, s2 = (PH + 2) * C.Sb, m2 = (PH + 2) * C.Smb;
 #pragma unroll
         for (int r = 0; r < RY; ++r) q[slot(6)][r] = Buf<T>::ld(C.ru, C.off[r], s6);
 #pragma unroll
-        for (int k = 0; k < G::HS; ++k) hn[k] = Buf<T>::ld(C.ru, C.hoff[k], s2);
+        for (int k = 0; k < G::HS; ++k) hq[slot(6)][k] = Buf<T>::ld(C.ru, C.hoff[k], s6);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            umn[r] = Buf<T>::ld(C.rs, C.off[r], s2);
+            umn[r] = Buf<T>::ld(C.rs, C.offs[r], s2);
             mn[r] = Buf<float>::ld(C.rm, C.offm[r], m2);
         }
     }
@@ -165,7 +169,7 @@ __device__ __forceinline__ void zbody(ZCtx<T, NW, RY> &C, const DevShot &s, floa
 #pragma unroll
     for (int r = 0; r < RY; ++r) L[(FDTD_R + C.r0 + r) * G::LW + FDTD_R + C.lane] = q[slot(0)][r];
 #pragma unroll
-    for (int k = 0; k < G::HS; ++k) L[C.hslot[k]] = C.hc[k];
+    for (int k = 0; k < G::HS; ++k) L[C.hslot[k]] = hq[slot(0)][k];
     __syncthreads();
     const bool srcplane = C.src_tile && wrap_ghost(s, 2, z) == C.sz;
     const uint32_t s0 = PH * C.Sb;
@@ -190,14 +194,9 @@ __device__ __forceinline__ void zbody(ZCtx<T, NW, RY> &C, const DevShot &s, floa
         const bool ok = C.full || (C.x >= C.nlo[0] && C.x < C.nhi[0] && y >= C.nlo[1] && y < C.nhi[1] &&
                                    !(C.partial && in_box(*C.R, C.x, y, z)));
         if (ok) {
-            Buf<T>::st(C.rw, C.off[r], s0, up.u);
-            if constexpr (IsInc<T>::v) Buf<T>::st(C.rs, C.off[r], s0, up.d);
+            Buf<T>::st(C.rw, C.offs[r], s0, up.u);
+            if constexpr (IsInc<T>::v) Buf<T>::st(C.rs, C.offs[r], s0, up.d);
         }
-    }
-#pragma unroll
-    for (int k = 0; k < G::HS; ++k) {
-        C.hc[k] = C.h1[k];
-        C.h1[k] = hn[k];
     }
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -283,8 +282,16 @@ __global__ __launch_bounds__(64 * NW) void k_zmarch(const DevShot *__restrict__ 
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const long e = (long)(C.y0 + C.r0 + r + s.fy) * P + C.x + FDTD_R;
-        C.off[r] = (uint32_t)(e * esz);
-        C.offm[r] = (uint32_t)(e * 4);
+        // loads a lane does not need read nothing (an offset past the descriptor's
+        // range reads zero without touching memory): u^n only within 4 points of
+        // the non-band box, the second state and m only inside it
+        const int y = C.y0 + C.r0 + r;
+        const bool nu = C.x >= C.nlo[0] - FDTD_R && C.x < C.nhi[0] + FDTD_R && y >= C.nlo[1] - FDTD_R &&
+                        y < C.nhi[1] + FDTD_R;
+        const bool ns = C.x >= C.nlo[0] && C.x < C.nhi[0] && y >= C.nlo[1] && y < C.nhi[1];
+        C.off[r] = nu ? (uint32_t)(e * esz) : kBufSkip;
+        C.offs[r] = ns ? (uint32_t)(e * esz) : kBufSkip;
+        C.offm[r] = ns ? (uint32_t)(e * 4) : kBufSkip;
     }
     // halo: values 0 .. 8 TY - 1 are the x halo (row i / 8, column i % 8: 4 left, 4
     // right), then 8 rows of 64 (4 above, 4 below the tile)
@@ -292,22 +299,26 @@ __global__ __launch_bounds__(64 * NW) void k_zmarch(const DevShot *__restrict__ 
     for (int k = 0; k < G::HS; ++k) {
         const int i = threadIdx.x + G::NT * k;
         C.hslot[k] = G::LH * G::LW;     // dummy
-        C.hoff[k] = C.off[0];
+        C.hoff[k] = kBufSkip;
         if (i < 2 * FDTD_R * G::TY) {
             const int row = i >> 3, c8 = i & 7;
             const int col = c8 < 4 ? c8 : 64 + c8;     // LDS column
             C.hslot[k] = (FDTD_R + row) * G::LW + col;
-            C.hoff[k] = (uint32_t)(((long)(C.y0 + row + s.fy) * P + x0 + col) * esz);
+            const int hx = x0 - FDTD_R + col, hy = C.y0 + row;
+            if (hx >= C.nlo[0] - FDTD_R && hx < C.nhi[0] + FDTD_R && hy >= C.nlo[1] - FDTD_R && hy < C.nhi[1] + FDTD_R)
+                C.hoff[k] = (uint32_t)(((long)(hy + s.fy) * P + hx + FDTD_R) * esz);
         } else if (i < G::NH) {
             const int j = i - 2 * FDTD_R * G::TY, r8 = j >> 6, c = j & 63;
             const int lrow = r8 < FDTD_R ? r8 : G::TY + r8;
             C.hslot[k] = lrow * G::LW + FDTD_R + c;
-            C.hoff[k] = (uint32_t)(((long)(C.y0 - FDTD_R + lrow + s.fy) * P + x0 + FDTD_R + c) * esz);
+            const int hx = x0 + c, hy = C.y0 - FDTD_R + lrow;
+            if (hx >= C.nlo[0] - FDTD_R && hx < C.nhi[0] + FDTD_R && hy >= C.nlo[1] - FDTD_R && hy < C.nhi[1] + FDTD_R)
+                C.hoff[k] = (uint32_t)(((long)(hy + s.fy) * P + hx + FDTD_R) * esz);
         }
     }
     C.src = source_at(s, *stepc);
 
-    float q[ZQ][RY];
+    float q[ZQ][RY], hq[ZQ][G::HS];
     int it = 0;
     for (int sg = 0; sg < nseg; ++sg) {
         const int a = seg_a[sg], b = seg_b[sg];
@@ -321,20 +332,19 @@ __global__ __launch_bounds__(64 * NW) void k_zmarch(const DevShot *__restrict__ 
                 for (int r = 0; r < RY; ++r) q[o + 4][r] = Buf<T>::ld(ru, C.off[r], (o + 4) * C.Sb);
             const Rsrc rs = make_rsrc(C.sec + (long)a * C.Sb);
             const Rsrc rm = make_rsrc(C.m + (long)a * C.Smb);
-            const uint32_t u4 = 4 * C.Sb, u5 = 5 * C.Sb;
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
                 q[ZQ - 1][r] = 0.0f;
-                C.umc[r] = Buf<T>::ld(rs, C.off[r], 0);
+                C.umc[r] = Buf<T>::ld(rs, C.offs[r], 0);
                 C.mc[r] = Buf<float>::ld(rm, C.offm[r], 0);
-                C.um1[r] = Buf<T>::ld(rs, C.off[r], C.Sb);
+                C.um1[r] = Buf<T>::ld(rs, C.offs[r], C.Sb);
                 C.m1[r] = Buf<float>::ld(rm, C.offm[r], C.Smb);
             }
+            // halo of planes a .. a + 5 (slots 4 .. 9)
 #pragma unroll
-            for (int k = 0; k < G::HS; ++k) {
-                C.hc[k] = Buf<T>::ld(ru, C.hoff[k], u4);
-                C.h1[k] = Buf<T>::ld(ru, C.hoff[k], u5);
-            }
+            for (int o = 0; o < 6; ++o)
+#pragma unroll
+                for (int k = 0; k < G::HS; ++k) hq[o + 4][k] = Buf<T>::ld(ru, C.hoff[k], (o + 4) * C.Sb);
         }
         for (int z0 = a; z0 < b; z0 += ZQ) {
             C.ru = make_rsrc(C.u + (long)z0 * C.Sb);
@@ -344,7 +354,7 @@ __global__ __launch_bounds__(64 * NW) void k_zmarch(const DevShot *__restrict__ 
             const int n = b - z0;
 #define ZSTEP(PH)                                                                 \
     if (n > PH) {                                                                 \
-        zbody<T, NW, RY, PH>(C, s, q, sm + (it & 1) * G::LB, z0 + PH);            \
+        zbody<T, NW, RY, PH>(C, s, q, hq, sm + (it & 1) * G::LB, z0 + PH);        \
         ++it;                                                                     \
     }
             ZSTEP(0) ZSTEP(1) ZSTEP(2) ZSTEP(3) ZSTEP(4) ZSTEP(5)
