@@ -19,6 +19,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+COPY_CEILING_GBS = 5090.0   # plain 1 GiB device copy, read + write (copy_1GiB_counters.txt)
 
 
 def slab_points(n, cpml):
@@ -219,6 +220,122 @@ def precision_leg(K=200):
     return out
 
 
+def _timed_steps(p, steps, graph):
+    """ms of `steps` steps from reset (capture, if any, untimed)."""
+    import torch
+
+    if graph:
+        p.step(steps, graph=True)
+        torch.cuda.synchronize()
+    p.reset()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(p.stream)
+    p.step(steps, graph=graph)
+    e1.record(p.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def small_leg():
+    """The 64^3 workload (10-cell layers, 200 steps): a few MB, launch-bound;
+    Mpts/s with every step launched eagerly and with the HIP-graph time loop."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2606_06910_amd import Propagator, Shot
+
+    w = synth.plain64()
+    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml)])
+    p.set_velocity(0, torch.from_numpy(w.v.astype(np.float32)).cuda())
+    p.inject_source(0, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)).cuda())
+    p.set_receivers(0, w.rec)
+    p.record(0, w.nt)
+    out = {}
+    for name, graph in (("eager", False), ("graph", True)):
+        ms = _timed_steps(p, w.nt, graph)
+        out[name + "_mpts"] = round(w.npts * w.nt / (ms / 1e3) / 1e6, 1)
+    p.close()
+    out["workload"] = "64^3, 10-cell CPML, 200 steps"
+    return out
+
+
+def pencil_leg(K=100):
+    """One GPU's pencil-yz share: owned 1024 x 384 x 384, CPML on +-x only,
+    ghost faces on y and z exchanged (loopback) every s steps with depth 4 s.
+    Mpts/s of owned points for s = 1, 2, 4, the speed-up S_s over s = 1 and
+    the exchange kernels' share of a step."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2606_06910_amd import Propagator, Shot
+
+    w = synth.pencil(nt=K + 8)
+    v = torch.from_numpy(w.v.astype(np.float32)).cuda()
+    wav = torch.from_numpy(w.wavelet.astype(np.float32)).cuda()
+    out = {}
+    for s_ in (1, 2, 4):
+        p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, face=(0, 0, 1, 1, 1, 1), exchange_every=s_)])
+        p.set_velocity(0, v)
+        p.inject_source(0, w.src[0], wav)
+        ms = _timed_steps(p, K, True)
+        p.reset()
+        p.set_timing(True)
+        p.step(4 * 4)
+        ex = p.timing(3)
+        p.set_timing(False)
+        exch_ms_per_step = ex[0] * ex[1] / 16.0
+        out["s%d" % s_] = {"mpts": round(w.npts * K / (ms / 1e3) / 1e6, 1),
+                           "exchange_ms_per_step": round(exch_ms_per_step, 5)}
+        p.close()
+    for s_ in (2, 4):
+        out["s%d" % s_]["S"] = round(out["s%d" % s_]["mpts"] / out["s1"]["mpts"], 3)
+    out["workload"] = "owned 1024x384x384, CPML 20 on +-x, y/z ghost faces (loopback), %d steps" % K
+    return out
+
+
+def adjoint_leg(nshots=3, K=600, every=25):
+    """Forward (with checkpoints every 25 steps) and adjoint (FP64 velocity
+    gradient, segment recomputation) of the smallest shots of the 24-shot
+    workload: Mpts/s of each pass over the shots' points x steps."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2606_06910_amd import Propagator, Shot
+
+    shapes = synth.batch_shapes(24)
+    order = sorted(range(len(shapes)), key=lambda i: np.prod(shapes[i]))[:nshots]
+    fwd_ms = adj_ms = 0.0
+    npts = 0
+    for i in order:
+        w, v0 = synth.batch_shot(i, shapes[i], nt=K)
+        p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, v_ref=float(w.v.max()))])
+        p.set_velocity(0, torch.from_numpy(v0.astype(np.float32)).cuda())
+        p.inject_source(0, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)).cuda())
+        p.set_receivers(0, w.rec)
+        p.set_checkpointing(0, every, K)
+        tr = p.record(0, K)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(p.stream)
+        p.step(K)
+        e[1].record(p.stream)
+        torch.cuda.synchronize()
+        fwd_ms += e[0].elapsed_time(e[1])
+        resid = tr.clone()
+        e[1].record(p.stream)
+        p.adjoint(0, K, resid)
+        e[2].record(p.stream)
+        torch.cuda.synchronize()
+        adj_ms += e[1].elapsed_time(e[2])
+        npts += w.npts
+        p.close()
+    return {"shots": [list(shapes[i]) for i in order], "steps": K, "checkpoint_every": every,
+            "forward_with_checkpoints_mpts": round(npts * K / (fwd_ms / 1e3) / 1e6, 1),
+            "adjoint_mpts": round(npts * K / (adj_ms / 1e3) / 1e6, 1)}
+
+
 def batched_leg(K=600, nshots=24):
     """24 shots of uneven shape (each axis uniform in [96, 288]), 15-cell CPML,
     layered models: Mpts/s of all shots advanced together (one launch per kernel
@@ -296,6 +413,28 @@ def cpu_baseline(w, steps=2):
                 % (steps, w.n[0], w.n[1], w.n[2]))
 
 
+LEGS = {
+    "storage_768": lambda: precision_leg(),
+    "batched_24": lambda: batched_leg(),
+    "small_64": lambda: small_leg(),
+    "pencil_1024x384x384": lambda: pencil_leg(),
+    "adjoint_3_smallest": lambda: adjoint_leg(),
+}
+
+
+def run_leg(name, timeout=600):
+    """One extra leg in a child process, so that a failure there cannot take
+    the headline figure down with it; returns its JSON, or the failure."""
+    import subprocess
+
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--leg", name], cwd=ROOT,
+                       stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=timeout)
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    if r.returncode == 0 and lines:
+        return json.loads(lines[-1])
+    return {"error": "leg exited with status %d" % r.returncode, "stderr_tail": r.stderr[-400:]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,7 +450,13 @@ def main():
                     help="only run a plain device copy of MIB MiB five times (counter calibration run)")
     ap.add_argument("--kernel-timing", action="store_true",
                     help="only run the per-kernel timing pass (the launches a profiler summary is taken over)")
+    ap.add_argument("--leg", choices=sorted(LEGS), help="only run one extra leg and print its JSON")
+    ap.add_argument("--storage-leg", action="store_true",
+                    help="also run the 768^3 FP32/FP16/BF16 storage leg (off by default, see DESIGN.md)")
     args = ap.parse_args()
+    if args.leg:
+        print(json.dumps(LEGS[args.leg]()), flush=True)
+        return
     if args.copy_probe:
         import torch
 
@@ -354,6 +499,7 @@ def main():
                          ("psi", psi_kernel_bytes(w.n, w.cpml))):
         if tm[name][1] > 0:
             kgbs[name] = round(nbytes / (tm[name][0] / 1e3) / 1e9, 1)
+    traffic = measured_traffic(w.n, plan)
     out = {
         "metric": "Mpts/s (output points/sec) + % HBM peak, FP32 vs FP16-storage at stated error",
         "value": round(value, 1),
@@ -370,7 +516,10 @@ def main():
         "config": {"workload": "layered %dx%dx%d, 20-cell CPML on 6 faces, Ricker 10 Hz, FP32 fields" % n,
                    "grid": list(n), "cpml": 20, "variant": args.variant, "graph": not args.eager},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(w.n, plan),
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "measured_frac": (round(traffic / (upd[0] / 1e3) / 1e9 / PEAK_HBM_GBS, 4)
+                                       if traffic else None),
+                     "copy_ceiling_gbs": COPY_CEILING_GBS,
                      "kernel": "k_zmarch<float, RY> (update of the points outside the layer bands)",
                      "kernel_ms": round(upd[0], 5), "algorithmic_bytes_per_launch": upd_bytes},
         "step_algorithmic_gbs": round(step_bytes(w.n, w.cpml) / (ms / K / 1e3) / 1e9, 1),
@@ -386,10 +535,13 @@ def main():
             var[name] = round(N * Kc / (m2 / 1e3) / 1e6, 1)
         out["variants_mpts"] = var
     if not args.no_extra:
-        print("bench: 16-bit storage leg (768^3)", file=sys.stderr, flush=True)
-        out["storage_768"] = precision_leg()
-        print("bench: batched-shot leg (24 shots)", file=sys.stderr, flush=True)
-        out["batched_24"] = batched_leg()
+        torch.cuda.empty_cache()
+        legs = ["batched_24", "small_64", "pencil_1024x384x384", "adjoint_3_smallest"]
+        if args.storage_leg:
+            legs.insert(0, "storage_768")
+        for name in legs:
+            print("bench: %s leg" % name, file=sys.stderr, flush=True)
+            out[name] = run_leg(name)
     if not args.no_cpu:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)

@@ -198,11 +198,11 @@ template <typename W> static std::vector<W> xcd_order(const std::vector<W> &sp) 
 
 // band-kernel tiles of a shot, for the largest compute box it uses (smaller
 // boxes reuse the list; tiles past a box end exit at once)
-static std::vector<BandItem> band_tiles(const ShotH &s, int shot, int kind) {
+static std::vector<BandItem> band_tiles(const ShotH &s, int shot) {
     const int ext = (s.gy || s.gz) ? s.g - 4 : 0;
     const int n3[3] = {s.nx, s.ny, s.nz}, gh[3] = {0, s.gy, s.gz};
     std::vector<BandItem> v;
-    for (int b = 2 * kind; b < 2 * kind + 2; ++b) {
+    for (int b = 0; b < 6; ++b) {
         int lo[3], hi[3];
         band_box(n3, s.Llo, s.Lhi, gh, ext, b, lo, hi);
         const int wx = hi[0] - lo[0], wy = hi[1] - lo[1], wz = hi[2] - lo[2];
@@ -214,7 +214,7 @@ static std::vector<BandItem> band_tiles(const ShotH &s, int shot, int kind) {
     }
     return v;
 }
-static size_t band_capacity(const ShotH &s, int kind) { return band_tiles(s, 0, kind).size() + 8; }
+static size_t band_capacity(const ShotH &s) { return band_tiles(s, 0).size() + 8; }
 
 static std::vector<WorkItem> shot_tiles(const ShotH &s, int shot, int ry, int zchunk) {
     int ext = s.g - 4;
@@ -553,12 +553,13 @@ static Roles plain_roles(const fdtd_ctx *ctx, int ext) {
 // z-march of the points outside the bands runs on the side stream, forked
 // from and joined back to the main one, concurrently with the psi pass and
 // the band kernels: the two sets of points are disjoint and both read only
-// u^n (and their own points' second state).  After the psi pass the three
-// band kinds (z, y and x slabs: disjoint boxes, reading u^n and psi) run
-// concurrently too, kinds 1 and 2 on streams of their own.  Naive shots
-// update every point after the psi pass, on the main stream.  With
-// per-kernel timing enabled everything stays on the main stream, so that
-// each timed duration is the kernel's own.
+// u^n (and their own points' second state).  The band kernel covers the
+// tiles of all three band kinds in one launch after the psi pass.  (One fork
+// per step keeps a captured graph to two branches per step: graphs of many
+// steps with more parallel branches have exhausted the HIP runtime's launch
+// resources.)  Naive shots update every point after the psi pass, on the main
+// stream.  With per-kernel timing enabled everything stays on the main
+// stream, so that each timed duration is the kernel's own.
 static void enqueue_psi_update(fdtd_ctx *ctx, int shot, const Roles &R, long maxc_psi) {
     const DevShot *dd = (const DevShot *)wsp(ctx, ctx->o_desc);
     int *stepc = (int *)wsp(ctx, ctx->o_stepc);
@@ -594,35 +595,19 @@ static void enqueue_psi_update(fdtd_ctx *ctx, int shot, const Roles &R, long max
     fdtd_launch_psi(stor, dd + lo, hi - lo, maxc_psi, R.iu, ext, ctx->stream);
     toc(ctx, 1, t0);
     if (any_zm) {
-        // the stream of each band kind: the main one for kind 0, its own for kinds 1 and 2
-        hipStream_t bst[3] = {ctx->stream, ctx->stream, ctx->stream};
-        if (side != ctx->stream && ctx->bside[0]) {
-            (void)hipEventRecord(ctx->ev_psi, ctx->stream);
-            for (int k = 1; k < 3; ++k) {
-                (void)hipStreamWaitEvent(ctx->bside[k - 1], ctx->ev_psi, 0);
-                bst[k] = ctx->bside[k - 1];
-            }
-        }
         t0 = tic(ctx);
-        for (int k = 0; k < 3; ++k) {
-            if (grouped) {
-                fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, ctx->o_band_all[k]), ctx->nband_all[k], k, R,
-                                 kBandZ, stepc, bst[k]);
-            } else {
-                for (int i = lo; i < hi; ++i) {
-                    const ShotH &s = ctx->shots[i];
-                    if (s.variant == FDTD_VARIANT_NAIVE) continue;
-                    fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, s.o_band[k]), s.nband[k], k, R, kBandZ,
-                                     stepc, bst[k]);
-                }
+        if (grouped) {
+            fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, ctx->o_band_all), ctx->nband_all, R, kBandZ, stepc,
+                             ctx->stream);
+        } else {
+            for (int i = lo; i < hi; ++i) {
+                const ShotH &s = ctx->shots[i];
+                if (s.variant == FDTD_VARIANT_NAIVE) continue;
+                fdtd_launch_band(stor, dd, (const BandItem *)wsp(ctx, s.o_band), s.nband, R, kBandZ, stepc,
+                                 ctx->stream);
             }
         }
         toc(ctx, 4, t0);
-        for (int k = 1; k < 3; ++k)
-            if (bst[k] != ctx->stream) {
-                (void)hipEventRecord(ctx->ev_bjoin[k - 1], bst[k]);
-                (void)hipStreamWaitEvent(ctx->stream, ctx->ev_bjoin[k - 1], 0);
-            }
     }
     for (int i = lo; i < hi; ++i) {
         const ShotH &s = ctx->shots[i];
@@ -864,11 +849,9 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
     size_t cap_all = 0;
     for (auto &s : ctx->shots) cap_all += work_capacity(s) + 8;
     ctx->o_work_all = take(sizeof(WorkItem) * cap_all);
-    for (int k = 0; k < 3; ++k) {
-        size_t band_all = 0;
-        for (auto &s : ctx->shots) band_all += band_capacity(s, k);
-        ctx->o_band_all[k] = take(sizeof(BandItem) * band_all);
-    }
+    size_t band_all = 0;
+    for (auto &s : ctx->shots) band_all += band_capacity(s);
+    ctx->o_band_all = take(sizeof(BandItem) * band_all);
     for (auto &s : ctx->shots) {
         s.o_u[0] = take(s.elems * s.esz);
         s.o_u[1] = take(s.elems * s.esz);
@@ -887,7 +870,7 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
         }
         s.o_prof = take((size_t)3 * 4 * s.nmax * 4);
         s.o_work = take(sizeof(WorkItem) * work_capacity(s));
-        for (int k = 0; k < 3; ++k) s.o_band[k] = take(sizeof(BandItem) * band_capacity(s, k));
+        s.o_band = take(sizeof(BandItem) * band_capacity(s));
         s.xbuf_bytes = xbuf_bytes(s);
         s.o_xbuf = take(s.xbuf_bytes);
         for (int p = 0; p < 2; ++p)
@@ -907,18 +890,18 @@ int fdtd_workspace_size(const fdtd_ctx *ctx, size_t *bytes) {
 
 static int write_work_lists(fdtd_ctx *ctx) {
     std::map<std::pair<int, int>, std::vector<WorkItem>> byplan;
-    std::vector<BandItem> band_all[3];
+    std::vector<BandItem> band_all;
     for (size_t i = 0; i < ctx->shots.size(); ++i) {
         ShotH &s = ctx->shots[i];
-        for (int k = 0; k < 3; ++k) {
-            std::vector<BandItem> bt = band_tiles(s, (int)i, k);
+        {
+            std::vector<BandItem> bt = band_tiles(s, (int)i);
             std::vector<BandItem> bw = xcd_order(bt);
-            if (bw.size() > band_capacity(s, k)) FAIL(ctx, FDTD_EINVAL, "band list overflow");
-            s.nband[k] = (int)bw.size();
+            if (bw.size() > band_capacity(s)) FAIL(ctx, FDTD_EINVAL, "band list overflow");
+            s.nband = (int)bw.size();
             if (!bw.empty())
-                HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_band[k]), bw.data(), sizeof(BandItem) * bw.size(),
+                HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_band), bw.data(), sizeof(BandItem) * bw.size(),
                                            hipMemcpyHostToDevice, ctx->stream));
-            if (s.variant != FDTD_VARIANT_NAIVE) band_all[k].insert(band_all[k].end(), bt.begin(), bt.end());
+            if (s.variant != FDTD_VARIANT_NAIVE) band_all.insert(band_all.end(), bt.begin(), bt.end());
         }
         std::vector<WorkItem> sp = shot_tiles(s, (int)i, s.ry, s.zchunk);
         std::vector<WorkItem> w = xcd_order(sp);
@@ -953,11 +936,11 @@ static int write_work_lists(fdtd_ctx *ctx) {
         all.insert(all.end(), wa.begin(), wa.end());
     }
     ctx->nwork_all = (int)all.size();
-    for (int k = 0; k < 3; ++k) {
-        std::vector<BandItem> bw = xcd_order(band_all[k]);
-        ctx->nband_all[k] = (int)bw.size();
+    {
+        std::vector<BandItem> bw = xcd_order(band_all);
+        ctx->nband_all = (int)bw.size();
         if (!bw.empty())
-            HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, ctx->o_band_all[k]), bw.data(), sizeof(BandItem) * bw.size(),
+            HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, ctx->o_band_all), bw.data(), sizeof(BandItem) * bw.size(),
                                        hipMemcpyHostToDevice, ctx->stream));
     }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -995,11 +978,6 @@ int fdtd_bind_workspace(fdtd_ctx *ctx, void *dev_ptr, size_t bytes) {
         HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
         HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
         HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
-        HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_psi, hipEventDisableTiming));
-        for (int k = 0; k < 2; ++k) {
-            HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->bside[k], hipStreamNonBlocking));
-            HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_bjoin[k], hipEventDisableTiming));
-        }
     }
     if (bytes < ctx->need) FAIL(ctx, FDTD_ENOMEM, "workspace of %zu bytes, need %zu", bytes, ctx->need);
     if (((uintptr_t)dev_ptr) & 255) FAIL(ctx, FDTD_EINVAL, "workspace must be 256-byte aligned");
@@ -1394,11 +1372,6 @@ void fdtd_destroy(fdtd_ctx *ctx) {
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
-    if (ctx->ev_psi) (void)hipEventDestroy(ctx->ev_psi);
-    for (int k = 0; k < 2; ++k) {
-        if (ctx->bside[k]) (void)hipStreamDestroy(ctx->bside[k]);
-        if (ctx->ev_bjoin[k]) (void)hipEventDestroy(ctx->ev_bjoin[k]);
-    }
     delete ctx;
 }
 

@@ -35,8 +35,8 @@ struct ShotH {
     int njobs[2][4] = {};
     long jobmax[2][4] = {};
     int nwork = 0;
-    size_t o_band[3] = {0, 0, 0};   // band-kernel tile lists per box kind (for the largest compute box)
-    int nband[3] = {0, 0, 0};
+    size_t o_band = 0;         // band-kernel tile list, all box kinds (for the largest compute box)
+    int nband = 0;
     // model / source / receivers
     bool vel_set = false;
     double vmax = 0, vref = 0, scale = 1;
@@ -69,12 +69,11 @@ struct fdtd_ctx {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
     hipStream_t side = nullptr;         // second stream: interior update concurrent with psi + band
-    hipStream_t bside[2] = {nullptr, nullptr};   // y-slab and x-slab band kernels beside the z-slab one
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_psi = nullptr, ev_bjoin[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0, need = 0;
-    size_t o_stepc = 0, o_scratch = 0, o_desc = 0, o_work_all = 0, o_band_all[3] = {0, 0, 0};
-    int nwork_all = 0, nband_all[3] = {0, 0, 0};
+    size_t o_stepc = 0, o_scratch = 0, o_desc = 0, o_work_all = 0, o_band_all = 0;
+    int nwork_all = 0, nband_all = 0;
     // multi-shot z-march launches: one per distinct (ry, zchunk) plan
     struct Group {
         int ry, zchunk;

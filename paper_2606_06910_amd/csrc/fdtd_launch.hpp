@@ -8,9 +8,9 @@ void fdtd_launch_naive(int stor, const DevShot *d_shots, int shot, int nx, int N
                        const int *stepc, hipStream_t st);
 void fdtd_launch_zmarch(int stor, const DevShot *d_shots, const WorkItem *work, int nwork, int ry, const Roles &R,
                         int zchunk, const int *stepc, hipStream_t st);
-// band points of one box kind (0: z slabs, 1: y slabs, 2: x slabs)
-void fdtd_launch_band(int stor, const DevShot *d_shots, const BandItem *work, int nwork, int kind, const Roles &R,
-                      int zchunk, const int *stepc, hipStream_t st);
+// band points (tiles of every box kind in one list)
+void fdtd_launch_band(int stor, const DevShot *d_shots, const BandItem *work, int nwork, const Roles &R, int zchunk,
+                      const int *stepc, hipStream_t st);
 void fdtd_launch_record(int stor, const DevShot *d_shots, int nshots, const Roles &R, int *stepc, hipStream_t st);
 // temporal blocking: args points to a host TBArgs (kernels_tblock.hip); K = 2 or 4
 void fdtd_launch_tblock(const DevShot *d_shots, const WorkItem *work, int nwork, int K, const void *args, int zchunk,

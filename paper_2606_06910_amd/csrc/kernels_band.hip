@@ -3,7 +3,8 @@
 // The band is the union of the absorbing-layer slabs and the 4-cell margin
 // their psi derivative reaches (paper, section "CPML Boundary Layers": the
 // stretched second derivative and its memory variables).  It is cut into six
-// disjoint boxes (band_box) of three kinds, one kernel instance per kind:
+// disjoint boxes (band_box) of three kinds, each a specialisation of one
+// tile routine (one launch covers the tiles of all kinds):
 //   kind 0, boxes 0/1: z band (x, y band at the edges);
 //   kind 1, boxes 2/3: y band (x band at the edges), z outside its band;
 //   kind 2, boxes 4/5: x band only.
@@ -46,10 +47,9 @@ __device__ __forceinline__ void axis_point(const DevShot &s, int d, int c, AxisP
 }  // namespace
 
 template <typename T, int KIND>
-__global__ __launch_bounds__(256) void k_band(const DevShot *__restrict__ shots, const BandItem *__restrict__ work,
-                                              Roles R, int zchunk, const int *__restrict__ stepc) {
+__device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, const BandItem wi, const Roles &R,
+                                          int zchunk, const int *__restrict__ stepc) {
     constexpr bool HAS_Y = KIND <= 1, HAS_Z = KIND == 0;
-    const BandItem wi = work[blockIdx.x];
     const DevShot &s = shots[wi.shot];
     int blo[3], bhi[3];
     const int n3[3] = {s.nx, s.ny, s.nz};
@@ -255,35 +255,36 @@ __global__ __launch_bounds__(256) void k_band(const DevShot *__restrict__ shots,
         }
     };
 
-    // two plane buffers in alternation: the loads of plane z + 1 are in flight
-    // while plane z is computed and stored
-    PL A, B;
-    load(za, A);
+    PL A;
 #pragma unroll 1
-    for (int z = za; z < zb; z += 2) {
-        if (z + 1 < zb) load(z + 1, B);
+    for (int z = za; z < zb; ++z) {
+        load(z, A);
         compute(z, A);
-        if (z + 1 >= zb) break;
-        if (z + 2 < zb) load(z + 2, A);
-        compute(z + 1, B);
     }
 }
 
+// one launch for the tiles of all three kinds (a workgroup's kind is that of
+// its box), so that they run side by side without extra streams
 template <typename T>
-static void launch_band_t(const DevShot *d_shots, const BandItem *work, int nwork, int kind, const Roles &R,
-                          int zchunk, const int *stepc, hipStream_t st) {
-    if (nwork <= 0) return;
-    if (kind == 0)
-        hipLaunchKernelGGL((k_band<T, 0>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
-    else if (kind == 1)
-        hipLaunchKernelGGL((k_band<T, 1>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
-    else
-        hipLaunchKernelGGL((k_band<T, 2>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
+__global__ __launch_bounds__(256) void k_band(const DevShot *__restrict__ shots, const BandItem *__restrict__ work,
+                                              Roles R, int zchunk, const int *__restrict__ stepc) {
+    const BandItem wi = work[blockIdx.x];
+    const int kind = wi.box >> 1;
+    if (kind == 0) band_tile<T, 0>(shots, wi, R, zchunk, stepc);
+    else if (kind == 1) band_tile<T, 1>(shots, wi, R, zchunk, stepc);
+    else band_tile<T, 2>(shots, wi, R, zchunk, stepc);
 }
 
-void fdtd_launch_band(int stor, const DevShot *d_shots, const BandItem *work, int nwork, int kind, const Roles &R,
-                      int zchunk, const int *stepc, hipStream_t st) {
-    if (stor == 1) launch_band_t<_Float16>(d_shots, work, nwork, kind, R, zchunk, stepc, st);
-    else if (stor == 2) launch_band_t<__bf16>(d_shots, work, nwork, kind, R, zchunk, stepc, st);
-    else launch_band_t<float>(d_shots, work, nwork, kind, R, zchunk, stepc, st);
+template <typename T>
+static void launch_band_t(const DevShot *d_shots, const BandItem *work, int nwork, const Roles &R, int zchunk,
+                          const int *stepc, hipStream_t st) {
+    if (nwork <= 0) return;
+    hipLaunchKernelGGL(k_band<T>, dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
+}
+
+void fdtd_launch_band(int stor, const DevShot *d_shots, const BandItem *work, int nwork, const Roles &R, int zchunk,
+                      const int *stepc, hipStream_t st) {
+    if (stor == 1) launch_band_t<_Float16>(d_shots, work, nwork, R, zchunk, stepc, st);
+    else if (stor == 2) launch_band_t<__bf16>(d_shots, work, nwork, R, zchunk, stepc, st);
+    else launch_band_t<float>(d_shots, work, nwork, R, zchunk, stepc, st);
 }
