@@ -75,15 +75,17 @@ static void plan_shot(ShotH &s) {
     s.psi_elems[2] = (size_t)s.SZ * s.PY * s.nx;
     s.nmax = std::max(s.nx, std::max(s.ny, s.nz));
     s.variant = c.variant == FDTD_VARIANT_AUTO ? FDTD_VARIANT_ZMARCH : c.variant;
-    // default z-march plan: tiles of 64 x 32 (8 waves), whole z columns per
-    // workgroup when the xy tiles alone give a workgroup per two compute units
-    // (the psi and band kernels run beside them), else chunks short enough to
-    // reach that (at least 32 planes)
-    s.ry = 4;
+    // default z-march plan (measured at 512^3 and 768^3 with the psi and band
+    // kernels running beside it): tiles of 64 x 32 (8 waves) while they number
+    // at most 128, else tiles of 64 x 16; whole z columns per workgroup when
+    // the xy tiles reach that count (128, resp. 256), else chunks short enough
+    // to reach it (at least 32 planes)
     {
         const int Ny = s.ny + (s.gy ? 2 * (s.g - 4) : 0), Nz = s.nz + (s.gz ? 2 * (s.g - 4) : 0);
-        const long nxy = (long)((s.nx + 63) / 64) * ((Ny + 31) / 32);
-        const long want = 128;
+        const long n32 = (long)((s.nx + 63) / 64) * ((Ny + 31) / 32);
+        s.ry = n32 <= 128 ? 4 : 2;
+        const long nxy = s.ry == 4 ? n32 : (long)((s.nx + 63) / 64) * ((Ny + 15) / 16);
+        const long want = s.ry == 4 ? 128 : 256;
         long nchunk = nxy >= want ? 1 : (want + nxy - 1) / nxy;
         int zc = (int)((Nz + nchunk - 1) / nchunk);
         zc = std::max(32, (zc + 15) / 16 * 16);
