@@ -209,7 +209,10 @@ static std::vector<BandItem> band_tiles(const ShotH &s, int shot) {
         band_box(n3, s.Llo, s.Lhi, gh, ext, b, lo, hi);
         const int wx = hi[0] - lo[0], wy = hi[1] - lo[1], wz = hi[2] - lo[2];
         if (wx <= 0 || wy <= 0 || wz <= 0) continue;
-        const int nzc = (wz + kBandZ - 1) / kBandZ, nty = (wy + kBandTY - 1) / kBandTY, ntx = (wx + kBandTX - 1) / kBandTX;
+        // z boxes (b < 2) are walked whole; x tiles as band_xtiles cuts them
+        int x0, x1;
+        const int ntx = band_xtiles(s.nx, s.Llo[0], s.Lhi[0], b, lo[0], hi[0], 0, &x0, &x1);
+        const int nzc = b < 2 ? 1 : (wz + kBandZ - 1) / kBandZ, nty = (wy + kBandTY - 1) / kBandTY;
         for (int zc = 0; zc < nzc; ++zc)
             for (int ty = 0; ty < nty; ++ty)
                 for (int tx = 0; tx < ntx; ++tx) v.push_back(BandItem{shot, b, tx, ty, zc, 0, 0, 0});
@@ -245,6 +248,19 @@ static long psi_count(const ShotH &s, int d, int ext) {
     if (d == 0) return (long)s.LX * Ny * Nz;
     if (d == 1) return (long)s.nx * s.LY * Nz;
     return (long)s.nx * Ny * s.LZ;
+}
+
+// Whether the band kernel advances psi_x and psi_z itself (DevShot::fused).
+// It needs every x-layer point and the band points that read it in one tile
+// row (each x band at most BAND_TX wide, and the two x bands far enough apart
+// that neither reads the other's layer points), and likewise the two z boxes
+// sharing no layer point.  Naive shots read every psi from the psi pass.
+static bool shot_fused(const ShotH &s) {
+    if (s.variant == FDTD_VARIANT_NAIVE) return false;
+    const int lx = s.Llo[0], hx = s.Lhi[0], lz = s.Llo[2], hz = s.Lhi[2];
+    if (lx + hx > 0 && (lx + FDTD_R > kBandTX || hx + FDTD_R > kBandTX || s.nx < lx + hx + 2 * FDTD_R)) return false;
+    if (lz + hz > 0 && s.nz < lz + hz + 2 * FDTD_R) return false;
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -359,6 +375,7 @@ static void fill_desc(fdtd_ctx *ctx, int i) {
     D.ghost[0] = 0;
     D.ghost[1] = s.gy;
     D.ghost[2] = s.gz;
+    D.fused = shot_fused(s) ? 1 : 0;
     double cc = 0;
     for (int d = 0; d < 3; ++d) {
         const double h = s.c.h[d];
@@ -562,7 +579,7 @@ static Roles plain_roles(const fdtd_ctx *ctx, int ext) {
 // resources.)  Naive shots update every point after the psi pass, on the main
 // stream.  With per-kernel timing enabled everything stays on the main
 // stream, so that each timed duration is the kernel's own.
-static void enqueue_psi_update(fdtd_ctx *ctx, int shot, const Roles &R, long maxc_psi) {
+static void enqueue_psi_update(fdtd_ctx *ctx, int shot, const Roles &R) {
     const DevShot *dd = (const DevShot *)wsp(ctx, ctx->o_desc);
     int *stepc = (int *)wsp(ctx, ctx->o_stepc);
     const int stor = ctx->storage;
@@ -593,8 +610,16 @@ static void enqueue_psi_update(fdtd_ctx *ctx, int shot, const Roles &R, long max
         }
         toc(ctx, 0, t0, side);
     }
+    // psi pass: psi_y only when every shot of the launch is fused, else all axes
+    // (the kernel skips x and z of fused shots)
+    bool all_fused = true;
+    for (int i = lo; i < hi; ++i) all_fused = all_fused && shot_fused(ctx->shots[i]);
+    const int d0 = all_fused ? 1 : 0, nd = all_fused ? 1 : 3;
+    long maxc = 0;
+    for (int i = lo; i < hi; ++i)
+        for (int d = d0; d < d0 + nd; ++d) maxc = std::max(maxc, psi_count(ctx->shots[i], d, ext));
     hipEvent_t t0 = tic(ctx);
-    fdtd_launch_psi(stor, dd + lo, hi - lo, maxc_psi, R.iu, ext, ctx->stream);
+    fdtd_launch_psi(stor, dd + lo, hi - lo, maxc, R.iu, ext, d0, nd, ctx->stream);
     toc(ctx, 1, t0);
     if (any_zm) {
         t0 = tic(ctx);
@@ -641,11 +666,8 @@ static void enqueue_step(fdtd_ctx *ctx, int shot) {
     }
     const int ext = ghost_ext(ctx, n);
     const DevShot *dd = (const DevShot *)wsp(ctx, ctx->o_desc);
-    long maxc = 0;
-    for (int i = lo; i < hi; ++i)
-        for (int d = 0; d < 3; ++d) maxc = std::max(maxc, psi_count(ctx->shots[i], d, ext));
     const Roles R = plain_roles(ctx, ext);
-    enqueue_psi_update(ctx, shot, R, maxc);
+    enqueue_psi_update(ctx, shot, R);
     hipEvent_t t0 = tic(ctx);
     fdtd_launch_record(ctx->storage, dd + lo, hi - lo, R, (int *)wsp(ctx, ctx->o_stepc), ctx->stream);
     toc(ctx, 2, t0);
@@ -689,8 +711,6 @@ static void enqueue_tblock(fdtd_ctx *ctx) {
     hipEvent_t t0 = tic(ctx);
     fdtd_launch_tblock(dd, (const WorkItem *)wsp(ctx, s.o_tbwork), s.ntbwork, K, &a, s.tb_zchunk, stepc, ctx->stream);
     toc(ctx, 5, t0);
-    long maxc = 0;
-    for (int d = 0; d < 3; ++d) maxc = std::max(maxc, psi_count(s, d, 0));
     for (int j = 1; j <= K; ++j) {
         Roles R;
         R.iu = Lv[j];
@@ -701,7 +721,7 @@ static void enqueue_tblock(fdtd_ctx *ctx) {
             R.lo[d] = s.blo[d] + 4 * j;
             R.hi[d] = s.bhi[d] - 4 * j;
         }
-        enqueue_psi_update(ctx, 0, R, maxc);
+        enqueue_psi_update(ctx, 0, R);
         t0 = tic(ctx);
         fdtd_launch_record(ctx->storage, dd, 1, R, stepc, ctx->stream);
         toc(ctx, 2, t0);

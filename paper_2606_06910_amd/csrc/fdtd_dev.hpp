@@ -89,6 +89,7 @@ struct DevShot {
     int LX, LY, LZ, nmax;
     int SX, SY, SZ;        // layer-array strides along the slab axis: width + 1 slot that stays zero
     int ghost[3];          // 1 if the axis has ghost (loopback) faces
+    int fused;             // 1: the band kernel advances psi_x and psi_z itself, the psi pass only psi_y
     float cc;              // sum_d (c0 + 2 c1) / h_d^2
     float w2[3][5];        // (c0 + 2 c1) / h_d^2, then c_l / h_d^2 for l = 1..4
     float w1[3][5];        // d_l / h_d   (w1[d][0] unused)
@@ -137,17 +138,19 @@ struct BandItem {
 // and k = 6, the non-band box itself.  Along each axis the non-band range is
 // [a, b): a = min(lo + 4, n) with a low layer (else the box start), b =
 // max(n - hi - 4, a) with a high layer (else the box end), so that c < a or
-// c >= b is exactly the band test.
+// c >= b is exactly the band test (band_range returns a, b and the box
+// extent [e0, e1) of one axis).
+__host__ __device__ inline void band_range(int n, int Llo, int Lhi, int ghost, int ext, int &a, int &b, int &e0,
+                                           int &e1) {
+    e0 = ghost ? -ext : 0;
+    e1 = n + (ghost ? ext : 0);
+    a = Llo > 0 ? (Llo + FDTD_R < n ? Llo + FDTD_R : n) : e0;
+    b = Lhi > 0 ? (n - Lhi - FDTD_R > a ? n - Lhi - FDTD_R : a) : e1;
+}
 __host__ __device__ inline void band_box(const int n[3], const int Llo[3], const int Lhi[3], const int ghost[3],
                                          int ext, int k, int lo[3], int hi[3]) {
     int a[3], b[3];
-    for (int d = 0; d < 3; ++d) {
-        const int e0 = ghost[d] ? -ext : 0, e1 = n[d] + (ghost[d] ? ext : 0);
-        a[d] = Llo[d] > 0 ? (Llo[d] + FDTD_R < n[d] ? Llo[d] + FDTD_R : n[d]) : e0;
-        b[d] = Lhi[d] > 0 ? (n[d] - Lhi[d] - FDTD_R > a[d] ? n[d] - Lhi[d] - FDTD_R : a[d]) : e1;
-        lo[d] = e0;
-        hi[d] = e1;
-    }
+    for (int d = 0; d < 3; ++d) band_range(n[d], Llo[d], Lhi[d], ghost[d], ext, a[d], b[d], lo[d], hi[d]);
     if (k == 6) {
         for (int d = 0; d < 3; ++d) {
             lo[d] = a[d];
@@ -171,6 +174,30 @@ __host__ __device__ inline void band_box(const int n[3], const int Llo[3], const
             else lo[0] = b[0];
         }
     }
+}
+
+// x tiles of band box k (box extent [lo0, hi0) along x): BAND_TX wide from the
+// box start, except that boxes spanning all x (k < 4) cut their tiling at the
+// start of the high x band, so that the band up to the end of x is a tile
+// row of its own.  Returns the number of tiles; tile tx covers [x0, x1).
+__host__ __device__ inline int band_xtiles(int nx, int Llo, int Lhi, int k, int lo0, int hi0, int tx, int *x0,
+                                           int *x1) {
+    int cut = hi0;
+    if (k < 4) {
+        int a, b, e0, e1;
+        band_range(nx, Llo, Lhi, 0, 0, a, b, e0, e1);
+        if (b > lo0 && b < hi0) cut = b;
+    }
+    const int nlo = (cut - lo0 + BAND_TX - 1) / BAND_TX;
+    const int nhi = (hi0 - cut + BAND_TX - 1) / BAND_TX;
+    if (tx < nlo) {
+        *x0 = lo0 + tx * BAND_TX;
+        *x1 = *x0 + BAND_TX < cut ? *x0 + BAND_TX : cut;
+    } else {
+        *x0 = cut + (tx - nlo) * BAND_TX;
+        *x1 = *x0 + BAND_TX < hi0 ? *x0 + BAND_TX : hi0;
+    }
+    return nlo + nhi;
 }
 
 // ---------------------------------------------------------------------------

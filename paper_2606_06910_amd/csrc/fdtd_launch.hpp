@@ -2,7 +2,8 @@
 #pragma once
 #include "fdtd_dev.hpp"
 
-void fdtd_launch_psi(int stor, const DevShot *d_shots, int nshots, long max_count, int iu, int ext,
+// psi pre-pass over axes d0 .. d0 + nd - 1 (fused shots: y only); max_count = largest slab of those axes
+void fdtd_launch_psi(int stor, const DevShot *d_shots, int nshots, long max_count, int iu, int ext, int d0, int nd,
                      hipStream_t st);
 void fdtd_launch_naive(int stor, const DevShot *d_shots, int shot, int nx, int Ny, int Nz, const Roles &R,
                        const int *stepc, hipStream_t st);

@@ -46,19 +46,35 @@ __device__ __forceinline__ void axis_point(const DevShot &s, int d, int c, AxisP
 }
 }  // namespace
 
-template <typename T, int KIND>
+// Tile of one band box.  With FUSE (DevShot::fused) the tile also advances the
+// layer memory of x and z itself, psi <- b psi + a D1 u^n with the D1 u^n its
+// own stencil already forms, instead of reading the psi pass's result:
+//  * psi_x: every x-slab point of a row lies in the same tile row (band_xtiles
+//    gives the high x band a tile of its own), so a lane updates its own point
+//    and takes its 8 neighbours from the other lanes of the row (ds_bpermute);
+//  * psi_z (kind 0): a box holds a whole z slab and is walked in one pass, so
+//    psi_z rides in the z queue: at plane z the lane advances psi_z at z + 4,
+//    from a u^n queue that reaches z + 8.
+// Each layer point is advanced once, by the tile that owns it, with the psi
+// pass's operations, so the bits do not change.
+template <typename T, int KIND, bool FUSE>
 __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, const BandItem wi, const Roles &R,
                                           int zchunk, const int *__restrict__ stepc) {
     constexpr bool HAS_Y = KIND <= 1, HAS_Z = KIND == 0;
+    constexpr bool FZ = FUSE && HAS_Z;   // psi_z advanced in the z queue
+    constexpr int QN = FZ ? 13 : 9;      // u^n queue: planes z - 4 .. z + QN - 5
     const DevShot &s = shots[wi.shot];
     int blo[3], bhi[3];
     const int n3[3] = {s.nx, s.ny, s.nz};
     band_box(n3, s.Llo, s.Lhi, s.ghost, R.ext, wi.box, blo, bhi);
-    const int x = blo[0] + wi.tx * BAND_TX + (int)(threadIdx.x % BAND_TX);
+    int x0, x1;
+    band_xtiles(s.nx, s.Llo[0], s.Lhi[0], wi.box, blo[0], bhi[0], wi.tx, &x0, &x1);
+    const int x = x0 + (int)(threadIdx.x % BAND_TX);
     const int y = blo[1] + wi.ty * BAND_TY + (int)(threadIdx.x / BAND_TX);
-    const int za = blo[2] + wi.zc * zchunk;
-    if (x >= bhi[0] || y >= bhi[1] || za >= bhi[2]) return;   // no barriers below
-    const int zb = min(za + zchunk, bhi[2]);
+    // z boxes are walked whole (their tile list has one chunk), the others in chunks
+    const int za = KIND == 0 ? blo[2] : blo[2] + wi.zc * zchunk;
+    if (x >= x1 || y >= bhi[1] || za >= bhi[2]) return;   // no barriers below
+    const int zb = KIND == 0 ? bhi[2] : min(za + zchunk, bhi[2]);
 
     const Coef K = load_coef(s);
     float w1[3][5];
@@ -95,6 +111,24 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
 #pragma unroll
     for (int j = 0; j < 8; ++j) px_off[j] = vx_row + 4 * (uint32_t)AX.npos[j];
     const uint32_t zx_off = vx_row + 4 * (uint32_t)AX.pos;
+    // FUSE: source lanes of the 8 x neighbours within the wave and the mask of
+    // those inside the x slabs (all of them lie in this tile row); whether the
+    // tile reaches the x band at all (uniform)
+    int xsrc[8];
+    unsigned xvalid = 0;
+    bool xedge = false;
+    if constexpr (FUSE) {
+        const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int off = j < 4 ? -(j + 1) : j - 3;
+            xsrc[j] = ((lane + off) & 63) * 4;
+            xvalid |= (AX.npos[j] != s.Llo[0] + s.Lhi[0]) ? (1u << j) : 0u;
+        }
+        int a, b, e0, e1;
+        band_range(nx, s.Llo[0], s.Lhi[0], 0, 0, a, b, e0, e1);
+        xedge = x0 < a || x1 > b;
+    }
     Rsrc rpy = rpx, rpz = rpx, rpr = rpx;
     uint32_t zy_off = 0, Spy = 0, vz_col = 0, Spz = 0, zdy = 0, zdz = 0;
     if constexpr (HAS_Y) {
@@ -113,31 +147,80 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
         vz_col = (uint32_t)(((long)(y + fy) * nx + x) * 4);
         Spz = (uint32_t)((long)s.PY * nx * 4);
     }
-    // psi_z of plane p at the column, 0 outside the z slabs (uniform condition)
+    // plane p of the z slabs (uniform condition)
+    auto zslab = [&](int p) -> bool { return p >= 0 && p < nz && in_slab(p, nz, zlo, zhi); };
+    // psi_z of plane p at the column, 0 outside the z slabs
     auto psi_z_at = [&](int p) -> float {
-        if (p < 0 || p >= nz || !in_slab(p, nz, zlo, zhi)) return 0.0f;
+        if (!zslab(p)) return 0.0f;
         return Buf<float>::ld(rpz, vz_col, (uint32_t)slab_pos(p, nz, zlo, zhi) * Spz);
     };
-
-    // z queues at the column: q[o] = u(x, y, z - 4 + o); pq[o] = psi_z there (0 outside its slab)
-    float q[9], pq[9];
+    // z-axis profile f (0 b, 1 a, 2 kinv, 3 dkinv) at plane p: a load whose
+    // value every lane shares (issued with the other loads of a plane), made
+    // a scalar where it is used
+    auto zprof_ld = [&](int f, int p) -> float {
+        return Buf<float>::ld(rpr, 0, (uint32_t)(((8 + f) * s.nmax + p) * 4));
+    };
+    auto uni = [](float v) -> float {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+    };
+    // FZ: psi_z at plane p (a z-slab plane) advanced from the u^n queue entries
+    // u(p - 4) .. u(p + 4) = qq[c - 4] .. qq[c + 4] and the profiles b, a there
+    auto psi_z_new = [&](const float *qq, int c, float b, float a, float old) -> float {
+        float fl[4], fh[4];
 #pragma unroll
-    for (int o = 0; o < 8; ++o) q[o] = Buf<T>::ld(ru, vc, o * Sb);
-    if constexpr (HAS_Z) {
+        for (int l = 1; l <= 4; ++l) {
+            fl[l - 1] = qq[c - l];
+            fh[l - 1] = qq[c + l];
+        }
+        return psi_update(b, old, a, d1_axis(w1[2], fl, fh));
+    };
+    auto psi_z_store = [&](int p, float v) {
+        Buf<float>::st(rpz, vz_col, (uint32_t)slab_pos(p, nz, zlo, zhi) * Spz, v);
+    };
+
+    // z queues at the column: q[o] = u(x, y, z - 4 + o); pq[o] = psi_z at z - 4 + o (0 outside its slab)
+    float q[QN], pq[9];
+#pragma unroll
+    for (int o = 0; o < QN - 1; ++o) q[o] = Buf<T>::ld(ru, vc, o * Sb);
+    if constexpr (FZ) {
+        // planes za - 4 .. za - 1 lie outside the z slabs (the host enables FUSE
+        // only when the two z boxes share no layer point); za .. za + 3 are
+        // advanced here from q (the box is at least 5 planes deep)
+        // (every load first, then the arithmetic, then the stores)
+        float old[4], pb[4], pa[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            old[o] = psi_z_at(za + o);
+            pb[o] = zslab(za + o) ? zprof_ld(0, za + o) : 0.0f;
+            pa[o] = zslab(za + o) ? zprof_ld(1, za + o) : 0.0f;
+        }
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            pq[o] = 0.0f;
+            pq[o + 4] = zslab(za + o) ? psi_z_new(q, o + 4, uni(pb[o]), uni(pa[o]), old[o]) : 0.0f;
+        }
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+            if (zslab(za + o)) psi_z_store(za + o, pq[o + 4]);
+    } else if constexpr (HAS_Z) {
 #pragma unroll
         for (int o = 0; o < 8; ++o) pq[o] = psi_z_at(za - 4 + o);
     }
 
-    // loads of one plane (issued a plane ahead of their use)
+    // loads of one plane
     struct PL {
         float xl[4], xh[4], yl[4], yh[4];
-        float qn, second, mm;         // u^n four planes ahead, second state, m
+        float qn, second, mm;         // u^n at the queue head, second state, m
         float px[8], zx, py[8], zy;   // psi_x / psi_y neighbours, zeta_x / zeta_y
-        float pqn, zz;                // psi_z four planes ahead, zeta_z
+        float pxo;                    // FUSE: psi_x of the point before its update
+        float pqn, zz;                // psi_z four planes ahead (FZ: before its update), zeta_z
+        float zpr[4], zb4, za4;       // z profiles at the plane; FZ: b, a four planes ahead
     };
     auto load = [&](int z, PL &p) {
         const uint32_t pz = (uint32_t)(z - za + 4) * Sb;
-        p.qn = Buf<T>::ld(ru, vc, pz + 4 * Sb);
+        // FZ: the head u(z + 8) is needed only while z + 4 is a grid plane (it may lie past the frame)
+        const uint32_t vq = (!FZ || z + 4 < nz) ? vc : kBufSkip;
+        p.qn = Buf<T>::ld(ru, vq, pz + (QN - 5) * Sb);
 #pragma unroll
         for (int l = 1; l <= 4; ++l) {
             p.xl[l - 1] = Buf<T>::ld(ru, vc - (uint32_t)(l * esz), pz);
@@ -148,8 +231,13 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
         p.second = Buf<T>::ld(rs, vc, pz);
         p.mm = Buf<float>::ld(rm, vcm, (uint32_t)(z - za + 4) * Smb);
         // (a neighbour outside the slabs reads the zero slot of its row)
-        if (AX.band) {
-            const uint32_t sox = (uint32_t)(z + fz) * Spx;
+        const uint32_t sox = (uint32_t)(z + fz) * Spx;
+        if constexpr (FUSE) {
+            if (AX.slab) {
+                p.pxo = Buf<float>::ld(rpx, zx_off, sox);
+                p.zx = Buf<float>::ld(rpx, zx_off, sox + zdx);
+            }
+        } else if (AX.band) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) p.px[j] = Buf<float>::ld(rpx, px_off[j], sox);
             if (AX.slab) p.zx = Buf<float>::ld(rpx, zx_off, sox + zdx);
@@ -164,12 +252,21 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
         }
         if constexpr (HAS_Z) {
             p.pqn = psi_z_at(z + 4);
-            if (in_slab(z, nz, zlo, zhi))
-                p.zz = Buf<float>::ld(rpz, vz_col, (uint32_t)slab_pos(z, nz, zlo, zhi) * Spz + zdz);
+            if (zslab(z)) p.zz = Buf<float>::ld(rpz, vz_col, (uint32_t)slab_pos(z, nz, zlo, zhi) * Spz + zdz);
+            if (in_band(z, nz, zlo, zhi)) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) p.zpr[f] = zprof_ld(f, z);
+            }
+            if constexpr (FZ) {
+                if (zslab(z + 4)) {
+                    p.zb4 = zprof_ld(0, z + 4);
+                    p.za4 = zprof_ld(1, z + 4);
+                }
+            }
         }
     };
-    auto compute = [&](int z, const PL &p) {
-        q[8] = p.qn;
+    auto compute = [&](int z, PL &p) {
+        q[QN - 1] = p.qn;
         float zl[4], zh[4];
 #pragma unroll
         for (int l = 1; l <= 4; ++l) {
@@ -177,6 +274,22 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
             zh[l - 1] = q[4 + l];
         }
         const float c = q[4];
+        if constexpr (FUSE) {
+            // psi_x of the point, then its neighbours from the lanes of the row
+            float pn = 0.0f;
+            if (AX.slab) {
+                pn = psi_update(AX.b, p.pxo, AX.a, d1_axis(w1[0], p.xl, p.xh));
+                Buf<float>::st(rpx, zx_off, (uint32_t)(z + fz) * Spx, pn);
+            }
+            if (xedge) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const float v = __builtin_bit_cast(
+                        float, __builtin_amdgcn_ds_bpermute(xsrc[j], __builtin_bit_cast(int, pn)));
+                    p.px[j] = (xvalid >> j) & 1u ? v : 0.0f;
+                }
+            }
+        }
         float pl[3][4], ph[3][4], zo[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
@@ -194,20 +307,23 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
         AZ.pos = 0;
         AZ.b = AZ.a = AZ.kinv = AZ.dkinv = 0.0f;
         if constexpr (HAS_Z) {
-            pq[8] = p.pqn;
+            if constexpr (FZ) {
+                pq[8] = 0.0f;
+                if (zslab(z + 4)) {
+                    pq[8] = psi_z_new(q, 8, uni(p.zb4), uni(p.za4), p.pqn);
+                    psi_z_store(z + 4, pq[8]);
+                }
+            } else {
+                pq[8] = p.pqn;
+            }
             AZ.band = in_band(z, nz, zlo, zhi);
             AZ.slab = AZ.band && in_slab(z, nz, zlo, zhi);
             AZ.pos = AZ.slab ? slab_pos(z, nz, zlo, zhi) : 0;
             if (AZ.band) {
-                const uint32_t pr = (uint32_t)((8 * s.nmax + z) * 4), pn = (uint32_t)(s.nmax * 4);
-                AZ.b = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                                     __builtin_bit_cast(int, Buf<float>::ld(rpr, 0, pr))));
-                AZ.a = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                                     __builtin_bit_cast(int, Buf<float>::ld(rpr, 0, pr + pn))));
-                AZ.kinv = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                                        __builtin_bit_cast(int, Buf<float>::ld(rpr, 0, pr + 2 * pn))));
-                AZ.dkinv = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                                         __builtin_bit_cast(int, Buf<float>::ld(rpr, 0, pr + 3 * pn))));
+                AZ.b = uni(p.zpr[0]);
+                AZ.a = uni(p.zpr[1]);
+                AZ.kinv = uni(p.zpr[2]);
+                AZ.dkinv = uni(p.zpr[3]);
             }
 #pragma unroll
             for (int l = 1; l <= 4; ++l) {
@@ -248,7 +364,7 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
                 if (slb[2]) Buf<float>::st(rpz, vz_col, (uint32_t)AZ.pos * Spz + zdz, zn[2]);
         }
 #pragma unroll
-        for (int o = 0; o < 8; ++o) q[o] = q[o + 1];
+        for (int o = 0; o < QN - 1; ++o) q[o] = q[o + 1];
         if constexpr (HAS_Z) {
 #pragma unroll
             for (int o = 0; o < 8; ++o) pq[o] = pq[o + 1];
@@ -270,9 +386,15 @@ __global__ __launch_bounds__(256) void k_band(const DevShot *__restrict__ shots,
                                               Roles R, int zchunk, const int *__restrict__ stepc) {
     const BandItem wi = work[blockIdx.x];
     const int kind = wi.box >> 1;
-    if (kind == 0) band_tile<T, 0>(shots, wi, R, zchunk, stepc);
-    else if (kind == 1) band_tile<T, 1>(shots, wi, R, zchunk, stepc);
-    else band_tile<T, 2>(shots, wi, R, zchunk, stepc);
+    if (shots[wi.shot].fused) {
+        if (kind == 0) band_tile<T, 0, true>(shots, wi, R, zchunk, stepc);
+        else if (kind == 1) band_tile<T, 1, true>(shots, wi, R, zchunk, stepc);
+        else band_tile<T, 2, true>(shots, wi, R, zchunk, stepc);
+    } else {
+        if (kind == 0) band_tile<T, 0, false>(shots, wi, R, zchunk, stepc);
+        else if (kind == 1) band_tile<T, 1, false>(shots, wi, R, zchunk, stepc);
+        else band_tile<T, 2, false>(shots, wi, R, zchunk, stepc);
+    }
 }
 
 template <typename T>

@@ -29,16 +29,18 @@ __device__ __forceinline__ Box shot_box(const DevShot &s, int ext) {
 }
 
 // ---------------------------------------------------------------------------
-// psi pre-pass.  grid: (blocks over the largest slab, 3 axes, shots)
+// psi pre-pass.  grid: (blocks over the largest slab, axes d0 .., shots); a
+// shot whose band kernel advances psi_x and psi_z itself (fused) has only
+// psi_y done here
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_psi(const DevShot *__restrict__ shots, int iu, int ext) {
+__global__ __launch_bounds__(256) void k_psi(const DevShot *__restrict__ shots, int iu, int ext, int d0) {
     typedef __attribute__((address_space(1))) const T gT;
     typedef __attribute__((address_space(1))) float gf;
     const DevShot &s = shots[blockIdx.z];
-    const int d = blockIdx.y;
+    const int d = d0 + (int)blockIdx.y;
     const int lo = s.Llo[d], hi = s.Lhi[d];
-    if (lo + hi == 0) return;
+    if (lo + hi == 0 || (s.fused && d != 1)) return;
     const Box bx = shot_box(s, ext);
     const unsigned Ny = bx.yhi - bx.ylo, Nz = bx.zhi - bx.zlo;
     // slab points as (a fastest, b, c): x-slab (is, y, z), y-slab (x, js, z), z-slab (x, y, ks)
@@ -390,10 +392,11 @@ __global__ __launch_bounds__(1024) void k_record(const DevShot *__restrict__ sho
 // host-side launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-static void launch_psi_t(const DevShot *d_shots, int nshots, long max_count, int iu, int ext, hipStream_t st) {
-    if (max_count <= 0) return;
-    dim3 grid((unsigned)((max_count + 255) / 256), 3, nshots);
-    hipLaunchKernelGGL(k_psi<T>, grid, dim3(256), 0, st, d_shots, iu, ext);
+static void launch_psi_t(const DevShot *d_shots, int nshots, long max_count, int iu, int ext, int d0, int nd,
+                         hipStream_t st) {
+    if (max_count <= 0 || nd <= 0) return;
+    dim3 grid((unsigned)((max_count + 255) / 256), nd, nshots);
+    hipLaunchKernelGGL(k_psi<T>, grid, dim3(256), 0, st, d_shots, iu, ext, d0);
 }
 template <typename T>
 static void launch_naive_t(const DevShot *d_shots, int shot, int nx, int Ny, int Nz, const Roles &R,
@@ -434,9 +437,9 @@ static void launch_record_t(const DevShot *d_shots, int nshots, const Roles &R, 
         else F<float>(__VA_ARGS__);                                                                       \
     } while (0)
 
-void fdtd_launch_psi(int stor, const DevShot *d_shots, int nshots, long max_count, int iu, int ext,
+void fdtd_launch_psi(int stor, const DevShot *d_shots, int nshots, long max_count, int iu, int ext, int d0, int nd,
                      hipStream_t st) {
-    FDTD_DISPATCH(stor, launch_psi_t, d_shots, nshots, max_count, iu, ext, st);
+    FDTD_DISPATCH(stor, launch_psi_t, d_shots, nshots, max_count, iu, ext, d0, nd, st);
 }
 void fdtd_launch_naive(int stor, const DevShot *d_shots, int shot, int nx, int Ny, int Nz, const Roles &R,
                        const int *stepc, hipStream_t st) {

@@ -73,6 +73,13 @@ CASES = {
     "someface": dict(n=(48, 40, 36), h=(10.0, 10.0, 10.0), cpml=(0, 9, 6, 0, 0, 7), nt=60, seed=4),
     # smallest grid the stencil allows, with the widest layer it allows
     "tiny": dict(n=(9, 9, 9), h=(10.0, 10.0, 10.0), cpml=(4,) * 6, nt=30, seed=5, src=(4, 4, 4)),
+    # x layers wider than a band tile row (28 + 4 > 32 on the low face): the band
+    # kernel reads psi_x from the psi pass instead of advancing it itself
+    "widex": dict(n=(80, 36, 40), h=(10.0, 10.0, 10.0), cpml=(30, 12, 5, 4, 6, 5), nt=50, seed=6),
+    # z layers whose bands read each other's layer points (nz < Llo + Lhi + 8)
+    "nearz": dict(n=(40, 30, 20), h=(10.0, 10.0, 10.0), cpml=(5, 6, 4, 4, 6, 7), nt=50, seed=7, src=(20, 15, 10)),
+    # high x band straddling a 32-column boundary (its own tile row), x-only layers
+    "xcut": dict(n=(75, 33, 30), h=(10.0, 10.0, 10.0), cpml=(9, 13, 0, 0, 0, 0), nt=60, seed=8),
 }
 
 
