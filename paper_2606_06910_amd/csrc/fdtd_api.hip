@@ -67,10 +67,10 @@ static void plan_shot(ShotH &s) {
     s.LX = s.Llo[0] + s.Lhi[0];
     s.LY = s.Llo[1] + s.Lhi[1];
     s.LZ = s.Llo[2] + s.Lhi[2];
-    s.SX = s.LX ? s.LX + 1 : 0;
+    s.WX = std::max(s.Llo[0], s.Lhi[0]);
     s.SY = s.LY ? s.LY + 1 : 0;
     s.SZ = s.LZ ? s.LZ + 1 : 0;
-    s.psi_elems[0] = (size_t)(s.nz + 2 * s.fz) * s.PY * s.SX;
+    s.psi_elems[0] = (size_t)2 * (s.nz + 2 * s.fz) * s.PY * s.WX;
     s.psi_elems[1] = (size_t)(s.nz + 2 * s.fz) * s.SY * s.nx;
     s.psi_elems[2] = (size_t)s.SZ * s.PY * s.nx;
     s.nmax = std::max(s.nx, std::max(s.ny, s.nz));
@@ -368,7 +368,7 @@ static void fill_desc(fdtd_ctx *ctx, int i) {
     D.LX = s.LX;
     D.LY = s.LY;
     D.LZ = s.LZ;
-    D.SX = s.SX;
+    D.WX = s.WX;
     D.SY = s.SY;
     D.SZ = s.SZ;
     D.nmax = s.nmax;
@@ -423,13 +423,16 @@ static void build_jobs(fdtd_ctx *ctx, int i, std::vector<CopyJob> (&jobs)[2][4],
         fs.push_back(F{un, (int)s.esz, s.nx, (long)s.P, (long)s.S, s.g});
         if (s.g - 4 > 0) {
             fs.push_back(F{um, (int)s.esz, s.nx, (long)s.P, (long)s.S, s.g - 4});
-            if (s.LX > 0) {
-                for (int w = 0; w < 2; ++w) {
-                    char *base = wsp(ctx, w == 0 ? s.o_psi[0] : s.o_zeta[0]);
-                    char *org = base + ((size_t)s.fz * s.PY + s.fy) * s.SX * 4;
-                    fs.push_back(F{org, 4, s.LX, (long)s.SX, (long)s.PY * s.SX, s.g - 4});
+            // x layer arrays: the two layers are blocks of their own (psi_index)
+            for (int w = 0; w < 2; ++w)
+                for (int side = 0; side < 2; ++side) {
+                    const int ex = side == 0 ? s.Llo[0] : s.Lhi[0];
+                    if (ex <= 0) continue;
+                    char *base = wsp(ctx, w == 0 ? s.o_psi[0] : s.o_zeta[0]) +
+                                 (size_t)side * (s.nz + 2 * s.fz) * s.PY * s.WX * 4;
+                    char *org = base + ((size_t)s.fz * s.PY + s.fy) * s.WX * 4;
+                    fs.push_back(F{org, 4, ex, (long)s.WX, (long)s.PY * s.WX, s.g - 4});
                 }
-            }
         }
         // phase y
         size_t off = 0;
@@ -489,9 +492,9 @@ static size_t xbuf_bytes(const ShotH &s) {
     };
     add((int)s.esz, s.nx, s.g);
     add((int)s.esz, s.nx, s.g - 4);
-    if (s.LX > 0) {
-        add(4, s.LX, s.g - 4);
-        add(4, s.LX, s.g - 4);
+    for (int w = 0; w < 2; ++w) {
+        if (s.Llo[0] > 0) add(4, s.Llo[0], s.g - 4);
+        if (s.Lhi[0] > 0) add(4, s.Lhi[0], s.g - 4);
     }
     return std::max(by, bz);
 }

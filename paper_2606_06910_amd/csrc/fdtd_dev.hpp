@@ -87,7 +87,8 @@ struct DevShot {
     int nx, ny, nz, P, PY, S, fy, fz;
     int Llo[3], Lhi[3];
     int LX, LY, LZ, nmax;
-    int SX, SY, SZ;        // layer-array strides along the slab axis: width + 1 slot that stays zero
+    int WX;                // x layer arrays: row width, max(Llo[0], Lhi[0])
+    int SY, SZ;            // y, z layer arrays: strides along the slab axis, width + 1 slot that stays zero
     int ghost[3];          // 1 if the axis has ghost (loopback) faces
     int fused;             // 1: the band kernel advances psi_x and psi_z itself, the psi pass only psi_y
     float cc;              // sum_d (c0 + 2 c1) / h_d^2
@@ -213,11 +214,18 @@ __device__ __forceinline__ bool in_band(int c, int n, int lo, int hi) {
 __device__ __forceinline__ int slab_pos(int c, int n, int lo, int hi) {
     return c < lo ? c : lo + (c - (n - hi));
 }
-// element index of (x, y, z) in the compact psi/zeta array of axis d: x
-// [z+fz][y+fy][SX], y [z+fz][SY][nx], z [SZ][y+fy][nx]; slab position LX (LY,
-// LZ) is an extra slot that is never written and reads zero
+// element index of (x, y, z) in the compact psi/zeta array of axis d:
+//   x [side][z+fz][y+fy][WX]: side 0 the low layer (position x), side 1 the
+//     high layer (position x - (nx - Lhi)), so that a tile row of one layer
+//     is contiguous;
+//   y [z+fz][SY][nx] and z [SZ][y+fy][nx], slab position LY (LZ) being an
+//     extra slot that is never written and reads zero.
 __device__ __forceinline__ long psi_index(const DevShot &s, int d, int x, int y, int z) {
-    if (d == 0) return ((long)(z + s.fz) * s.PY + (y + s.fy)) * s.SX + slab_pos(x, s.nx, s.Llo[0], s.Lhi[0]);
+    if (d == 0) {
+        const long row = ((long)(z + s.fz) * s.PY + (y + s.fy)) * s.WX;
+        if (x < s.Llo[0]) return row + x;
+        return (long)(s.nz + 2 * s.fz) * s.PY * s.WX + row + (x - (s.nx - s.Lhi[0]));
+    }
     if (d == 1) return ((long)(z + s.fz) * s.SY + slab_pos(y, s.ny, s.Llo[1], s.Lhi[1])) * s.nx + x;
     return ((long)slab_pos(z, s.nz, s.Llo[2], s.Lhi[2]) * s.PY + (y + s.fy)) * s.nx + x;
 }

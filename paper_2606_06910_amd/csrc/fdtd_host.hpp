@@ -26,7 +26,8 @@ struct ShotH {
     size_t esz = 4;            // bytes per stored field element
     int Llo[3] = {0, 0, 0}, Lhi[3] = {0, 0, 0};
     int LX = 0, LY = 0, LZ = 0, nmax = 0;
-    int SX = 0, SY = 0, SZ = 0;   // psi/zeta strides: slab width + 1 zero slot (0 without layers)
+    int WX = 0;                 // x psi/zeta row width: max(Llo[0], Lhi[0])
+    int SY = 0, SZ = 0;         // y, z psi/zeta strides: slab width + 1 zero slot (0 without layers)
     size_t psi_elems[3] = {0, 0, 0};
     // workspace offsets
     size_t o_u[4] = {0, 0, 0, 0}, o_d = 0, o_m = 0, o_psi[3] = {0, 0, 0}, o_zeta[3] = {0, 0, 0}, o_prof = 0;

@@ -105,12 +105,21 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
     // psi_d and zeta_d of an axis through one descriptor (zeta_d follows psi_d in the workspace)
     const Rsrc rpx = make_rsrc(s.psi[0]);
     const uint32_t zdx = (uint32_t)((const char *)s.zeta[0] - (const char *)s.psi[0]);
-    const uint32_t vx_row = (uint32_t)((long)(y + fy) * s.SX * 4);   // psi_x, zeta_x row (+ 4 slab pos)
-    const uint32_t Spx = (uint32_t)((long)s.PY * s.SX * 4);          // psi_x, zeta_x plane
+    // psi_x, zeta_x (psi_index layout): byte offset of (x', y) within a plane of
+    // either layer block, plane stride Spx; a neighbour outside the slabs reads
+    // zero through an out-of-range offset
+    const int xlo = s.Llo[0], xhi = s.Lhi[0];
+    const uint32_t Spx = (uint32_t)((long)s.PY * s.WX * 4);
+    const uint32_t xhib = (uint32_t)((long)(s.nz + 2 * fz) * s.PY * s.WX * 4);
+    const uint32_t vx_row = (uint32_t)((long)(y + fy) * s.WX * 4);
+    auto xoff = [&](int xp) -> uint32_t {
+        return xp < xlo ? vx_row + 4 * (uint32_t)xp : xhib + vx_row + 4 * (uint32_t)(xp - (nx - xhi));
+    };
     uint32_t px_off[8], py_off[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) px_off[j] = vx_row + 4 * (uint32_t)AX.npos[j];
-    const uint32_t zx_off = vx_row + 4 * (uint32_t)AX.pos;
+    for (int j = 0; j < 8; ++j)
+        px_off[j] = AX.npos[j] != xlo + xhi ? xoff(j < 4 ? x - (j + 1) : x + (j - 3)) : kBufSkip;
+    const uint32_t zx_off = AX.slab ? xoff(x) : 0u;
     // FUSE: source lanes of the 8 x neighbours within the wave and the mask of
     // those inside the x slabs (all of them lie in this tile row); whether the
     // tile reaches the x band at all (uniform)
@@ -123,7 +132,7 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
         for (int j = 0; j < 8; ++j) {
             const int off = j < 4 ? -(j + 1) : j - 3;
             xsrc[j] = ((lane + off) & 63) * 4;
-            xvalid |= (AX.npos[j] != s.Llo[0] + s.Lhi[0]) ? (1u << j) : 0u;
+            xvalid |= (AX.npos[j] != xlo + xhi) ? (1u << j) : 0u;
         }
         int a, b, e0, e1;
         band_range(nx, s.Llo[0], s.Lhi[0], 0, 0, a, b, e0, e1);
@@ -230,7 +239,7 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
         }
         p.second = Buf<T>::ld(rs, vc, pz);
         p.mm = Buf<float>::ld(rm, vcm, (uint32_t)(z - za + 4) * Smb);
-        // (a neighbour outside the slabs reads the zero slot of its row)
+        // (a y neighbour outside the slabs reads the zero slot of its row)
         const uint32_t sox = (uint32_t)(z + fz) * Spx;
         if constexpr (FUSE) {
             if (AX.slab) {

@@ -47,7 +47,12 @@ __global__ __launch_bounds__(256) void k_psi(const DevShot *__restrict__ shots, 
     const unsigned W = d == 0 ? (unsigned)s.LX : (unsigned)s.nx;
     const unsigned M = d == 1 ? (unsigned)s.LY : Ny;
     const unsigned N = d == 2 ? (unsigned)s.LZ : Nz;
-    const unsigned t = blockIdx.x * 256u + threadIdx.x;
+    // workgroups go to the 8 XCDs in turn; give each XCD a contiguous range of
+    // logical blocks (the grid is a multiple of 8), so that the u rows that
+    // neighbouring slab rows share are read through one L2
+    const unsigned per = gridDim.x >> 3;
+    const unsigned lb = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    const unsigned t = lb * 256u + threadIdx.x;
     if (t >= W * M * N) return;
     const unsigned r = t / W, a = t - r * W;
     const unsigned c = r / M, b = r - c * M;
@@ -395,7 +400,7 @@ template <typename T>
 static void launch_psi_t(const DevShot *d_shots, int nshots, long max_count, int iu, int ext, int d0, int nd,
                          hipStream_t st) {
     if (max_count <= 0 || nd <= 0) return;
-    dim3 grid((unsigned)((max_count + 255) / 256), nd, nshots);
+    dim3 grid((unsigned)((max_count + 255) / 256 + 7) / 8 * 8, nd, nshots);
     hipLaunchKernelGGL(k_psi<T>, grid, dim3(256), 0, st, d_shots, iu, ext, d0);
 }
 template <typename T>
