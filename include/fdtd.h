@@ -92,8 +92,10 @@ typedef struct {
 /* Create a context for nshots shots on hip_stream (a hipStream_t, may be NULL
  * for the null stream).  Validates every shot (EINVAL for bad shapes, layers
  * wider than half an axis, bad faces, a field plane above 64 MiB (e.g.
- * more than about 4000 x 4000 FP32 points) or a layer array above 1 GiB,
- * which the kernels' 32-bit offsets cannot address; EUNSTABLE is checked at
+ * more than about 4000 x 4000 FP32 points) or above 2 GiB / (W + 12) with W
+ * the larger of 32 and the widest z layer + 4 (about 46 MiB with layers up
+ * to 28 cells), or a layer array above 1 GiB, which the kernels' 32-bit
+ * offsets cannot address; EUNSTABLE is checked at
  * fdtd_set_velocity, once the velocity is known).  *out receives the context
  * (host memory owned by the library; free with fdtd_destroy). */
 int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream, fdtd_ctx **out);

@@ -613,16 +613,19 @@ static void enqueue_psi_update(fdtd_ctx *ctx, int shot, const Roles &R) {
         }
         toc(ctx, 0, t0, side);
     }
-    // psi pass: psi_y only when every shot of the launch is fused, else all axes
-    // (the kernel skips x and z of fused shots)
+    // psi pass: psi_y along y lines; psi_x and psi_z of shots that are not
+    // fused (the kernel skips the fused ones)
     bool all_fused = true;
-    for (int i = lo; i < hi; ++i) all_fused = all_fused && shot_fused(ctx->shots[i]);
-    const int d0 = all_fused ? 1 : 0, nd = all_fused ? 1 : 3;
-    long maxc = 0;
-    for (int i = lo; i < hi; ++i)
-        for (int d = d0; d < d0 + nd; ++d) maxc = std::max(maxc, psi_count(ctx->shots[i], d, ext));
+    long maxc = 0, maxl = 0;
+    for (int i = lo; i < hi; ++i) {
+        const ShotH &si = ctx->shots[i];
+        all_fused = all_fused && shot_fused(si);
+        maxc = std::max(maxc, std::max(psi_count(si, 0, ext), psi_count(si, 2, ext)));
+        if (si.LY > 0) maxl = std::max(maxl, (long)si.nx * (si.nz + (si.gz ? 2 * ext : 0)));
+    }
     hipEvent_t t0 = tic(ctx);
-    fdtd_launch_psi(stor, dd + lo, hi - lo, maxc, R.iu, ext, d0, nd, ctx->stream);
+    fdtd_launch_psi_y(stor, dd + lo, hi - lo, maxl, R.iu, ext, ctx->stream);
+    if (!all_fused) fdtd_launch_psi(stor, dd + lo, hi - lo, maxc, R.iu, ext, 0, 3, ctx->stream);
     toc(ctx, 1, t0);
     if (any_zm) {
         t0 = tic(ctx);
@@ -837,12 +840,16 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
         ShotH s;
         s.c = shots[i];
         plan_shot(s);
-        // kernels address a field plane, and a layer array, with 32-bit offsets
-        bool big = (size_t)s.S * s.esz > ((size_t)1 << 26);
+        // kernels address a field plane, and a layer array, with 32-bit offsets;
+        // the band kernel reaches up to its z walk (a whole z box, or a chunk of
+        // kBandZ planes) plus 12 planes from one descriptor
+        const size_t walk = (size_t)std::max(kBandZ, std::max(s.Llo[2], s.Lhi[2]) + FDTD_R) + 12;
+        bool big = (size_t)s.S * s.esz > ((size_t)1 << 26) || walk * s.S * s.esz >= ((size_t)1 << 31);
         for (int d = 0; d < 3; ++d) big = big || 2 * s.psi_elems[d] * 4 > ((size_t)1 << 31) - 4096;
         if (big) {
             delete ctx;
-            fprintf(stderr, "fdtd_create: shot %d: a field plane above 64 MiB or a layer array above 1 GiB\n", i);
+            fprintf(stderr, "fdtd_create: shot %d: a field plane above 64 MiB or 2 GiB / (z walk + 12 planes), "
+                            "or a layer array above 1 GiB\n", i);
             return FDTD_EINVAL;
         }
         if (s.gy || s.gz) {

@@ -2,9 +2,12 @@
 #pragma once
 #include "fdtd_dev.hpp"
 
-// psi pre-pass over axes d0 .. d0 + nd - 1 (fused shots: y only); max_count = largest slab of those axes
+// psi pre-pass of x and z over axes d0 .. d0 + nd - 1 (y and fused shots skipped); max_count =
+// largest slab of those axes
 void fdtd_launch_psi(int stor, const DevShot *d_shots, int nshots, long max_count, int iu, int ext, int d0, int nd,
                      hipStream_t st);
+// psi_y pre-pass along y lines; max_lines = largest nx * Nz of the shots
+void fdtd_launch_psi_y(int stor, const DevShot *d_shots, int nshots, long max_lines, int iu, int ext, hipStream_t st);
 void fdtd_launch_naive(int stor, const DevShot *d_shots, int shot, int nx, int Ny, int Nz, const Roles &R,
                        const int *stepc, hipStream_t st);
 void fdtd_launch_zmarch(int stor, const DevShot *d_shots, const WorkItem *work, int nwork, int ry, const Roles &R,

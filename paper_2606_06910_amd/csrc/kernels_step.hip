@@ -29,9 +29,8 @@ __device__ __forceinline__ Box shot_box(const DevShot &s, int ext) {
 }
 
 // ---------------------------------------------------------------------------
-// psi pre-pass.  grid: (blocks over the largest slab, axes d0 .., shots); a
-// shot whose band kernel advances psi_x and psi_z itself (fused) has only
-// psi_y done here
+// psi pre-pass of x and z (shots whose band kernel does not advance them
+// itself).  grid: (blocks over the largest slab, axes d0 .., shots)
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_psi(const DevShot *__restrict__ shots, int iu, int ext, int d0) {
@@ -40,7 +39,7 @@ __global__ __launch_bounds__(256) void k_psi(const DevShot *__restrict__ shots, 
     const DevShot &s = shots[blockIdx.z];
     const int d = d0 + (int)blockIdx.y;
     const int lo = s.Llo[d], hi = s.Lhi[d];
-    if (lo + hi == 0 || (s.fused && d != 1)) return;
+    if (lo + hi == 0 || d == 1 || s.fused) return;   // psi_y: k_psi_y
     const Box bx = shot_box(s, ext);
     const unsigned Ny = bx.yhi - bx.ylo, Nz = bx.zhi - bx.zlo;
     // slab points as (a fastest, b, c): x-slab (is, y, z), y-slab (x, js, z), z-slab (x, y, ks)
@@ -84,6 +83,53 @@ __global__ __launch_bounds__(256) void k_psi(const DevShot *__restrict__ shots, 
     const float d1 = d1_axis(s.w1[d], fl, fh);
     gf *pp = (gf *)s.psi[d] + psi_index(s, d, x, y, z);
     *pp = psi_update(prof_at(s, d, 0, k), *pp, prof_at(s, d, 1, k), d1);
+}
+
+// psi_y pre-pass along y: one thread per (x, z) line and layer side walks the
+// side's slab rows with a 9-row register queue of u^n, so that each u row is
+// read once per line, not once per neighbour that uses it.  grid: (blocks
+// over the largest nx * Nz, 2 sides, shots)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_psi_y(const DevShot *__restrict__ shots, int iu, int ext) {
+    typedef __attribute__((address_space(1))) const T gT;
+    typedef __attribute__((address_space(1))) float gf;
+    const DevShot &s = shots[blockIdx.z];
+    const int side = (int)blockIdx.y;
+    const int L = side ? s.Lhi[1] : s.Llo[1];
+    if (L == 0) return;
+    const Box bx = shot_box(s, ext);
+    const unsigned nx = (unsigned)s.nx, Nz = (unsigned)(bx.zhi - bx.zlo);
+    // contiguous ranges of lines per XCD (as in k_psi)
+    const unsigned per = gridDim.x >> 3;
+    const unsigned lb = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    const unsigned t = lb * 256u + threadIdx.x;
+    if (t >= nx * Nz) return;
+    const int x = (int)(t % nx), z = bx.zlo + (int)(t / nx);
+    const int y0 = side ? s.ny - s.Lhi[1] : 0;
+    const long P = s.P;
+    gT *u = (gT *)s.u[iu] + ((long)z * s.S + x);   // element (x, y, z) at u[y P]
+    gf *pp = (gf *)s.psi[1] + psi_index(s, 1, x, y0, z);
+    float w[5];
+#pragma unroll
+    for (int l = 0; l < 5; ++l) w[l] = s.w1[1][l];
+    float q[9];   // q[o] = u(x, y - 4 + o, z)
+#pragma unroll
+    for (int o = 0; o < 8; ++o) q[o] = (float)u[(long)(y0 - 4 + o) * P];
+    for (int j = 0; j < L; ++j) {
+        const int y = y0 + j;
+        q[8] = (float)u[(long)(y + 4) * P];
+        float fl[4], fh[4];
+#pragma unroll
+        for (int l = 1; l <= 4; ++l) {
+            fl[l - 1] = q[4 - l];
+            fh[l - 1] = q[4 + l];
+        }
+        const float d1 = d1_axis(w, fl, fh);
+        pp[(long)j * nx] = psi_update(prof_at(s, 1, 0, y), pp[(long)j * nx], prof_at(s, 1, 1, y), d1);
+#pragma unroll
+        for (int o = 0; o < 8; ++o) q[o] = q[o + 1];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -404,6 +450,12 @@ static void launch_psi_t(const DevShot *d_shots, int nshots, long max_count, int
     hipLaunchKernelGGL(k_psi<T>, grid, dim3(256), 0, st, d_shots, iu, ext, d0);
 }
 template <typename T>
+static void launch_psi_y_t(const DevShot *d_shots, int nshots, long max_lines, int iu, int ext, hipStream_t st) {
+    if (max_lines <= 0) return;
+    dim3 grid((unsigned)((max_lines + 255) / 256 + 7) / 8 * 8, 2, nshots);
+    hipLaunchKernelGGL(k_psi_y<T>, grid, dim3(256), 0, st, d_shots, iu, ext);
+}
+template <typename T>
 static void launch_naive_t(const DevShot *d_shots, int shot, int nx, int Ny, int Nz, const Roles &R,
                            const int *stepc, hipStream_t st) {
     dim3 grid((nx + 63) / 64, (Ny + 3) / 4, Nz);
@@ -445,6 +497,9 @@ static void launch_record_t(const DevShot *d_shots, int nshots, const Roles &R, 
 void fdtd_launch_psi(int stor, const DevShot *d_shots, int nshots, long max_count, int iu, int ext, int d0, int nd,
                      hipStream_t st) {
     FDTD_DISPATCH(stor, launch_psi_t, d_shots, nshots, max_count, iu, ext, d0, nd, st);
+}
+void fdtd_launch_psi_y(int stor, const DevShot *d_shots, int nshots, long max_lines, int iu, int ext, hipStream_t st) {
+    FDTD_DISPATCH(stor, launch_psi_y_t, d_shots, nshots, max_lines, iu, ext, st);
 }
 void fdtd_launch_naive(int stor, const DevShot *d_shots, int shot, int nx, int Ny, int Nz, const Roles &R,
                        const int *stepc, hipStream_t st) {

@@ -63,6 +63,9 @@ def _create(cfgs):
     dict(variant=9),
     dict(variant=3, tblock_k=3),
     dict(field_scale=3.0),
+    # a 49 MB FP32 plane: below 64 MiB, but the band kernel's z walk (32 planes
+    # + 12) from one descriptor would pass the 2^31-byte offset range
+    dict(n=(3500, 3500, 20), cpml=(5,) * 6),
 ])
 def test_create_rejects_invalid_configs(bad):
     from paper_2606_06910_amd import _lib
