@@ -22,14 +22,15 @@ PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
 COPY_CEILING_GBS = 5090.0   # plain 1 GiB device copy, read + write (copy_1GiB_counters.txt)
 
 
+def slab_points_axis(n, cpml, d):
+    """Points inside axis d's layers (rho_d > 0)."""
+    nx, ny, nz = n
+    return (cpml[2 * d] + cpml[2 * d + 1]) * (ny * nz, nx * nz, nx * ny)[d]
+
+
 def slab_points(n, cpml):
     """Points inside each axis' layer (rho > 0), summed over the axes."""
-    nx, ny, nz = n
-    tot = 0
-    for d, (lo, hi) in enumerate([(cpml[0], cpml[1]), (cpml[2], cpml[3]), (cpml[4], cpml[5])]):
-        other = (ny * nz, nx * nz, nx * ny)[d]
-        tot += (lo + hi) * other
-    return tot
+    return sum(slab_points_axis(n, cpml, d) for d in range(3))
 
 
 def band_split(n, cpml):
@@ -52,15 +53,17 @@ def interior_kernel_bytes(n, cpml, field_bytes=4):
 
 
 def band_kernel_bytes(n, cpml, field_bytes=4):
-    """Algorithmic bytes of one band launch: the four arrays per band point,
-    plus per layer point and axis a read of psi and a read + write of zeta."""
-    return (3 * field_bytes + 4) * band_split(n, cpml)[1] + 12 * slab_points(n, cpml)
+    """Algorithmic bytes of one band launch (layer memory of x and z advanced
+    in the kernel): the four arrays per band point, a read + write of zeta per
+    layer point and axis, a read + write of psi_x and psi_z, a read of psi_y."""
+    sx, sy, sz = (slab_points_axis(n, cpml, d) for d in range(3))
+    return (3 * field_bytes + 4) * band_split(n, cpml)[1] + 8 * (sx + sy + sz) + 8 * (sx + sz) + 4 * sy
 
 
 def psi_kernel_bytes(n, cpml, field_bytes=4):
-    """Algorithmic bytes of one psi pre-pass: per layer point and axis read u,
-    read and write psi."""
-    return (field_bytes + 8) * slab_points(n, cpml)
+    """Algorithmic bytes of one psi pre-pass (psi_y only): per y-layer point
+    read u, read and write psi_y."""
+    return (field_bytes + 8) * slab_points_axis(n, cpml, 1)
 
 
 def step_bytes(n, cpml, field_bytes=4):
@@ -443,7 +446,9 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 naive, 2 z-march, 3 temporal blocking")
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--compare", action="store_true", help="also time the other kernel variants")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip timing the other kernel variants (naive, temporal blocking)")
+    ap.add_argument("--compare", action="store_true", help="(default; kept for old command lines)")
     ap.add_argument("--eager", action="store_true", help="launch every step eagerly (no HIP graph)")
     ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage and batched-shot legs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -451,8 +456,9 @@ def main():
     ap.add_argument("--kernel-timing", action="store_true",
                     help="only run the per-kernel timing pass (the launches a profiler summary is taken over)")
     ap.add_argument("--leg", choices=sorted(LEGS), help="only run one extra leg and print its JSON")
-    ap.add_argument("--storage-leg", action="store_true",
-                    help="also run the 768^3 FP32/FP16/BF16 storage leg (off by default, see DESIGN.md)")
+    ap.add_argument("--no-storage-leg", action="store_true",
+                    help="skip the 768^3 FP32/FP16/BF16 storage leg")
+    ap.add_argument("--storage-leg", action="store_true", help="(default; kept for old command lines)")
     args = ap.parse_args()
     if args.leg:
         print(json.dumps(LEGS[args.leg]()), flush=True)
@@ -526,7 +532,7 @@ def main():
         "kernel_ms": {k: round(v[0], 5) for k, v in tm.items() if v[1] > 0},
         "kernel_algorithmic_gbs": kgbs,
     }
-    if args.compare:
+    if not args.no_compare:
         var = {}
         Kc = min(K, 200)
         for name, vv, kk in (("naive", 1, 1), ("zmarch", 2, 1), ("tblock2", 3, 2), ("tblock4", 3, 4)):
@@ -537,7 +543,7 @@ def main():
     if not args.no_extra:
         torch.cuda.empty_cache()
         legs = ["batched_24", "small_64", "pencil_1024x384x384", "adjoint_3_smallest"]
-        if args.storage_leg:
+        if not args.no_storage_leg:
             legs.insert(0, "storage_768")
         for name in legs:
             print("bench: %s leg" % name, file=sys.stderr, flush=True)
