@@ -75,21 +75,48 @@ static void plan_shot(ShotH &s) {
     s.psi_elems[2] = (size_t)s.SZ * s.PY * s.nx;
     s.nmax = std::max(s.nx, std::max(s.ny, s.nz));
     s.variant = c.variant == FDTD_VARIANT_AUTO ? FDTD_VARIANT_ZMARCH : c.variant;
-    // default z-march plan (measured at 512^3 and 768^3 with the psi and band
-    // kernels running beside it): tiles of 64 x 32 (8 waves) while they number
-    // at most 128, else tiles of 64 x 16; whole z columns per workgroup when
-    // the xy tiles reach that count (128, resp. 256), else chunks short enough
-    // to reach it (at least 32 planes)
+    // default z-march plan (measured with the psi and band kernels running
+    // beside it: 384^3 to 768^3 and the 1024 x 384 x 384 pencil at s = 1, 2,
+    // 4).  The z-march's workgroups each hold a CU for the whole step, so their
+    // number W sets how the 256 CUs are shared with the band kernel: aim at
+    // W = 0.75 * 256 * (fraction of points outside the bands), never above 256
+    // (a CU holding two z-march workgroups runs them at half speed and the
+    // step waits for it).  Among tiles of 64 x 64, 64 x 32 and 64 x 16 points
+    // (tile_ry 8, 4, 2) over 1..8 z chunks, the score |W - target| + 5 per
+    // extra chunk + 20 for 64 x 16 tiles (more halo rows per point) is
+    // lowest; ties go to the larger tile.
     {
-        const int Ny = s.ny + (s.gy ? 2 * (s.g - 4) : 0), Nz = s.nz + (s.gz ? 2 * (s.g - 4) : 0);
-        const long n32 = (long)((s.nx + 63) / 64) * ((Ny + 31) / 32);
-        s.ry = n32 <= 128 ? 4 : 2;
-        const long nxy = s.ry == 4 ? n32 : (long)((s.nx + 63) / 64) * ((Ny + 15) / 16);
-        const long want = s.ry == 4 ? 128 : 256;
-        long nchunk = nxy >= want ? 1 : (want + nxy - 1) / nxy;
-        int zc = (int)((Nz + nchunk - 1) / nchunk);
-        zc = std::max(32, (zc + 15) / 16 * 16);
-        s.zchunk = std::min(zc, 4096);
+        const int ext = s.g - 4;
+        const int Ny = s.ny + (s.gy ? 2 * ext : 0), Nz = s.nz + (s.gz ? 2 * ext : 0);
+        const int gh[3] = {0, s.gy, s.gz}, n3[3] = {s.nx, s.ny, s.nz};
+        double inner = 1.0;
+        for (int d = 0; d < 3; ++d) {
+            int a, b, e0, e1;
+            band_range(n3[d], s.Llo[d], s.Lhi[d], gh[d], ext, a, b, e0, e1);
+            inner *= (double)(b - a) / (double)(e1 - e0);
+        }
+        const double target = 0.75 * kCUs * inner;
+        const long tx = (s.nx + 63) / 64;
+        double best = 1e30;
+        s.ry = 2;
+        s.zchunk = std::min(std::max(32, (Nz + 15) / 16 * 16), 4096);
+        for (int ry : {8, 4, 2}) {
+            const long nxy = tx * ((Ny + 8 * ry - 1) / (8 * ry));
+            for (int nc = 1; nc <= 8; ++nc) {
+                int zc = (Nz + nc - 1) / nc;
+                zc = std::min(std::max(32, (zc + 15) / 16 * 16), 4096);
+                const long nch = (Nz + zc - 1) / zc;
+                if (nch != nc) continue;   // that many chunks is not reachable
+                const long W = nxy * nch;
+                if (W > kCUs) continue;
+                const double score = std::fabs((double)W - target) + 5.0 * (nch - 1) + (ry == 2 ? 20.0 : 0.0);
+                if (score < best - 1e-9) {
+                    best = score;
+                    s.ry = ry;
+                    s.zchunk = zc;
+                }
+            }
+        }
     }
     s.tk = c.tblock_k > 1 ? c.tblock_k : 1;
     if (s.variant == FDTD_VARIANT_TBLOCK && s.tk < 2) s.tk = 2;

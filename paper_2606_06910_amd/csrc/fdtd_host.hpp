@@ -14,6 +14,7 @@ constexpr int kTYMAX = 64;  // tallest y tile (rows) a kernel may overhang
 constexpr int kMaxRec = 65536;  // receivers per shot with temporal blocking
 constexpr int kTimingClasses = 6;   // update, psi, record, exchange, band update, temporal block
 constexpr int kBandTX = BAND_TX, kBandTY = BAND_TY, kBandZ = 32;   // band-kernel tile and z chunk
+constexpr int kCUs = 256;   // compute units of an MI355X (the default z-march plan shares them)
 
 struct ShotH {
     fdtd_shot_config c;

@@ -96,3 +96,25 @@ def test_strerror_covers_every_status():
     L = _lib.lib()
     for st in range(-7, 1):
         assert L.fdtd_strerror(st) and L.fdtd_strerror(st) != b"unknown status"
+
+
+@pytest.mark.parametrize("n,face,s,ry", [
+    ((512, 512, 512), (0,) * 6, 1, 4),              # 128 tiles of 64 x 32 (target 143)
+    ((768, 768, 768), (0,) * 6, 1, 8),              # 144 tiles of 64 x 64 (64 x 32: 288 > 256)
+    ((640, 640, 640), (0,) * 6, 1, 4),              # 200 tiles of 64 x 32 (target 152)
+    ((384, 384, 384), (0,) * 6, 1, 4),              # 72 tiles of 64 x 32 in two z chunks
+    ((1024, 384, 384), (0, 0, 1, 1, 1, 1), 1, 4),   # pencil share: 192 tiles of 64 x 32
+    ((1024, 384, 384), (0, 0, 1, 1, 1, 1), 4, 4),   # with 12 ghost rows: 208 tiles of 64 x 32
+    ((1024, 1024, 1024), (0,) * 6, 1, 8),           # 256 tiles of 64 x 64
+])
+def test_default_plan_tile_shape(n, face, s, ry):
+    """The default z-march plan: about one workgroup per CU for three quarters
+    of the chip times the fraction of points outside the bands (the shapes
+    measured best beside the band kernel), never more workgroups than CUs."""
+    cp = (20, 20, 0, 0, 0, 0) if face[2] else (20,) * 6
+    L, rc, ctx = _create([_cfg(n=n, cpml=cp, face=face, exchange_every=s)])
+    assert rc == 0
+    v, r, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert L.fdtd_get_plan(ctx, 0, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k)) == 0
+    assert (v.value, r.value, k.value) == (2, ry, 1)
+    L.fdtd_destroy(ctx)
