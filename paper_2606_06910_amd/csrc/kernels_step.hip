@@ -1,12 +1,15 @@
 // kernels_step.hip -- one leapfrog step of the second-order acoustic FDTD + CPML on gfx950.
 //
-//  k_psi          layer-memory pre-pass: psi_d <- b psi_d + a D1_d u^n on every
-//                 slab point (paper, section "CPML Boundary Layers": the memory
-//                 variable recursion, updated before it is used).
+//  k_psi_y        layer-memory pre-pass of y: psi_y <- b psi_y + a D1_y u^n on
+//                 every y-slab point (paper, section "CPML Boundary Layers": the
+//                 memory variable recursion, updated before it is used), along
+//                 y lines with a register queue.
+//  k_psi          the same for x and z, for shots whose band kernel does not
+//                 advance psi_x and psi_z itself.
 //  k_update_naive one thread per grid point; all layer logic inline.
-//  k_zmarch       points outside the layer bands: xy tile (64 x 4*RY points)
+//  k_zmarch       points outside the layer bands: xy tile (64 x NW*RY points)
 //                 staged through LDS with a 4-cell halo, marching along z with
-//                 a 9-plane register queue of u^n; one x point per lane.
+//                 an 11-plane register queue of u^n; one x point per lane.
 //  k_record       receiver gather for every shot and the device step counter.
 //
 // All kernels evaluate a point with the shared functions of fdtd_dev.hpp, so
