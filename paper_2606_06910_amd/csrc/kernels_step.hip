@@ -190,6 +190,7 @@ template <typename T, int NW, int RY> struct ZCtx {
     float umc[RY], mc[RY];       // second state and m of plane z
     float um1[RY], m1[RY];       // the same of plane z + 1
     const Roles *R;
+    int zlast;           // last plane the current segment's stencils read (segment end + 3)
     int x, y0, lane, r0; // column, tile origin row, lane, first own row (tile-local)
     int nlo[3], nhi[3];  // box of points outside every band
     int sx, sy, sz;      // source node
@@ -210,7 +211,10 @@ __device__ __forceinline__ void zbody(ZCtx<T, NW, RY> &C, const DevShot &s, floa
     // that it is found in L2), u^{n-1} (or d^n) and m plane z + 2
     float umn[RY], mn[RY];
     {
-        const uint32_t s6 = (PH + 6) * C.Sb, s2 = (PH + 2) * C.Sb, m2 = (PH + 2) * C.Smb;
+        // (past the last plane the segment's stencils read, the u^n loads take an
+        // out-of-range offset: zero, no traffic, nothing read beyond the frame)
+        const uint32_t s6 = z + 6 <= C.zlast ? (PH + 6) * C.Sb : kBufSkip;
+        const uint32_t s2 = (PH + 2) * C.Sb, m2 = (PH + 2) * C.Smb;
 #pragma unroll
         for (int r = 0; r < RY; ++r) q[slot(6)][r] = Buf<T>::ld(C.ru, C.off[r], s6);
 #pragma unroll
@@ -379,13 +383,15 @@ __global__ __launch_bounds__(64 * NW) void k_zmarch(const DevShot *__restrict__ 
     for (int sg = 0; sg < nseg; ++sg) {
         const int a = seg_a[sg], b = seg_b[sg];
         if (a >= b) continue;
+        C.zlast = b + FDTD_R - 1;
         {
             // planes a - 4 .. a + 5 (phase 0: slot o + 4); plane a + 6 is the first body's
             const Rsrc ru = make_rsrc(C.u + (long)(a - 4) * C.Sb);
 #pragma unroll
             for (int o = -4; o < 6; ++o)
 #pragma unroll
-                for (int r = 0; r < RY; ++r) q[o + 4][r] = Buf<T>::ld(ru, C.off[r], (o + 4) * C.Sb);
+                for (int r = 0; r < RY; ++r)
+                    q[o + 4][r] = Buf<T>::ld(ru, C.off[r], a + o <= C.zlast ? (o + 4) * C.Sb : kBufSkip);
             const Rsrc rs = make_rsrc(C.sec + (long)a * C.Sb);
             const Rsrc rm = make_rsrc(C.m + (long)a * C.Smb);
 #pragma unroll
@@ -400,7 +406,8 @@ __global__ __launch_bounds__(64 * NW) void k_zmarch(const DevShot *__restrict__ 
 #pragma unroll
             for (int o = 0; o < 6; ++o)
 #pragma unroll
-                for (int k = 0; k < G::HS; ++k) hq[o + 4][k] = Buf<T>::ld(ru, C.hoff[k], (o + 4) * C.Sb);
+                for (int k = 0; k < G::HS; ++k)
+                    hq[o + 4][k] = Buf<T>::ld(ru, C.hoff[k], a + o <= C.zlast ? (o + 4) * C.Sb : kBufSkip);
         }
         for (int z0 = a; z0 < b; z0 += ZQ) {
             C.ru = make_rsrc(C.u + (long)z0 * C.Sb);
