@@ -241,7 +241,9 @@ def _timed_steps(p, steps, graph):
 
 def small_leg():
     """The 64^3 workload (10-cell layers, 200 steps): a few MB, launch-bound;
-    Mpts/s with every step launched eagerly and with the HIP-graph time loop."""
+    Mpts/s with every step launched eagerly and with the HIP-graph time loop,
+    for the automatic variant (the naive kernel at this size) and for the
+    z-march."""
     import numpy as np
     import torch
 
@@ -249,16 +251,19 @@ def small_leg():
     from paper_2606_06910_amd import Propagator, Shot
 
     w = synth.plain64()
-    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml)])
-    p.set_velocity(0, torch.from_numpy(w.v.astype(np.float32)).cuda())
-    p.inject_source(0, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)).cuda())
-    p.set_receivers(0, w.rec)
-    p.record(0, w.nt)
     out = {}
-    for name, graph in (("eager", False), ("graph", True)):
-        ms = _timed_steps(p, w.nt, graph)
-        out[name + "_mpts"] = round(w.npts * w.nt / (ms / 1e3) / 1e6, 1)
-    p.close()
+    for tag, variant in (("", 0), ("zmarch_", 2)):
+        p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, variant=variant)])
+        p.set_velocity(0, torch.from_numpy(w.v.astype(np.float32)).cuda())
+        p.inject_source(0, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)).cuda())
+        p.set_receivers(0, w.rec)
+        p.record(0, w.nt)
+        for name, graph in (("eager", False), ("graph", True)):
+            ms = _timed_steps(p, w.nt, graph)
+            out[tag + name + "_mpts"] = round(w.npts * w.nt / (ms / 1e3) / 1e6, 1)
+        if not tag:
+            out["auto_variant"] = {1: "naive", 2: "zmarch"}.get(p.plan(0)[0], str(p.plan(0)[0]))
+        p.close()
     out["workload"] = "64^3, 10-cell CPML, 200 steps"
     return out
 

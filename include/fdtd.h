@@ -62,7 +62,8 @@ enum fdtd_status {
 enum fdtd_storage { FDTD_F32 = 0, FDTD_F16 = 1, FDTD_BF16 = 2 };
 enum fdtd_face { FDTD_FACE_DIRICHLET = 0, FDTD_FACE_GHOST = 1 };
 enum fdtd_variant {
-    FDTD_VARIANT_AUTO = 0,   /* z-march (or the tuned choice, see fdtd_autotune)   */
+    FDTD_VARIANT_AUTO = 0,   /* z-march (or the tuned choice, see fdtd_autotune);
+                                naive for a single-shot context below 150^3 points */
     FDTD_VARIANT_NAIVE = 1,  /* one thread per point, all layer logic inline       */
     FDTD_VARIANT_ZMARCH = 2, /* LDS-staged xy tiles, z-marching register queue      */
     FDTD_VARIANT_TBLOCK = 3  /* tblock_k steps per launch (temporal blocking)       */

@@ -889,6 +889,15 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
         ctx->shots.push_back(s);
     }
     ctx->storage = shots[0].storage;
+    // the automatic variant of a lone small shot is the naive kernel: below about
+    // 150^3 points the z-march has too few tiles to fill the chip and the band
+    // kernel's share is large (measured with graph steps: 64^3 14.0 k vs 4.5 k
+    // Mpts/s, 128^3 38.2 k vs 30.4 k; 160^3 48.3 k vs 50.1 k).  Shots of a
+    // batch share the grouped z-march and band launches and stay on the z-march.
+    if (nshots == 1 && shots[0].variant == FDTD_VARIANT_AUTO) {
+        ShotH &s0 = ctx->shots[0];
+        if ((long)s0.nx * s0.ny * s0.nz < kSmallShot) s0.variant = FDTD_VARIANT_NAIVE;
+    }
     for (auto &sh : ctx->shots)
         if (sh.tb_bufs && nshots != 1) {
             delete ctx;

@@ -15,6 +15,7 @@ constexpr int kMaxRec = 65536;  // receivers per shot with temporal blocking
 constexpr int kTimingClasses = 6;   // update, psi, record, exchange, band update, temporal block
 constexpr int kBandTX = BAND_TX, kBandTY = BAND_TY, kBandZ = 32;   // band-kernel tile and z chunk
 constexpr int kCUs = 256;   // compute units of an MI355X (the default z-march plan shares them)
+constexpr long kSmallShot = 150L * 150 * 150;   // a lone shot below this many points runs naive by default
 
 struct ShotH {
     fdtd_shot_config c;

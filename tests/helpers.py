@@ -30,11 +30,14 @@ def rel_l2(a, b):
 
 
 def run_gpu(w, nt=None, snap_every=0, graph=False, plan=None, **shot_kw):
-    """Forward run on cuda:0.  Returns (traces, snaps, final u^n) as numpy float64."""
+    """Forward run on cuda:0.  Returns (traces, snaps, final u^n) as numpy float64.
+    The variant defaults to the z-march (the automatic choice would run the
+    naive kernel on the small test grids)."""
     import torch
 
     from paper_2606_06910_amd import Propagator, Shot
 
+    shot_kw.setdefault("variant", 2)
     nt = w.nt if nt is None else nt
     face = shot_kw.pop("face", None)
     if face is None:

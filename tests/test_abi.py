@@ -118,3 +118,19 @@ def test_default_plan_tile_shape(n, face, s, ry):
     assert L.fdtd_get_plan(ctx, 0, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k)) == 0
     assert (v.value, r.value, k.value) == (2, ry, 1)
     L.fdtd_destroy(ctx)
+
+
+@pytest.mark.parametrize("cfgs,variants", [
+    ([dict(n=(64, 64, 64))], [1]),                         # a lone small shot: naive
+    ([dict(n=(160, 160, 160))], [2]),                      # above 150^3 points: z-march
+    ([dict(n=(64, 64, 64)), dict(n=(64, 64, 64))], [2, 2]),   # batched shots: z-march
+    ([dict(n=(64, 64, 64), variant=2)], [2]),              # an explicit choice stands
+])
+def test_auto_variant(cfgs, variants):
+    L, rc, ctx = _create([_cfg(**c) for c in cfgs])
+    assert rc == 0
+    for i, want in enumerate(variants):
+        v, r, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        assert L.fdtd_get_plan(ctx, i, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k)) == 0
+        assert v.value == want
+    L.fdtd_destroy(ctx)

@@ -31,7 +31,7 @@ def _gpu_grad(w, dobs, every, storage=0):
     from paper_2606_06910_amd import Propagator, Shot
 
     vref = float(v32(w).max())
-    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, v_ref=vref, storage=storage)])
+    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, v_ref=vref, storage=storage, variant=2)])
     p.set_velocity(0, torch.from_numpy(w.v.astype(np.float32)).cuda())
     p.inject_source(0, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)))
     p.set_receivers(0, w.rec)
@@ -84,7 +84,7 @@ def test_autograd_function(adj_case):
 
     w, dobs, _, gref = adj_case
     v = torch.from_numpy(w.v.astype(np.float32)).cuda().requires_grad_(True)
-    shot = Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, v_ref=float(v32(w).max()))
+    shot = Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, v_ref=float(v32(w).max()), variant=2)
     tr = simulate(v, shot, torch.from_numpy(w.wavelet.astype(np.float32)), w.src[0], w.rec, w.nt, every=25)
     J = 0.5 * ((tr.double() - torch.from_numpy(dobs).cuda()) ** 2).sum()
     J.backward()

@@ -115,7 +115,7 @@ def test_graph_replay_matches_eager():
 
     w = _ragged((40, 36, 44), (10.0, 10.0, 10.0), (6,) * 6, 50, 7)
     eager = run_gpu(w, variant=ZMARCH)
-    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml)])
+    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, variant=2)])
     p.set_velocity(0, torch.from_numpy(w.v.astype(np.float32)).cuda())
     p.inject_source(0, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)))
     p.set_receivers(0, w.rec)
