@@ -170,7 +170,9 @@ int fdtd_check_finite(fdtd_ctx *ctx);
 
 /* Size in bytes of the device buffer fdtd_adjoint needs for one shot with
  * checkpoints every `every` steps over nt steps (checkpoints, one segment of
- * recomputed levels, adjoint state, scratch). */
+ * recomputed levels, adjoint state, scratch, the receivers grouped by
+ * location).  It depends on the shot's receiver count: set the receivers
+ * first (fdtd_adjoint returns ENOMEM if they outgrew the buffer since). */
 int fdtd_adjoint_workspace_size(const fdtd_ctx *ctx, int32_t shot, int32_t every, int32_t nt, size_t *bytes);
 
 /* Register the adjoint buffer of one shot and the checkpoint interval.  While

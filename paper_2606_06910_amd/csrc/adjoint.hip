@@ -18,9 +18,11 @@
 #include "fdtd_launch.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <vector>
 
 struct AdjArgs {
@@ -32,6 +34,7 @@ struct AdjArgs {
     const int *band[3];      // band coordinates per axis
     int nband[3];
     const void *um, *u0, *up;   // forward u^{n-1}, u^n, u^{n+1} (storage type)
+    float *Lb;               // Lbar = m lambda^{n+1} at every grid point (origin-adjusted; zero in the frame)
     double *G;               // dense accumulator sum lambda * (u^{n+1} - 2u^n + u^{n-1})
 };
 
@@ -47,14 +50,31 @@ __device__ __forceinline__ float slab_val(const DevShot &s, const float *arr, in
     return arr[psi_index(s, d, x, y, z)];
 }
 
-// residual injection: one thread, receivers in order (repeated receivers add up)
-__global__ void k_adj_resid(float *lam, const DevShot *sp, const float *resid_row) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// residual injection: one thread per distinct receiver location, adding the
+// residuals of the receivers there in receiver order (repeated receivers add
+// up, with the rounding of a serial pass over the receivers).  gstart[g] ..
+// gstart[g + 1] index ridx, the receivers of location g.
+__global__ __launch_bounds__(256) void k_adj_resid(float *lam, const DevShot *sp, const float *resid_row,
+                                                   const int *gstart, const int *ridx, int ngroups) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngroups) return;
     const DevShot &s = *sp;
-    for (int r = 0; r < s.nrec; ++r) {
-        const int32_t *q = s.rec + 3 * r;
-        lam[fidx(s, q[0], q[1], q[2])] += resid_row[r];
-    }
+    const int k0 = gstart[g], k1 = gstart[g + 1];
+    const int32_t *q = s.rec + 3 * ridx[k0];
+    float *l = lam + fidx(s, q[0], q[1], q[2]);
+    float v = *l;
+    for (int k = k0; k < k1; ++k) v += resid_row[ridx[k]];
+    *l = v;
+}
+
+// Lbar = m lambda^{n+1} once per point, so that the passes below read it
+// instead of forming it at every stencil tap (the same product, so the same bits)
+__global__ __launch_bounds__(256) void k_adj_lbar(AdjArgs a) {
+    const DevShot &s = *a.s;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= s.nx) return;
+    const long i = fidx(s, x, (int)blockIdx.y, (int)blockIdx.z);
+    a.Lb[i] = s.m[i] * a.lam[i];
 }
 
 // pass 1 on band points of axis d: E_d and the zeta adjoint
@@ -87,7 +107,7 @@ __global__ __launch_bounds__(256) void k_adj_p1(AdjArgs a, int d) {
         z = c;
     }
     const long i = fidx(s, x, y, z);
-    const float lb = s.m[i] * a.lam[i];
+    const float lb = a.Lb[i];
     const int n = coord_n(s, d);
     float e = lb;
     if (in_slab(c, n, s.Llo[d], s.Lhi[d])) {
@@ -152,7 +172,7 @@ __device__ __forceinline__ float kE(const DevShot &s, const AdjArgs &a, int d, i
     const int n = coord_n(s, d);
     if (c < 0 || c >= n) return 0.0f;
     if (in_band(c, n, s.Llo[d], s.Lhi[d])) return prof_at(s, d, 2, c) * a.E[d][i];
-    return s.m[i] * a.lam[i];
+    return a.Lb[i];
 }
 __device__ __forceinline__ float dE(const DevShot &s, const AdjArgs &a, int d, int c, long i) {
     const int n = coord_n(s, d);
@@ -182,10 +202,10 @@ __global__ __launch_bounds__(256) void k_adj_p3(AdjArgs a, float inv_scale) {
 #pragma unroll
             for (int l = 1; l <= 4; ++l) {
                 const long im = i - l * st[d], ip = i + l * st[d];
-                lo[l - 1] = s.m[im] * a.lam[im];
-                hi[l - 1] = s.m[ip] * a.lam[ip];
+                lo[l - 1] = a.Lb[im];
+                hi[l - 1] = a.Lb[ip];
             }
-            t = d2_axis(s.w2[d], s.m[i] * a.lam[i], lo, hi);
+            t = d2_axis(s.w2[d], a.Lb[i], lo, hi);
         } else {
             float kl[4], kh[4], dl[4], dh[4], fl[4], fh[4];
             int xm[3] = {x, y, z}, xp[3] = {x, y, z};
@@ -250,6 +270,8 @@ static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 namespace {
 struct AdjLayout {
     size_t ck = 0, seg = 0, lam = 0, lamp = 0, psib[3] = {}, zetab[3] = {}, F[3] = {}, E[3] = {}, band[3] = {};
+    size_t gstart = 0, ridx = 0;   // receivers grouped by location (k_adj_resid)
+    size_t lb = 0;                 // Lbar field
     size_t total = 0;
     int nck = 0;
 };
@@ -283,6 +305,9 @@ static AdjLayout adj_layout(const ShotH &s, int every, int nt) {
         L.E[d] = take((s.Llo[d] + s.Lhi[d]) > 0 ? s.elems * 4 : 0);
         L.band[d] = take((size_t)s.nmax * 4);
     }
+    L.lb = take(s.elems * 4);
+    L.gstart = take((size_t)(s.nrec + 1) * 4);
+    L.ridx = take((size_t)std::max(s.nrec, 1) * 4);
     L.total = off;
     return L;
 }
@@ -347,6 +372,9 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
     if (!s.vel_set) AFAIL(ctx, FDTD_ESTATE, "no velocity model");
     const int every = s.ck_every;
     AdjLayout L = adj_layout(s, every, nt);
+    if (L.total > s.ck_bytes)
+        AFAIL(ctx, FDTD_ENOMEM, "adjoint buffer of %zu bytes, %zu needed (receivers set after sizing it?)", s.ck_bytes,
+              L.total);
     char *B = s.ck_buf;
     hipStream_t st = ctx->stream;
     DevShot *dd = (DevShot *)fdtd_ws(ctx, ctx->o_desc);
@@ -362,11 +390,13 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
     // adjoint state to zero; band coordinate lists
     fdtd_launch_fill_zero(B + L.lam, a256(s.elems * 4), st);
     fdtd_launch_fill_zero(B + L.lamp, a256(s.elems * 4), st);
+    fdtd_launch_fill_zero(B + L.lb, a256(s.elems * 4), st);
     AdjArgs a;
     memset(&a, 0, sizeof a);
     a.s = sp;
     a.lam = (float *)origin4(s, B + L.lam);
     a.lamp = (float *)origin4(s, B + L.lamp);
+    a.Lb = (float *)origin4(s, B + L.lb);
     for (int d = 0; d < 3; ++d) {
         fdtd_launch_fill_zero(B + L.psib[d], a256(s.psi_elems[d] * 4), st);
         fdtd_launch_fill_zero(B + L.zetab[d], a256(s.psi_elems[d] * 4), st);
@@ -384,6 +414,35 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
             a.band[d] = (const int *)(B + L.band[d]);
         }
     }
+    // receivers grouped by location, in first-appearance order; receiver order within a group
+    int ngroups = 0;
+    if (s.nrec > 0) {
+        std::vector<int32_t> h((size_t)s.nrec * 3);
+        AHIP(ctx, hipMemcpy(h.data(), s.rec, h.size() * 4, hipMemcpyDeviceToHost));
+        std::vector<int> gstart, ridx;
+        std::vector<std::vector<int>> members;
+        std::map<std::array<int32_t, 3>, int> where;
+        for (int r = 0; r < s.nrec; ++r) {
+            const std::array<int32_t, 3> key{h[3 * r], h[3 * r + 1], h[3 * r + 2]};
+            auto it = where.find(key);
+            if (it == where.end()) {
+                where[key] = (int)members.size();
+                members.push_back({r});
+            } else {
+                members[it->second].push_back(r);
+            }
+        }
+        for (auto &m : members) {
+            gstart.push_back((int)ridx.size());
+            ridx.insert(ridx.end(), m.begin(), m.end());
+        }
+        gstart.push_back((int)ridx.size());
+        ngroups = (int)members.size();
+        AHIP(ctx, hipMemcpyAsync(B + L.gstart, gstart.data(), gstart.size() * 4, hipMemcpyHostToDevice, st));
+        AHIP(ctx, hipMemcpyAsync(B + L.ridx, ridx.data(), ridx.size() * 4, hipMemcpyHostToDevice, st));
+        AHIP(ctx, hipStreamSynchronize(st));
+    }
+    const int *gstart_d = (const int *)(B + L.gstart), *ridx_d = (const int *)(B + L.ridx);
     const long N = (long)s.nx * s.ny * s.nz;
     hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)std::min<long>((N + 255) / 256, 65536)), dim3(256), 0, st,
                        grad_v_dev, N);
@@ -412,7 +471,10 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
         }
         // reverse sweep over the segment
         for (int n = s1 - 1; n >= s0; --n) {
-            hipLaunchKernelGGL(k_adj_resid, dim3(1), dim3(64), 0, st, a.lam, sp, resid_dev + (size_t)n * s.nrec);
+            if (ngroups > 0)
+                hipLaunchKernelGGL(k_adj_resid, dim3((ngroups + 255) / 256), dim3(256), 0, st, a.lam, sp,
+                                   resid_dev + (size_t)n * s.nrec, gstart_d, ridx_d, ngroups);
+            hipLaunchKernelGGL(k_adj_lbar, dim3((s.nx + 255) / 256, s.ny, s.nz), dim3(256), 0, st, a);
             a.up = origin_t(s, seg + (size_t)(n - s0 + 2) * fb);
             a.u0 = origin_t(s, seg + (size_t)(n - s0 + 1) * fb);
             a.um = origin_t(s, seg + (size_t)(n - s0) * fb);
