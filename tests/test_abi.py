@@ -134,3 +134,22 @@ def test_auto_variant(cfgs, variants):
         assert L.fdtd_get_plan(ctx, i, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k)) == 0
         assert v.value == want
     L.fdtd_destroy(ctx)
+
+
+def test_batch_default_plan():
+    """Batched shots whose single-shot plans would over-subscribe the CUs get
+    many small z-march workgroups (64 x 8 tiles); a pair of large shots keeps
+    the single-shot shapes."""
+    shapes = [(96 + 8 * i, 288 - 8 * i, 160) for i in range(24)]
+    L, rc, ctx = _create([_cfg(n=n, cpml=(15,) * 6) for n in shapes])
+    assert rc == 0
+    v, r, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    for i in range(len(shapes)):
+        assert L.fdtd_get_plan(ctx, i, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k)) == 0
+        assert (v.value, r.value) == (2, 1)
+    L.fdtd_destroy(ctx)
+    L, rc, ctx = _create([_cfg(n=(512, 512, 256), cpml=(20,) * 6)] * 2)
+    assert rc == 0
+    assert L.fdtd_get_plan(ctx, 0, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k)) == 0
+    assert r.value != 1
+    L.fdtd_destroy(ctx)
