@@ -400,7 +400,14 @@ def batched_leg(K=600, nshots=24):
             "sequential_mpts": round(npts * K / (ms_s / 1e3) / 1e6, 1)}
 
 
-def cpu_baseline(w, steps=2):
+def zmarch_instance(plan):
+    """Template instance of the z-march kernel a plan (variant, tile_ry, tblock_k) launches:
+    tile_ry 1, 2, 4, 8 -> (waves, rows per thread) (4, 2), (4, 4), (8, 4), (16, 4)."""
+    nw, ry = {1: (4, 2), 2: (4, 4), 4: (8, 4), 8: (16, 4)}.get(plan[1], (0, 0))
+    return "k_zmarch<float, %d, %d>" % (nw, ry)
+
+
+def cpu_baseline(w, steps=5):
     """The FP64 oracle on the same workload: `steps` full steps after one untimed step."""
     import numpy as np
 
@@ -531,7 +538,7 @@ def main():
                      "measured_frac": (round(traffic / (upd[0] / 1e3) / 1e9 / PEAK_HBM_GBS, 4)
                                        if traffic else None),
                      "copy_ceiling_gbs": COPY_CEILING_GBS,
-                     "kernel": "k_zmarch<float, RY> (update of the points outside the layer bands)",
+                     "kernel": "%s (update of the points outside the layer bands)" % zmarch_instance(plan),
                      "kernel_ms": round(upd[0], 5), "algorithmic_bytes_per_launch": upd_bytes},
         "step_algorithmic_gbs": round(step_bytes(w.n, w.cpml) / (ms / K / 1e3) / 1e9, 1),
         "kernel_ms": {k: round(v[0], 5) for k, v in tm.items() if v[1] > 0},
