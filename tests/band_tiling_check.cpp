@@ -1,0 +1,160 @@
+// Host-only brute force over random grids: the band kernel's tiles (band_box
+// boxes, band_xtiles x tiles, rows of BAND_TY, z chunks of 32 except z boxes,
+// which are walked whole) cover every band point of the compute box exactly
+// once; and, on geometries the library fuses (each x band at most BAND_TX wide,
+// the x bands and the z bands each far enough apart), every x-layer point lies
+// in the same tile row as each band point that reads it, and every z-layer
+// point in the same z-box walk as its readers, with the walk's first planes
+// outside the layers and at least 5 planes deep.  Prints "ok <cases> <fused>".
+#include "fdtd_dev.hpp"
+
+#include <array>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+namespace {
+bool fused(const int *n, const int *lo, const int *hi) {
+    if (lo[0] + hi[0] > 0 && (lo[0] + FDTD_R > BAND_TX || hi[0] + FDTD_R > BAND_TX || n[0] < lo[0] + hi[0] + 2 * FDTD_R))
+        return false;
+    return lo[2] + hi[2] == 0 || n[2] >= lo[2] + hi[2] + 2 * FDTD_R;
+}
+struct Owner {
+    int box = -1, tx, ty, zc, za, zb;
+};
+// dense owner table over the compute box (x in [0, nx), y, z in [-ext, n + ext))
+struct Table {
+    int nx, ny, nz, ext;
+    std::vector<Owner> v;
+    Table(int nx_, int ny_, int nz_, int ext_) : nx(nx_), ny(ny_ + 2 * ext_), nz(nz_ + 2 * ext_), ext(ext_) {
+        v.resize((size_t)nx * ny * nz);
+    }
+    bool inside(int x, int y, int z) const {
+        return x >= 0 && x < nx && y + ext >= 0 && y + ext < ny && z + ext >= 0 && z + ext < nz;
+    }
+    Owner &at(int x, int y, int z) { return v[((size_t)(z + ext) * ny + (y + ext)) * nx + x]; }
+};
+}  // namespace
+
+int main(int argc, char **argv) {
+    const int cases = argc > 1 ? atoi(argv[1]) : 2000;
+    srand(7);
+    long nf = 0;
+    for (int it = 0; it < cases; ++it) {
+        int n[3], lo[3], hi[3], gh[3] = {0, 0, 0};
+        for (int d = 0; d < 3; ++d) {
+            n[d] = 9 + rand() % 60;
+            const int m = (n[d] - 1) / 2;
+            lo[d] = rand() % 3 ? rand() % (m + 1) : 0;
+            hi[d] = rand() % 3 ? rand() % (m + 1) : 0;
+        }
+        int ext = 0;
+        if (rand() % 4 == 0) {   // ghost (loopback) y, maybe z: no layers there
+            gh[1] = 1;
+            lo[1] = hi[1] = 0;
+            if (rand() % 2) {
+                gh[2] = 1;
+                lo[2] = hi[2] = 0;
+            }
+            ext = rand() % 13;
+        }
+        Table own(n[0], n[1], n[2], ext);
+        for (int b = 0; b < 6; ++b) {
+            int blo[3], bhi[3];
+            band_box(n, lo, hi, gh, ext, b, blo, bhi);
+            if (bhi[0] <= blo[0] || bhi[1] <= blo[1] || bhi[2] <= blo[2]) continue;
+            int x0, x1;
+            const int ntx = band_xtiles(n[0], lo[0], hi[0], b, blo[0], bhi[0], 0, &x0, &x1);
+            const int nty = (bhi[1] - blo[1] + BAND_TY - 1) / BAND_TY;
+            const int nzc = b < 2 ? 1 : (bhi[2] - blo[2] + 31) / 32;
+            for (int zc = 0; zc < nzc; ++zc)
+                for (int ty = 0; ty < nty; ++ty)
+                    for (int tx = 0; tx < ntx; ++tx) {
+                        band_xtiles(n[0], lo[0], hi[0], b, blo[0], bhi[0], tx, &x0, &x1);
+                        if (x1 <= x0 || x1 - x0 > BAND_TX) {
+                            printf("FAIL tile width %d\n", x1 - x0);
+                            return 1;
+                        }
+                        const int za = b < 2 ? blo[2] : blo[2] + 32 * zc, zb = b < 2 ? bhi[2] : std::min(za + 32, bhi[2]);
+                        for (int z = za; z < zb; ++z)
+                            for (int r = 0; r < BAND_TY; ++r) {
+                                const int y = blo[1] + ty * BAND_TY + r;
+                                if (y >= bhi[1]) continue;
+                                for (int x = x0; x < x1; ++x) {
+                                    Owner &w = own.at(x, y, z);
+                                    if (w.box >= 0) {
+                                        printf("FAIL point (%d,%d,%d) in two tiles\n", x, y, z);
+                                        return 1;
+                                    }
+                                    w = Owner{b, tx, ty, zc, za, zb};
+                                }
+                            }
+                    }
+            band_xtiles(n[0], lo[0], hi[0], b, blo[0], bhi[0], 1 << 20, &x0, &x1);   // idle work item
+            if (x1 > x0) {
+                printf("FAIL idle item has points\n");
+                return 1;
+            }
+        }
+        auto in_band_d = [&](int d, int c) {
+            return (lo[d] > 0 && c < lo[d] + FDTD_R) || (hi[d] > 0 && c >= n[d] - hi[d] - FDTD_R);
+        };
+        auto in_slab_d = [&](int d, int c) { return c >= 0 && c < n[d] && (c < lo[d] || c >= n[d] - hi[d]); };
+        int e0[3], e1[3];
+        for (int d = 0; d < 3; ++d) {
+            int a, b;
+            band_range(n[d], lo[d], hi[d], gh[d], ext, a, b, e0[d], e1[d]);
+        }
+        for (int z = e0[2]; z < e1[2]; ++z)
+            for (int y = e0[1]; y < e1[1]; ++y)
+                for (int x = 0; x < n[0]; ++x) {
+                    const bool band = in_band_d(0, x) || in_band_d(1, y) || in_band_d(2, z);
+                    if (band != (own.at(x, y, z).box >= 0)) {
+                        printf("FAIL coverage at (%d,%d,%d): band %d\n", x, y, z, band);
+                        return 1;
+                    }
+                }
+        if (!fused(n, lo, hi)) continue;
+        ++nf;
+        for (int z = e0[2]; z < e1[2]; ++z)
+        for (int y = e0[1]; y < e1[1]; ++y)
+        for (int x = 0; x < n[0]; ++x) {
+            const Owner &o = own.at(x, y, z);
+            if (o.box < 0) continue;
+            if (in_band_d(0, x))
+                for (int l = -FDTD_R; l <= FDTD_R; ++l) {
+                    if (!l || !in_slab_d(0, x + l)) continue;
+                    const Owner &p = own.at(x + l, y, z);
+                    if (p.box != o.box || p.tx != o.tx || p.ty != o.ty || p.zc != o.zc) {
+                        printf("FAIL x-layer point (%d,%d,%d) outside its reader's tile row\n", x + l, y, z);
+                        return 1;
+                    }
+                }
+            if (in_slab_d(2, z) && o.box >= 2) {
+                printf("FAIL z-layer point outside the z boxes\n");
+                return 1;
+            }
+            if (in_band_d(2, z)) {
+                for (int l = -FDTD_R; l <= FDTD_R; ++l) {
+                    if (!l || !in_slab_d(2, z + l)) continue;
+                    const Owner &p = own.at(x, y, z + l);
+                    if (p.box != o.box || p.tx != o.tx || p.ty != o.ty) {
+                        printf("FAIL z-layer point outside its reader's walk\n");
+                        return 1;
+                    }
+                }
+                for (int p = o.za - FDTD_R; p < o.za; ++p)
+                    if (in_slab_d(2, p)) {
+                        printf("FAIL z walk starts next to a layer plane\n");
+                        return 1;
+                    }
+                if (o.zb - o.za < FDTD_R + 1) {
+                    printf("FAIL z walk shorter than 5 planes\n");
+                    return 1;
+                }
+            }
+        }
+    }
+    printf("ok %d %ld\n", cases, nf);
+    return 0;
+}
