@@ -7,7 +7,7 @@ step of the whole grid: psi pre-pass, wavefield update (interior + layers),
 source and receiver gather.  Metric: million output points per second,
 nx*ny*nz*steps / time, plus the HBM roofline of the dominant kernel.
 
-Prints one JSON line.  With --gpus above 1 it exits: this build runs on one GPU.
+Prints one JSON line.  With --gpus above 1 it exits: the library runs on one GPU.
 """
 import argparse
 import json
@@ -487,7 +487,7 @@ def main():
         print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

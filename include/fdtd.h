@@ -56,7 +56,7 @@ enum fdtd_status {
     FDTD_ENOMEM = -4,        /* workspace or buffer too small                   */
     FDTD_EHIP = -5,          /* a HIP runtime call failed                       */
     FDTD_ENONFINITE = -6,    /* non-finite value found by fdtd_check_finite     */
-    FDTD_EUNSUPPORTED = -7   /* valid request this build does not implement     */
+    FDTD_EUNSUPPORTED = -7   /* valid request the library does not implement    */
 };
 
 enum fdtd_storage { FDTD_F32 = 0, FDTD_F16 = 1, FDTD_BF16 = 2 };
