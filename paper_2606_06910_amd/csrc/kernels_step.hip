@@ -253,10 +253,10 @@ __device__ __forceinline__ void zbody(ZCtx<T, NW, RY> &C, const DevShot &s, floa
         const Upd up = time_update<T>(C.mc[r], lt, c, C.umc[r], src, C.src);
         const bool ok = C.full || (C.x >= C.nlo[0] && C.x < C.nhi[0] && y >= C.nlo[1] && y < C.nhi[1] &&
                                    !(C.partial && in_box(*C.R, C.x, y, z)));
-        if (ok) {
-            Buf<T>::st(C.rw, C.offs[r], s0, up.u);
-            if constexpr (IsInc<T>::v) Buf<T>::st(C.rs, C.offs[r], s0, up.d);
-        }
+        // (a masked point's store takes an out-of-range offset: no branch per row)
+        const uint32_t so = ok ? C.offs[r] : kBufSkip;
+        Buf<T>::st(C.rw, so, s0, up.u);
+        if constexpr (IsInc<T>::v) Buf<T>::st(C.rs, so, s0, up.d);
     }
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
