@@ -465,6 +465,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage and batched-shot legs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration run)")
+    ap.add_argument("--stream-probe", type=int, default=0, metavar="MIB",
+                    help="only time o = a + b * c over FP32 arrays of MIB MiB (3 read + 1 write streams)")
     ap.add_argument("--kernel-timing", action="store_true",
                     help="only run the per-kernel timing pass (the launches a profiler summary is taken over)")
     ap.add_argument("--leg", choices=sorted(LEGS), help="only run one extra leg and print its JSON")
@@ -485,6 +487,28 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}), flush=True)
+        return
+    if args.stream_probe:
+        import torch
+
+        # the z-march's access mix with nothing else: three FP32 streams read,
+        # one written, o = a + b * c, arrays far larger than the caches
+        n = args.stream_probe * (1 << 20) // 4
+        a, b, c = (torch.rand(n, device="cuda") for _ in range(3))
+        o = torch.empty_like(a)
+        for _ in range(3):
+            torch.addcmul(a, b, c, out=o)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            torch.addcmul(a, b, c, out=o)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"stream_probe": "o = a + b * c, FP32", "bytes_per_launch": 16 * n,
+                          "ms": round(ms, 4), "TB_per_s": round(16 * n / (ms / 1e3) / 1e12, 3)}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)

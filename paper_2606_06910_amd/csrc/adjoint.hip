@@ -29,8 +29,9 @@ struct AdjArgs {
     const DevShot *s;        // forward descriptor (geometry, m, profiles, coefficients)
     float *lam;              // lambda^{n+1}   (origin-adjusted, FP32, forward layout)
     float *lamp;             // lambda^{n+2} in, lambda^n out
-    float *psib[3], *zetab[3], *F[3];   // compact slab layouts (as psi)
-    float *E[3];             // origin-adjusted FP32 fields (band points)
+    float *psib[3], *zetab[3];          // compact slab layouts (as psi)
+    float *E[3];             // origin-adjusted FP32 fields (band points; zero elsewhere)
+    float *F[3];             // origin-adjusted FP32 fields (slab points; zero elsewhere)
     const int *band[3];      // band coordinates per axis
     int nband[3];
     const void *um, *u0, *up;   // forward u^{n-1}, u^n, u^{n+1} (storage type)
@@ -40,14 +41,6 @@ struct AdjArgs {
 
 __device__ __forceinline__ long fidx(const DevShot &s, int x, int y, int z) {
     return (long)z * s.S + (long)y * s.P + x;
-}
-
-// F_d / psi-layout value at (x,y,z), zero outside the slab
-__device__ __forceinline__ float slab_val(const DevShot &s, const float *arr, int d, int x, int y, int z) {
-    int c = d == 0 ? x : (d == 1 ? y : z);
-    int n = coord_n(s, d);
-    if (c < 0 || c >= n || !in_slab(c, n, s.Llo[d], s.Lhi[d])) return 0.0f;
-    return arr[psi_index(s, d, x, y, z)];
 }
 
 // residual injection: one thread per distinct receiver location, adding the
@@ -77,10 +70,12 @@ __global__ __launch_bounds__(256) void k_adj_lbar(AdjArgs a) {
     a.Lb[i] = s.m[i] * a.lam[i];
 }
 
-// pass 1 on band points of axis d: E_d and the zeta adjoint
-__global__ __launch_bounds__(256) void k_adj_p1(AdjArgs a, int d) {
+// pass 1 on band points of axis d = blockIdx.y: E_d and the zeta adjoint
+__global__ __launch_bounds__(256) void k_adj_p1(AdjArgs a) {
     const DevShot &s = *a.s;
+    const int d = (int)blockIdx.y;
     const int nb = a.nband[d];
+    if (nb == 0) return;
     const int n1 = d == 0 ? s.ny : s.nx;          // the two other axes, fastest first
     const int n2 = d == 2 ? s.ny : s.nz;
     long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -119,9 +114,10 @@ __global__ __launch_bounds__(256) void k_adj_p1(AdjArgs a, int d) {
     a.E[d][i] = e;
 }
 
-// pass 2 on slab points of axis d: psi adjoint and F_d = a (psi_b - D1 E_d)
-__global__ __launch_bounds__(256) void k_adj_p2(AdjArgs a, int d) {
+// pass 2 on slab points of axis d = blockIdx.y: psi adjoint and F_d = a (psi_b - D1 E_d)
+__global__ __launch_bounds__(256) void k_adj_p2(AdjArgs a) {
     const DevShot &s = *a.s;
+    const int d = (int)blockIdx.y;
     const int lo = s.Llo[d], hi = s.Lhi[d];
     if (lo + hi == 0) return;
     long count;
@@ -163,65 +159,72 @@ __global__ __launch_bounds__(256) void k_adj_p2(AdjArgs a, int d) {
     }
     const long pi = psi_index(s, d, x, y, z);
     const float pt = a.psib[d][pi] - d1_axis(s.w1[d], el, eh);
-    a.F[d][pi] = prof_at(s, d, 1, k) * pt;
+    a.F[d][i] = prof_at(s, d, 1, k) * pt;
     a.psib[d][pi] = prof_at(s, d, 0, k) * pt;
 }
 
-// kinv E_d at coordinate c along d (Lbar outside the band); zero outside the grid
-__device__ __forceinline__ float kE(const DevShot &s, const AdjArgs &a, int d, int c, long i) {
-    const int n = coord_n(s, d);
-    if (c < 0 || c >= n) return 0.0f;
-    if (in_band(c, n, s.Llo[d], s.Lhi[d])) return prof_at(s, d, 2, c) * a.E[d][i];
-    return a.Lb[i];
-}
-__device__ __forceinline__ float dE(const DevShot &s, const AdjArgs &a, int d, int c, long i) {
-    const int n = coord_n(s, d);
-    if (c < 0 || c >= n || !in_slab(c, n, s.Llo[d], s.Lhi[d])) return 0.0f;
-    return prof_at(s, d, 3, c) * a.E[d][i];
-}
-
-// pass 3 on every point: lambda^n and the gradient accumulation
+// Pass 3 on every point: lambda^n and the gradient accumulation.  Along an
+// axis d whose band the wave does not touch, the axis term is D2_d Lbar.  A
+// wave that touches it evaluates the band form for all its lanes:
+//   D2_d(K) - D1_d(dkinv E_d) - D1_d(F_d),  K = kinv E_d in the band, Lbar outside,
+// with dkinv E_d and F_d zero outside the slab and every field zero outside
+// the grid.  At a lane outside the band this is D2_d Lbar with the same bits
+// (kinv = 1 and E_d = Lbar in the band outside the slab; the D1 terms are
+// exact zeros), so the per-lane branch is not needed.  A wave is one y row of
+// 64 x points (blockDim = 64 x 4), so the y and z tests are wave-uniform and
+// the x test is taken per 64-point tile.
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_p3(AdjArgs a, float inv_scale) {
     const DevShot &s = *a.s;
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int x0 = blockIdx.x * 64;
+    const int x = x0 + threadIdx.x;
+    const int y = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * 4 + threadIdx.y));
     const int z = blockIdx.z;
     if (x >= s.nx || y >= s.ny) return;
+    const int xe = min(x0 + 64, s.nx) - 1;   // last x of the tile
     const long i = fidx(s, x, y, z);
     const int cc[3] = {x, y, z};
     const long st[3] = {1, (long)s.P, (long)s.S};
+    // the band of an axis is an interval at each end of the grid, so a tile meets it iff one of its end points lies in it
+    const bool touch[3] = {in_band(x0, s.nx, s.Llo[0], s.Lhi[0]) || in_band(xe, s.nx, s.Llo[0], s.Lhi[0]),
+                           in_band(y, s.ny, s.Llo[1], s.Lhi[1]), in_band(z, s.nz, s.Llo[2], s.Lhi[2])};
     float acc = fmaf(2.0f, a.lam[i], -a.lamp[i]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int n = coord_n(s, d);
         const int c = cc[d];
         float t;
-        if (!in_band(c, n, s.Llo[d], s.Lhi[d])) {
+        if (!touch[d]) {
             float lo[4], hi[4];
 #pragma unroll
             for (int l = 1; l <= 4; ++l) {
-                const long im = i - l * st[d], ip = i + l * st[d];
-                lo[l - 1] = a.Lb[im];
-                hi[l - 1] = a.Lb[ip];
+                lo[l - 1] = a.Lb[i - l * st[d]];
+                hi[l - 1] = a.Lb[i + l * st[d]];
             }
             t = d2_axis(s.w2[d], a.Lb[i], lo, hi);
         } else {
-            float kl[4], kh[4], dl[4], dh[4], fl[4], fh[4];
-            int xm[3] = {x, y, z}, xp[3] = {x, y, z};
+            const int lo_ = s.Llo[d], hi_ = s.Lhi[d];
+            const float *pk = s.prof + (d * 4 + 2) * s.nmax, *pdk = s.prof + (d * 4 + 3) * s.nmax;
+            const float *E = a.E[d], *F = a.F[d];
+            // one tap at coordinate cq along d, element j: K and dkinv E_d
+            auto tap = [&](int cq, long j, float &kv, float &dv) {
+                const float e = E[j], lb = a.Lb[j];
+                const int cl = min(max(cq, 0), n - 1);
+                const bool ing = cq >= 0 && cq < n;
+                kv = ing && in_band(cq, n, lo_, hi_) ? pk[cl] * e : (ing ? lb : 0.0f);
+                dv = ing && in_slab(cq, n, lo_, hi_) ? pdk[cl] * e : 0.0f;
+            };
+            float kl[4], kh[4], dl[4], dh[4], fl[4], fh[4], kc, dc;
+            tap(c, i, kc, dc);
 #pragma unroll
             for (int l = 1; l <= 4; ++l) {
                 const long im = i - l * st[d], ip = i + l * st[d];
-                xm[d] = c - l;
-                xp[d] = c + l;
-                kl[l - 1] = kE(s, a, d, c - l, im);
-                kh[l - 1] = kE(s, a, d, c + l, ip);
-                dl[l - 1] = dE(s, a, d, c - l, im);
-                dh[l - 1] = dE(s, a, d, c + l, ip);
-                fl[l - 1] = slab_val(s, a.F[d], d, xm[0], xm[1], xm[2]);
-                fh[l - 1] = slab_val(s, a.F[d], d, xp[0], xp[1], xp[2]);
+                tap(c - l, im, kl[l - 1], dl[l - 1]);
+                tap(c + l, ip, kh[l - 1], dh[l - 1]);
+                fl[l - 1] = F[im];
+                fh[l - 1] = F[ip];
             }
-            t = d2_axis(s.w2[d], kE(s, a, d, c, i), kl, kh) - d1_axis(s.w1[d], dl, dh) - d1_axis(s.w1[d], fl, fh);
+            t = d2_axis(s.w2[d], kc, kl, kh) - d1_axis(s.w1[d], dl, dh) - d1_axis(s.w1[d], fl, fh);
         }
         acc = acc + t;
     }
@@ -301,7 +304,7 @@ static AdjLayout adj_layout(const ShotH &s, int every, int nt) {
     for (int d = 0; d < 3; ++d) {
         L.psib[d] = take(s.psi_elems[d] * 4);
         L.zetab[d] = take(s.psi_elems[d] * 4);
-        L.F[d] = take(s.psi_elems[d] * 4);
+        L.F[d] = take((s.Llo[d] + s.Lhi[d]) > 0 ? s.elems * 4 : 0);
         L.E[d] = take((s.Llo[d] + s.Lhi[d]) > 0 ? s.elems * 4 : 0);
         L.band[d] = take((size_t)s.nmax * 4);
     }
@@ -400,10 +403,12 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
     for (int d = 0; d < 3; ++d) {
         fdtd_launch_fill_zero(B + L.psib[d], a256(s.psi_elems[d] * 4), st);
         fdtd_launch_fill_zero(B + L.zetab[d], a256(s.psi_elems[d] * 4), st);
-        fdtd_launch_fill_zero(B + L.F[d], a256(s.psi_elems[d] * 4), st);
         a.psib[d] = (float *)(B + L.psib[d]);
         a.zetab[d] = (float *)(B + L.zetab[d]);
-        a.F[d] = (float *)(B + L.F[d]);
+        if (s.Llo[d] + s.Lhi[d] > 0) {
+            fdtd_launch_fill_zero(B + L.F[d], a256(s.elems * 4), st);
+            a.F[d] = (float *)origin4(s, B + L.F[d]);
+        }
         std::vector<int> bc = band_coords(s, d);
         a.nband[d] = (int)bc.size();
         if (!bc.empty()) {
@@ -451,6 +456,15 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
     char *seg = B + L.seg;
     const bool was_saving = ctx->saving;
     ctx->saving = false;
+    // largest per-axis thread counts of passes 1 (band points) and 2 (slab points)
+    long p1_max = 0, p2_max = 0;
+    for (int d = 0; d < 3; ++d) {
+        const int n1 = d == 0 ? s.ny : s.nx, n2 = d == 2 ? s.ny : s.nz;
+        p1_max = std::max(p1_max, (long)a.nband[d] * n1 * n2);
+        if (s.Llo[d] + s.Lhi[d] > 0)
+            p2_max = std::max(p2_max, d == 0 ? (long)s.LX * s.ny * s.nz
+                                             : (d == 1 ? (long)s.nx * s.LY * s.nz : (long)s.nx * s.ny * s.LZ));
+    }
     const int nck = (nt + every - 1) / every;
     const float inv_scale = (float)(1.0 / s.scale);
     int *stepc = (int *)fdtd_ws(ctx, ctx->o_stepc);
@@ -478,18 +492,10 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
             a.up = origin_t(s, seg + (size_t)(n - s0 + 2) * fb);
             a.u0 = origin_t(s, seg + (size_t)(n - s0 + 1) * fb);
             a.um = origin_t(s, seg + (size_t)(n - s0) * fb);
-            for (int d = 0; d < 3; ++d) {
-                if (a.nband[d] == 0) continue;
-                const int n1 = d == 0 ? s.ny : s.nx, n2 = d == 2 ? s.ny : s.nz;
-                long tot = (long)a.nband[d] * n1 * n2;
-                hipLaunchKernelGGL(k_adj_p1, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a, d);
-            }
-            for (int d = 0; d < 3; ++d) {
-                if (s.Llo[d] + s.Lhi[d] == 0) continue;
-                long cnt = d == 0 ? (long)s.LX * s.ny * s.nz : (d == 1 ? (long)s.nx * s.LY * s.nz
-                                                                       : (long)s.nx * s.ny * s.LZ);
-                hipLaunchKernelGGL(k_adj_p2, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, a, d);
-            }
+            if (p1_max > 0)   // the three axes in one launch (disjoint outputs)
+                hipLaunchKernelGGL(k_adj_p1, dim3((unsigned)((p1_max + 255) / 256), 3), dim3(256), 0, st, a);
+            if (p2_max > 0)
+                hipLaunchKernelGGL(k_adj_p2, dim3((unsigned)((p2_max + 255) / 256), 3), dim3(256), 0, st, a);
             if (ctx->storage == FDTD_F16) launch_p3<_Float16>(a, s, inv_scale, st);
             else if (ctx->storage == FDTD_BF16) launch_p3<__bf16>(a, s, inv_scale, st);
             else launch_p3<float>(a, s, inv_scale, st);
