@@ -13,15 +13,16 @@ from helpers import oracle_grid, rel_l2, v32
 pytestmark = pytest.mark.gpu
 
 
-def _problem(n=(40, 36, 32), L=6, nt=120, seed=21, nrec=10):
+def _problem(n=(40, 36, 32), L=6, nt=120, seed=21, nrec=10, cpml=None):
     rng = np.random.default_rng(seed)
+    cpml = (L,) * 6 if cpml is None else tuple(cpml)
     nx, ny, nz = n
     vt = synth.layered_model((nz, ny, nx), rng, nlayers=(3, 5), smooth_sigma=2.0)
     v0 = vt * (1.0 + 0.03 * synth.smooth_field((nz, ny, nx), rng, sigma=3.0))
     dt = synth.dt_from_courant(max(vt.max(), v0.max()), (10.0,) * 3)
     rec = synth.receivers_on_plane(n, L, nrec, rng)
     src = np.array([[nx // 2, ny // 2, nz // 2]], np.int32)
-    w = synth.Workload("adj", tuple(n), (10.0,) * 3, dt, nt, (L,) * 6, v0, src, synth.ricker(nt, dt, 25.0), rec)
+    w = synth.Workload("adj", tuple(n), (10.0,) * 3, dt, nt, cpml, v0, src, synth.ricker(nt, dt, 25.0), rec)
     return w, vt
 
 
@@ -89,6 +90,36 @@ def test_autograd_function(adj_case):
     J = 0.5 * ((tr.double() - torch.from_numpy(dobs).cuda()) ** 2).sum()
     J.backward()
     assert rel_l2(v.grad.double().cpu().numpy(), gref) <= 1e-4
+
+
+def test_gradient_wide_uneven_layers():
+    """Several 64-point x tiles, of which the middle ones do not meet the x
+    band, layers of different widths on each face and faces without layers."""
+    from oracle import oracle as O
+
+    w, vt = _problem(n=(150, 26, 24), L=5, nt=160, seed=23, nrec=8, cpml=(7, 5, 0, 6, 4, 0))
+    # source beside the low x layer; receivers inside the x, y and z layers and in the open,
+    # so that each band holds a large part of the gradient (about half of its norm or more)
+    src = np.array([[14, 13, 12]], np.int32)
+    rec = np.array([[3, 13, 12], [5, 22, 12], [8, 13, 2], [40, 4, 12], [60, 13, 20], [100, 13, 12],
+                    [146, 13, 12], [14, 24, 1]], np.int32)
+    w = synth.Workload("adj", w.n, w.h, w.dt, w.nt, w.cpml, w.v, src, w.wavelet, rec)
+    g = oracle_grid(w)
+    wt = synth.Workload("t", w.n, w.h, w.dt, w.nt, w.cpml, vt, w.src, w.wavelet, w.rec)
+    dobs = O.forward(g, v32(wt), w.nt, w.src, w.wavelet, w.rec)["traces"]
+    fwd = O.forward(g, v32(w), w.nt, w.src, w.wavelet, w.rec, keep_lapf=True)
+    gref = O.gradient(g, v32(w), w.nt, w.src, w.wavelet, w.rec, fwd["traces"] - dobs, fwd=fwd)
+    d, gg = _gpu_grad(w, dobs, every=16)
+    assert rel_l2(d, fwd["traces"]) <= 1e-5
+    e = rel_l2(gg, gref)
+    print("gradient rel-L2 vs oracle (wide, uneven layers): %.3e" % e, flush=True)
+    assert e <= 1e-4
+    # the same bar on each axis's band (layer plus 4 cells) on its own
+    z, y, x = np.meshgrid(np.arange(24), np.arange(26), np.arange(150), indexing="ij")
+    for name, m in (("x", (x < 7 + 4) | (x >= 150 - 5 - 4)), ("y", y >= 26 - 6 - 4), ("z", z < 4 + 4)):
+        eb = rel_l2(gg[m], gref[m])
+        print("  %s band: %.3e" % (name, eb), flush=True)
+        assert eb <= 1e-4
 
 
 def test_adjoint_state_errors():
