@@ -20,6 +20,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
 COPY_CEILING_GBS = 5090.0   # plain 1 GiB device copy, read + write (copy_1GiB_counters.txt)
+STREAM_CEILING_GBS = 5730.0  # o = a + b * c over 400 MiB FP32 arrays: the interior's 3-read 1-write mix
+                             # (--stream-probe 400; stream_probe_400MiB_kernel_trace.txt)
 
 
 def slab_points_axis(n, cpml, d):
@@ -562,6 +564,7 @@ def main():
                      "measured_frac": (round(traffic / (upd[0] / 1e3) / 1e9 / PEAK_HBM_GBS, 4)
                                        if traffic else None),
                      "copy_ceiling_gbs": COPY_CEILING_GBS,
+                     "stream_ceiling_gbs": STREAM_CEILING_GBS,
                      "kernel": "%s (update of the points outside the layer bands)" % zmarch_instance(plan),
                      "kernel_ms": round(upd[0], 5), "algorithmic_bytes_per_launch": upd_bytes},
         "step_algorithmic_gbs": round(step_bytes(w.n, w.cpml) / (ms / K / 1e3) / 1e9, 1),
