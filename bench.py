@@ -430,12 +430,58 @@ def cpu_baseline(w, steps=5):
                 % (steps, w.n[0], w.n[1], w.n[2]))
 
 
+PAPER_PV_MPTS = {320: 3289.58, 480: 2889.58, 544: 2900.14, 640: 2909.64, 800: 2920.36}   # one Quadro RTX 6000
+
+
+def pv_leg(sizes=(320, 480, 544, 640, 800), K=64, W=4):
+    """The paper's own first-order pressure-velocity system (two stages per
+    step, six memory variables) on its single-GPU throughput grids: N^3 with
+    20-cell layers on every face, lambda = 0.05, 64 steps from an initial
+    pulse, FP32.  Mpts/s, and the step's algorithmic bytes over its time
+    (48 B per point: p read, v read and written in the velocity stage; v read,
+    p read and written in the pressure stage; plus a read and write of a
+    memory variable per layer point and axis in each stage).  The paper's
+    numbers for the same grids (another GPU) ride along as context."""
+    import torch
+
+    from paper_2606_06910_amd import PVPropagator
+
+    out = {}
+    for N in sizes:
+        s = PVPropagator((N, N, N), (20,) * 6, 0.05)
+        g = torch.arange(N, device="cuda", dtype=torch.float32) - (N - 1) / 2.0
+        r2 = g[:, None, None] ** 2 + g[None, :, None] ** 2 + g[None, None, :] ** 2
+        s.set_pressure(torch.exp(-r2 / 30.0))
+        del g, r2
+        s.step(W)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.step(K)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        assert torch.isfinite(s.get_pressure()).all()
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        slab = slab_points((N, N, N), (20,) * 6)
+        nbytes = 48 * N ** 3 + 16 * slab
+        mpts = N ** 3 * K / (ms / 1e3) / 1e6
+        out["n%d" % N] = {"mpts": round(mpts, 1), "ms_per_step": round(ms / K, 4),
+                          "algorithmic_gbs": round(nbytes / (ms / K / 1e3) / 1e9, 1),
+                          "paper_rtx6000_mpts": PAPER_PV_MPTS.get(N)}
+    out["workload"] = "first-order p-v, N^3, 20-cell CPML on 6 faces, lambda 0.05, %d steps, FP32" % K
+    return out
+
+
 LEGS = {
     "storage_768": lambda: precision_leg(),
     "batched_24": lambda: batched_leg(),
     "small_64": lambda: small_leg(),
     "pencil_1024x384x384": lambda: pencil_leg(),
     "adjoint_3_smallest": lambda: adjoint_leg(),
+    "pv_paper_grids": lambda: pv_leg(),
 }
 
 
@@ -581,7 +627,7 @@ def main():
         out["variants_mpts"] = var
     if not args.no_extra:
         torch.cuda.empty_cache()
-        legs = ["batched_24", "small_64", "pencil_1024x384x384", "adjoint_3_smallest"]
+        legs = ["batched_24", "small_64", "pencil_1024x384x384", "adjoint_3_smallest", "pv_paper_grids"]
         if not args.no_storage_leg:
             legs.insert(0, "storage_768")
         for name in legs:

@@ -9,6 +9,7 @@ the library must be built (see build_lib.py).
 from ._lib import (BF16, F16, F32, FACE_DIRICHLET, FACE_GHOST, VARIANT_AUTO, VARIANT_NAIVE, VARIANT_TBLOCK,
                    VARIANT_ZMARCH, FDTDError, FDTDValueError, lib)
 from .propagator import Propagator, Shot
+from .pv import PVPropagator
 
-__all__ = ["Propagator", "Shot", "lib", "FDTDError", "FDTDValueError", "F32", "F16", "BF16", "FACE_DIRICHLET",
+__all__ = ["Propagator", "Shot", "PVPropagator", "lib", "FDTDError", "FDTDValueError", "F32", "F16", "BF16", "FACE_DIRICHLET",
            "FACE_GHOST", "VARIANT_AUTO", "VARIANT_NAIVE", "VARIANT_ZMARCH", "VARIANT_TBLOCK"]

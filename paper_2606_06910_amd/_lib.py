@@ -1,4 +1,4 @@
-"""ctypes binding of libfdtd.so (the C ABI declared in include/fdtd.h).
+"""ctypes binding of libfdtd.so (the C ABI declared in include/fdtd.h and include/fdtd_pv.h).
 
 Argument marshalling only: every step of the path runs in the library's
 HIP kernels.  There is no fallback: if the library is missing or cannot be
@@ -49,6 +49,19 @@ class ShotConfig(ctypes.Structure):
     ]
 
 
+class PVConfig(ctypes.Structure):
+    """Mirror of fdtd_pv_config (include/fdtd_pv.h)."""
+
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3),
+        ("cpml", ctypes.c_int32 * 6),
+        ("lam", ctypes.c_double),
+        ("R", ctypes.c_double),
+        ("kappa_max", ctypes.c_double),
+        ("alpha_frac", ctypes.c_double),
+    ]
+
+
 class FDTDError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__("%s: %s" % (STATUS.get(status, status), msg))
@@ -95,6 +108,17 @@ _SIGS = {
     "fdtd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fdtd_last_error": (ctypes.c_char_p, [_P]),
     "fdtd_destroy": (None, [_P]),
+    # first-order pressure-velocity path (include/fdtd_pv.h)
+    "fdtd_pv_create": (ctypes.c_int, [ctypes.POINTER(PVConfig), _P, ctypes.POINTER(_P)]),
+    "fdtd_pv_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "fdtd_pv_bind_workspace": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "fdtd_pv_set_pressure": (ctypes.c_int, [_P, _P]),
+    "fdtd_pv_get_pressure": (ctypes.c_int, [_P, _P]),
+    "fdtd_pv_set_source": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32]),
+    "fdtd_pv_set_receivers": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32]),
+    "fdtd_pv_step": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "fdtd_pv_last_error": (ctypes.c_char_p, [_P]),
+    "fdtd_pv_destroy": (None, [_P]),
 }
 
 

@@ -1,4 +1,4 @@
-"""C ABI: the library loads, exports every entry point of include/fdtd.h, and
+"""C ABI: the library loads, exports every entry point of include/*.h, and
 validates configurations on the host (no GPU work involved)."""
 import ctypes
 import os
@@ -10,15 +10,19 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    txt = open(os.path.join(ROOT, "include", "fdtd.h")).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(fdtd_[a-z_0-9]+)\s*\(", txt)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names.update(re.findall(r"\b(fdtd_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
     names = _declared()
     for must in ["fdtd_create", "fdtd_set_velocity", "fdtd_inject_source", "fdtd_step", "fdtd_record_receivers",
-                 "fdtd_adjoint"]:
+                 "fdtd_adjoint", "fdtd_pv_create", "fdtd_pv_step"]:
         assert must in names
 
 
@@ -153,3 +157,30 @@ def test_batch_default_plan():
     assert L.fdtd_get_plan(ctx, 0, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k)) == 0
     assert r.value != 1
     L.fdtd_destroy(ctx)
+
+
+def test_pv_create_validates_on_the_host():
+    """The first-order path's context: sizes and argument checks, no GPU work."""
+    from paper_2606_06910_amd import _lib
+
+    L = _lib.lib()
+
+    def make(n=(32, 30, 28), cpml=(5,) * 6, lam=0.05):
+        c = _lib.PVConfig()
+        c.n[:] = list(n)
+        c.cpml[:] = list(cpml)
+        c.lam = lam
+        ctx = ctypes.c_void_p()
+        return L.fdtd_pv_create(ctypes.byref(c), None, ctypes.byref(ctx)), ctx
+
+    rc, ctx = make()
+    assert rc == 0
+    nb = ctypes.c_size_t()
+    assert L.fdtd_pv_workspace_size(ctx, ctypes.byref(nb)) == 0
+    assert nb.value >= 10 * (32 + 8) * (30 + 8) * (28 + 8) * 4      # ten padded fields
+    assert L.fdtd_pv_step(ctx, 1) == -3                           # no workspace bound
+    L.fdtd_pv_destroy(ctx)
+    for kw in (dict(lam=0.0), dict(lam=0.8), dict(n=(8, 30, 28)), dict(cpml=(16, 16, 5, 5, 5, 5)),
+               dict(cpml=(-1, 5, 5, 5, 5, 5))):
+        rc, _ = make(**kw)
+        assert rc == -1, kw
