@@ -59,6 +59,7 @@ class PVConfig(ctypes.Structure):
         ("R", ctypes.c_double),
         ("kappa_max", ctypes.c_double),
         ("alpha_frac", ctypes.c_double),
+        ("variant", ctypes.c_int32),
     ]
 
 

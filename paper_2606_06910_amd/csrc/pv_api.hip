@@ -7,6 +7,8 @@
 //             memory variable advanced first inside axis d's layer
 //  k_pv_pres  pressure stage: p -= lambda sum_d (kinv_d delta_d v_d + psi_p,d),
 //             then the point source
+//  k_pv_vel_zm, k_pv_pres_zm  the same stages z-marching: register queue of
+//             the z taps, x / y taps from an LDS plane (the default variant)
 //  k_pv_rec   receiver gather
 //
 // Layout: every field x fastest with a zero frame of 4 points on each side
@@ -29,6 +31,12 @@ namespace {
 constexpr int kR = 4;        // stencil radius
 constexpr int kLead = 128;   // leading pad of every field (elements)
 constexpr int kNF = 10;      // p, v_x, v_y, v_z, psi_v x3, psi_p x3
+constexpr int kRY = 4;       // z-march: rows per thread
+constexpr int kNW = 4;       // z-march: waves per workgroup
+constexpr int kTY = kRY * kNW;          // tile rows (tile: 64 x kTY)
+constexpr int kLW = 64 + 2 * kR;        // LDS row length with the x halo
+constexpr int kLH = kTY + 2 * kR;       // LDS rows with the y halo
+constexpr int kZC = 32;                 // z-march: planes per chunk
 
 // central first-derivative weights of order 8 at unit spacing (a_1 .. a_4)
 constexpr double kA1[kR + 1] = {0.0, 4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
@@ -96,6 +104,238 @@ __global__ __launch_bounds__(256) void k_pv_pres(PvArgs g) {
     if (g.wav && g.step < g.wav_n && x == g.src[0] && y == g.src[1] && z == g.src[2])
         pn = fmaf(g.lam, g.wav[g.step], pn);
     g.p[i] = pn;
+}
+
+// ---------------------------------------------------------------------------
+// z-marching stages.  A workgroup of kNW waves owns a 64 x kTY xy tile and a
+// chunk of kZC planes; lane l of wave w owns column x0 + l and rows
+// w kRY .. w kRY + kRY - 1.  The z taps come from a register queue of the
+// field's planes z - 4 .. z + 4 (own rows), the x and y taps from the plane z
+// staged in LDS with its halo (two buffers: one barrier per plane).  Every
+// tap is summed in the order of pv_delta, so the results equal the
+// one-thread-per-point kernels bit for bit.  Points outside the grid (tile
+// overhang) compute on the zero frame and store nothing.
+// grid: (ceil(nx / 64), ceil(ny / kTY), ceil(nz / kZC)), block 64 x kNW
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float zm_d(const float *w, float a1, float b1, float a2, float b2, float a3, float b3,
+                                      float a4, float b4) {
+    // sum_l w_l (a_l - b_l), a = f_{+l}, b = f_{-l}, in pv_delta's order
+    float acc = w[1] * (a1 - b1);
+    acc = fmaf(w[2], a2 - b2, acc);
+    acc = fmaf(w[3], a3 - b3, acc);
+    acc = fmaf(w[4], a4 - b4, acc);
+    return acc;
+}
+
+// halo slots of a plane: x halo (4 columns each side, kTY rows), y halo (4 rows
+// each side, 64 columns); 'xh' / 'yh' select which are staged
+template <bool XH, bool YH> struct Halo {
+    static constexpr int NX = XH ? 2 * kR * kTY : 0;
+    static constexpr int NY = YH ? 2 * kR * 64 : 0;
+    static constexpr int N = NX + NY;
+    static constexpr int PER = (N + 64 * kNW - 1) / (64 * kNW);
+};
+
+constexpr long kNoHalo = -(1L << 62);   // halo slot without a value (reads as zero)
+
+template <bool XH, bool YH>
+__device__ __forceinline__ void halo_setup(int t, int x0, int y0, long P, long (&off)[Halo<XH, YH>::PER],
+                                           int (&slot)[Halo<XH, YH>::PER]) {
+    using H = Halo<XH, YH>;
+#pragma unroll
+    for (int k = 0; k < H::PER; ++k) {
+        const int i = t + 64 * kNW * k;
+        off[k] = kNoHalo;
+        slot[k] = kLH * kLW;            // dummy slot
+        if (i < H::NX) {
+            const int row = i / (2 * kR), c8 = i % (2 * kR);
+            const int lx = c8 < kR ? c8 - kR : 64 + (c8 - kR);
+            slot[k] = (row + kR) * kLW + lx + kR;
+            off[k] = (long)(y0 + row) * P + x0 + lx;
+        } else if (i < H::N) {
+            const int j = i - H::NX, r8 = j / 64, c = j % 64;
+            const int ly = r8 < kR ? r8 - kR : kTY + (r8 - kR);
+            slot[k] = (ly + kR) * kLW + c + kR;
+            off[k] = (long)(y0 + ly) * P + x0 + c;
+        }
+    }
+}
+
+__global__ __launch_bounds__(64 * kNW) void k_pv_vel_zm(PvArgs g) {
+    using H = Halo<true, true>;
+    __shared__ float sm[2][kLH * kLW + 1];
+    const int lane = threadIdx.x, wv = threadIdx.y, t = wv * 64 + lane;
+    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kTY;
+    const int za = blockIdx.z * kZC, zb = min(za + kZC, g.n[2]);
+    const int x = x0 + lane;
+    const long P = g.P, S = g.S;
+    long hoff[H::PER];
+    int hslot[H::PER];
+    halo_setup<true, true>(t, x0, y0, P, hoff, hslot);
+    float q[2 * kR + 1][kRY];     // p at z - 4 .. z + 4, own rows
+    float hq[H::PER];             // halo of plane z
+#pragma unroll
+    for (int o = 0; o < 2 * kR + 1; ++o)
+#pragma unroll
+        for (int r = 0; r < kRY; ++r) q[o][r] = g.p[(long)(za - kR + o) * S + (long)(y0 + wv * kRY + r) * P + x];
+#pragma unroll
+    for (int k = 0; k < H::PER; ++k) hq[k] = hoff[k] != kNoHalo ? g.p[(long)za * S + hoff[k]] : 0.0f;
+    float vc[3][kRY];             // v_d of plane z, own rows (read, updated, written back)
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int r = 0; r < kRY; ++r) vc[d][r] = g.v[d][(long)za * S + (long)(y0 + wv * kRY + r) * P + x];
+    int buf = 0;
+    for (int z = za; z < zb; ++z) {
+        float *L = sm[buf];
+#pragma unroll
+        for (int r = 0; r < kRY; ++r) L[(wv * kRY + r + kR) * kLW + lane + kR] = q[kR][r];
+#pragma unroll
+        for (int k = 0; k < H::PER; ++k) L[hslot[k]] = hq[k];
+        // loads ahead: p plane z + 5 (own rows) and the halo of plane z + 1
+        float nq[kRY], nh[H::PER];
+#pragma unroll
+        for (int r = 0; r < kRY; ++r)   // (the last frame plane is nz + 3; plane nz + 4 is never used)
+            nq[r] = z + kR + 1 <= g.n[2] + kR - 1 ? g.p[(long)(z + kR + 1) * S + (long)(y0 + wv * kRY + r) * P + x]
+                                                  : 0.0f;
+#pragma unroll
+        for (int k = 0; k < H::PER; ++k) nh[k] = hoff[k] != kNoHalo ? g.p[(long)(z + 1) * S + hoff[k]] : 0.0f;
+        float vn[3][kRY];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int r = 0; r < kRY; ++r) vn[d][r] = g.v[d][(long)(z + 1) * S + (long)(y0 + wv * kRY + r) * P + x];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRY; ++r) {
+            const int y = y0 + wv * kRY + r;
+            const float *c = L + (wv * kRY + r + kR) * kLW + lane + kR;
+            const float gx = zm_d(g.w, c[1], c[-1], c[2], c[-2], c[3], c[-3], c[4], c[-4]);
+            const float gy = zm_d(g.w, c[kLW], c[-kLW], c[2 * kLW], c[-2 * kLW], c[3 * kLW], c[-3 * kLW],
+                                  c[4 * kLW], c[-4 * kLW]);
+            const float gz = zm_d(g.w, q[kR + 1][r], q[kR - 1][r], q[kR + 2][r], q[kR - 2][r], q[kR + 3][r],
+                                  q[kR - 3][r], q[kR + 4][r], q[kR - 4][r]);
+            if (x < g.n[0] && y < g.n[1]) {
+                const long i = (long)z * S + (long)y * P + x;
+                const int cc[3] = {x, y, z};
+                const float gr[3] = {gx, gy, gz};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const float tt = pv_stretched(g, d, cc[d], gr[d], g.psv[d], i);
+                    g.v[d][i] = fmaf(-g.lam, tt, vc[d][r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int r = 0; r < kRY; ++r) vc[d][r] = vn[d][r];
+#pragma unroll
+        for (int o = 0; o < 2 * kR; ++o)
+#pragma unroll
+            for (int r = 0; r < kRY; ++r) q[o][r] = q[o + 1][r];
+#pragma unroll
+        for (int r = 0; r < kRY; ++r) q[2 * kR][r] = nq[r];
+#pragma unroll
+        for (int k = 0; k < H::PER; ++k) hq[k] = nh[k];
+        buf ^= 1;
+    }
+}
+
+__global__ __launch_bounds__(64 * kNW) void k_pv_pres_zm(PvArgs g) {
+    using HX = Halo<true, false>;
+    using HY = Halo<false, true>;
+    __shared__ float sx[2][kLH * kLW + 1];   // v_x plane with its x halo
+    __shared__ float sy[2][kLH * kLW + 1];   // v_y plane with its y halo
+    const int lane = threadIdx.x, wv = threadIdx.y, t = wv * 64 + lane;
+    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kTY;
+    const int za = blockIdx.z * kZC, zb = min(za + kZC, g.n[2]);
+    const int x = x0 + lane;
+    const long P = g.P, S = g.S;
+    long xoff[HX::PER], yoff[HY::PER];
+    int xslot[HX::PER], yslot[HY::PER];
+    halo_setup<true, false>(t, x0, y0, P, xoff, xslot);
+    halo_setup<false, true>(t, x0, y0, P, yoff, yslot);
+    float q[2 * kR + 1][kRY];     // v_z at z - 4 .. z + 4, own rows
+#pragma unroll
+    for (int o = 0; o < 2 * kR + 1; ++o)
+#pragma unroll
+        for (int r = 0; r < kRY; ++r) q[o][r] = g.v[2][(long)(za - kR + o) * S + (long)(y0 + wv * kRY + r) * P + x];
+    float cx[kRY], cy[kRY], hx[HX::PER], hy[HY::PER];   // plane z of v_x, v_y (own rows and halo)
+#pragma unroll
+    for (int r = 0; r < kRY; ++r) {
+        const long o = (long)za * S + (long)(y0 + wv * kRY + r) * P + x;
+        cx[r] = g.v[0][o];
+        cy[r] = g.v[1][o];
+    }
+#pragma unroll
+    for (int k = 0; k < HX::PER; ++k) hx[k] = xoff[k] != kNoHalo ? g.v[0][(long)za * S + xoff[k]] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < HY::PER; ++k) hy[k] = yoff[k] != kNoHalo ? g.v[1][(long)za * S + yoff[k]] : 0.0f;
+    float pc[kRY];                // p of plane z, own rows
+#pragma unroll
+    for (int r = 0; r < kRY; ++r) pc[r] = g.p[(long)za * S + (long)(y0 + wv * kRY + r) * P + x];
+    int buf = 0;
+    for (int z = za; z < zb; ++z) {
+        float *LX = sx[buf], *LY = sy[buf];
+#pragma unroll
+        for (int r = 0; r < kRY; ++r) {
+            LX[(wv * kRY + r + kR) * kLW + lane + kR] = cx[r];
+            LY[(wv * kRY + r + kR) * kLW + lane + kR] = cy[r];
+        }
+#pragma unroll
+        for (int k = 0; k < HX::PER; ++k) LX[xslot[k]] = hx[k];
+#pragma unroll
+        for (int k = 0; k < HY::PER; ++k) LY[yslot[k]] = hy[k];
+        // loads ahead: v_z plane z + 5, v_x / v_y / p plane z + 1 (own rows and halo)
+        float nq[kRY], pn1[kRY];
+#pragma unroll
+        for (int r = 0; r < kRY; ++r) {
+            const long o = (long)(y0 + wv * kRY + r) * P + x;
+            nq[r] = z + kR + 1 <= g.n[2] + kR - 1 ? g.v[2][(long)(z + kR + 1) * S + o] : 0.0f;
+            cx[r] = g.v[0][(long)(z + 1) * S + o];
+            cy[r] = g.v[1][(long)(z + 1) * S + o];
+            pn1[r] = g.p[(long)(z + 1) * S + o];
+        }
+#pragma unroll
+        for (int k = 0; k < HX::PER; ++k) hx[k] = xoff[k] != kNoHalo ? g.v[0][(long)(z + 1) * S + xoff[k]] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < HY::PER; ++k) hy[k] = yoff[k] != kNoHalo ? g.v[1][(long)(z + 1) * S + yoff[k]] : 0.0f;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRY; ++r) {
+            const int y = y0 + wv * kRY + r;
+            const int li = (wv * kRY + r + kR) * kLW + lane + kR;
+            const float *ax = LX + li, *ay = LY + li;
+            const float gx = zm_d(g.w, ax[1], ax[-1], ax[2], ax[-2], ax[3], ax[-3], ax[4], ax[-4]);
+            const float gy = zm_d(g.w, ay[kLW], ay[-kLW], ay[2 * kLW], ay[-2 * kLW], ay[3 * kLW], ay[-3 * kLW],
+                                  ay[4 * kLW], ay[-4 * kLW]);
+            const float gz = zm_d(g.w, q[kR + 1][r], q[kR - 1][r], q[kR + 2][r], q[kR - 2][r], q[kR + 3][r],
+                                  q[kR - 3][r], q[kR + 4][r], q[kR - 4][r]);
+            if (x < g.n[0] && y < g.n[1]) {
+                const long i = (long)z * S + (long)y * P + x;
+                const int cc[3] = {x, y, z};
+                const float gr[3] = {gx, gy, gz};
+                float div = 0.0f;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) div += pv_stretched(g, d, cc[d], gr[d], g.psp[d], i);
+                float pn = fmaf(-g.lam, div, pc[r]);
+                if (g.wav && g.step < g.wav_n && x == g.src[0] && y == g.src[1] && z == g.src[2])
+                    pn = fmaf(g.lam, g.wav[g.step], pn);
+                g.p[i] = pn;
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < 2 * kR; ++o)
+#pragma unroll
+            for (int r = 0; r < kRY; ++r) q[o][r] = q[o + 1][r];
+#pragma unroll
+        for (int r = 0; r < kRY; ++r) {
+            q[2 * kR][r] = nq[r];
+            pc[r] = pn1[r];
+        }
+        buf ^= 1;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_pv_rec(const float *__restrict__ p, const int32_t *__restrict__ rec,
@@ -226,6 +466,7 @@ int fdtd_pv_create(const fdtd_pv_config *cfg, void *hip_stream, fdtd_pv_ctx **ou
     }
     if (!(cfg->lambda > 0.0 && cfg->lambda <= 0.7)) return FDTD_EINVAL;
     if (cfg->R < 0 || cfg->R >= 1 || cfg->kappa_max < 0 || cfg->alpha_frac < 0) return FDTD_EINVAL;
+    if (cfg->variant < 0 || cfg->variant > 2) return FDTD_EINVAL;
     fdtd_pv_ctx *ctx = new fdtd_pv_ctx;
     ctx->c = *cfg;
     if (ctx->c.R == 0) ctx->c.R = 1e-8;
@@ -240,7 +481,8 @@ int fdtd_pv_create(const fdtd_pv_config *cfg, void *hip_stream, fdtd_pv_ctx **ou
     ctx->nmax = std::max(ctx->n[0], std::max(ctx->n[1], ctx->n[2]));
     ctx->P = (long)((ctx->n[0] + kR + 63) / 64) * 64;
     ctx->S = (long)(ctx->n[1] + 2 * kR) * ctx->P;
-    ctx->elems = (size_t)kLead + (size_t)(ctx->n[2] + 2 * kR) * ctx->S + 128;
+    // trailing pad: a z-march tile may overhang the last row by up to kTY - 1 rows (plus its halo)
+    ctx->elems = (size_t)kLead + (size_t)(ctx->n[2] + 2 * kR) * ctx->S + (size_t)(kTY + 2 * kR) * ctx->P + 128;
     ctx->field_bytes = a256(ctx->elems * 4);
     ctx->prof_bytes = a256((size_t)3 * 3 * ctx->nmax * 4);
     ctx->total = (size_t)kNF * ctx->field_bytes + ctx->prof_bytes;
@@ -330,10 +572,21 @@ int fdtd_pv_step(fdtd_pv_ctx *ctx, int32_t nsteps) {
     if (!ctx || nsteps < 0) return FDTD_EINVAL;
     if (!ctx->ws) PVFAIL(ctx, FDTD_ESTATE, "no workspace bound");
     const dim3 grid((ctx->n[0] + 63) / 64, (ctx->n[1] + 3) / 4, ctx->n[2]), block(64, 4);
+    const dim3 zgrid((ctx->n[0] + 63) / 64, (ctx->n[1] + kTY - 1) / kTY, (ctx->n[2] + kZC - 1) / kZC),
+        zblock(64, kNW);
+    // automatic choice: the z-march from 2^27 points up (measured crossover between
+    // 480^3 and 544^3: below it its workgroups fill the chip in too few rounds)
+    const double npts = (double)ctx->n[0] * ctx->n[1] * ctx->n[2];
+    const bool naive = ctx->c.variant == 1 || (ctx->c.variant == 0 && npts < (double)(1L << 27));
     for (int s = 0; s < nsteps; ++s) {
         PvArgs g = pv_args(ctx);
-        hipLaunchKernelGGL(k_pv_vel, grid, block, 0, ctx->st, g);
-        hipLaunchKernelGGL(k_pv_pres, grid, block, 0, ctx->st, g);
+        if (naive) {
+            hipLaunchKernelGGL(k_pv_vel, grid, block, 0, ctx->st, g);
+            hipLaunchKernelGGL(k_pv_pres, grid, block, 0, ctx->st, g);
+        } else {
+            hipLaunchKernelGGL(k_pv_vel_zm, zgrid, zblock, 0, ctx->st, g);
+            hipLaunchKernelGGL(k_pv_pres_zm, zgrid, zblock, 0, ctx->st, g);
+        }
         const long row = ctx->step - ctx->rec0;
         if (ctx->nrec > 0 && row < ctx->cap)
             hipLaunchKernelGGL(k_pv_rec, dim3((ctx->nrec + 255) / 256), dim3(256), 0, ctx->st, (const float *)g.p,

@@ -23,7 +23,7 @@ def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
 class PVPropagator:
     """One grid of the first-order system: p, v_x, v_y, v_z and the layer memory."""
 
-    def __init__(self, n: Sequence[int], cpml: Sequence[int] = (20,) * 6, lam: float = 0.05,
+    def __init__(self, n: Sequence[int], cpml: Sequence[int] = (20,) * 6, lam: float = 0.05, variant: int = 0,
                  device: str = "cuda", stream: Optional[torch.cuda.Stream] = None):
         self.L = _lib.lib()
         self.n = tuple(int(x) for x in n)
@@ -34,6 +34,7 @@ class PVPropagator:
         cfg.n[:] = list(self.n)
         cfg.cpml[:] = [int(x) for x in cpml]
         cfg.lam = float(lam)
+        cfg.variant = int(variant)
         ctx = ctypes.c_void_p()
         self._check(self.L.fdtd_pv_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
                                           ctypes.byref(ctx)), None)

@@ -23,12 +23,12 @@ def _coords(n):
     return x, y, z
 
 
-def _gpu(n, cpml, lam, nt, src=None, wav=None, rec=None, p0=None, snap_every=0):
+def _gpu(n, cpml, lam, nt, src=None, wav=None, rec=None, p0=None, snap_every=0, variant=0):
     import torch
 
     from paper_2606_06910_amd import PVPropagator
 
-    s = PVPropagator(n, cpml, lam)
+    s = PVPropagator(n, cpml, lam, variant=variant)
     if p0 is not None:
         s.set_pressure(torch.from_numpy(p0.astype(np.float32)))
     if src is not None:
@@ -59,8 +59,9 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_pv_matches_oracle(name):
+def test_pv_matches_oracle(name, variant):
     c = CASES[name]
     rng = np.random.default_rng(7)
     n = c["n"]
@@ -68,10 +69,26 @@ def test_pv_matches_oracle(name):
     rec = rec.astype(np.int32)
     wav = synth.ricker(c["nt"], c["lam"], c["f0"])         # time in units of h / c (wavelength 1 / f0 cells)
     ref = P.forward(n, c["cpml"], c["lam"], c["nt"], c["src"], wav, rec, snap_every=30)
-    tr, snaps, p = _gpu(n, c["cpml"], c["lam"], c["nt"], c["src"], wav, rec, snap_every=30)
+    tr, snaps, p = _gpu(n, c["cpml"], c["lam"], c["nt"], c["src"], wav, rec, snap_every=30, variant=variant)
     e_tr, e_st, e_p = rel_l2(tr, ref["traces"]), rel_l2(snaps, ref["snaps"]), rel_l2(p, ref["p"])
-    print("%s: traces %.3e  snapshots %.3e  final p %.3e" % (name, e_tr, e_st, e_p), flush=True)
+    print("%s/%d: traces %.3e  snapshots %.3e  final p %.3e" % (name, variant, e_tr, e_st, e_p), flush=True)
     assert e_tr <= 1e-5 and e_st <= 1e-5 and e_p <= 1e-5
+
+
+@pytest.mark.parametrize("n,cpml", [((70, 45, 38), (5, 7, 3, 6, 8, 4)),     # ragged x, y tiles; two z chunks
+                                    ((33, 29, 97), (0, 9, 6, 0, 0, 7)),     # one partial x tile; 4 z chunks
+                                    ((130, 17, 31), (12, 12, 0, 0, 6, 6))])  # three x tiles, one y tile
+def test_pv_variants_bitwise(n, cpml):
+    """The z-marching stages sum every tap in the order of the one-thread-per-
+    point stages, so both give the same bits (traces, snapshots, final p)."""
+    rng = np.random.default_rng(11)
+    rec = np.stack([rng.integers(0, n[0], 10), rng.integers(0, n[1], 10), rng.integers(0, n[2], 10)], 1)
+    wav = synth.ricker(100, 0.3, 0.08)
+    src = (n[0] // 3, n[1] // 2, n[2] // 2)
+    a = _gpu(n, cpml, 0.3, 100, src, wav, rec.astype(np.int32), snap_every=25, variant=1)
+    b = _gpu(n, cpml, 0.3, 100, src, wav, rec.astype(np.int32), snap_every=25, variant=2)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
 
 
 def test_pv_initial_pressure_matches_oracle():
