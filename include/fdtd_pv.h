@@ -41,7 +41,7 @@ typedef struct fdtd_pv_ctx fdtd_pv_ctx;
 
 /* One grid.  Zero-valued optional fields take the default shown. */
 typedef struct {
-    int32_t n[3];            /* nx, ny, nz (points, >= 9 each)                          */
+    int32_t n[3];            /* nx, ny, nz (points, 9 .. 32768 each)                    */
     int32_t cpml[6];         /* layer width per face -x,+x,-y,+y,-z,+z (0 = none); the
                                 two layers of an axis together narrower than the axis  */
     double lambda;           /* wave-update scaling c dt / h, in (0, 0.7]               */

@@ -462,7 +462,8 @@ int fdtd_pv_create(const fdtd_pv_config *cfg, void *hip_stream, fdtd_pv_ctx **ou
     *out = nullptr;
     for (int d = 0; d < 3; ++d) {
         const int n = cfg->n[d], lo = cfg->cpml[2 * d], hi = cfg->cpml[2 * d + 1];
-        if (n < 9 || n > (1 << 16) || lo < 0 || hi < 0 || lo + hi >= n) return FDTD_EINVAL;
+        // (the per-point stages launch one workgroup row per plane: nz stays below the grid limit)
+        if (n < 9 || n > (1 << 15) || lo < 0 || hi < 0 || lo + hi >= n) return FDTD_EINVAL;
     }
     if (!(cfg->lambda > 0.0 && cfg->lambda <= 0.7)) return FDTD_EINVAL;
     if (cfg->R < 0 || cfg->R >= 1 || cfg->kappa_max < 0 || cfg->alpha_frac < 0) return FDTD_EINVAL;
