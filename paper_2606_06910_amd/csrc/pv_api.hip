@@ -31,8 +31,8 @@ namespace {
 constexpr int kR = 4;        // stencil radius
 constexpr int kLead = 128;   // leading pad of every field (elements)
 constexpr int kNF = 10;      // p, v_x, v_y, v_z, psi_v x3, psi_p x3
-constexpr int kRY = 4;       // z-march: rows per thread
-constexpr int kNW = 4;       // z-march: waves per workgroup
+constexpr int kRY = 2;       // z-march: rows per thread
+constexpr int kNW = 8;       // z-march: waves per workgroup
 constexpr int kTY = kRY * kNW;          // tile rows (tile: 64 x kTY)
 constexpr int kLW = 64 + 2 * kR;        // LDS row length with the x halo
 constexpr int kLH = kTY + 2 * kR;       // LDS rows with the y halo
@@ -575,10 +575,10 @@ int fdtd_pv_step(fdtd_pv_ctx *ctx, int32_t nsteps) {
     const dim3 grid((ctx->n[0] + 63) / 64, (ctx->n[1] + 3) / 4, ctx->n[2]), block(64, 4);
     const dim3 zgrid((ctx->n[0] + 63) / 64, (ctx->n[1] + kTY - 1) / kTY, (ctx->n[2] + kZC - 1) / kZC),
         zblock(64, kNW);
-    // automatic choice: the z-march from 2^27 points up (measured crossover between
-    // 480^3 and 544^3: below it its workgroups fill the chip in too few rounds)
+    // automatic choice: the z-march from 3 * 2^23 points up (measured crossover between
+    // 256^3 and 320^3: below it its workgroups fill the chip in too few rounds)
     const double npts = (double)ctx->n[0] * ctx->n[1] * ctx->n[2];
-    const bool naive = ctx->c.variant == 1 || (ctx->c.variant == 0 && npts < (double)(1L << 27));
+    const bool naive = ctx->c.variant == 1 || (ctx->c.variant == 0 && npts < 3.0 * (double)(1L << 23));
     for (int s = 0; s < nsteps; ++s) {
         PvArgs g = pv_args(ctx);
         if (naive) {
