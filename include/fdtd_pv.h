@@ -49,7 +49,7 @@ typedef struct {
     double kappa_max;        /* default 5                                               */
     double alpha_frac;       /* alpha_max / sigma_max, default 0.05                     */
     int32_t variant;         /* 1: one thread per point; 2: z-marching stages (LDS xy
-                                planes, register queue along z); 0: 2 from 3 * 2^23
+                                planes, register queue along z); 0: 2 from 2^24
                                 points up, else 1.  Both give the same bits.            */
 } fdtd_pv_config;
 

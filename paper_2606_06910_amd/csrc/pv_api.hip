@@ -31,7 +31,7 @@ namespace {
 constexpr int kR = 4;        // stencil radius
 constexpr int kLead = 128;   // leading pad of every field (elements)
 constexpr int kNF = 10;      // p, v_x, v_y, v_z, psi_v x3, psi_p x3
-constexpr int kRY = 2;       // z-march: rows per thread
+constexpr int kRY = 1;       // z-march: rows per thread
 constexpr int kNW = 8;       // z-march: waves per workgroup
 constexpr int kTY = kRY * kNW;          // tile rows (tile: 64 x kTY)
 constexpr int kLW = 64 + 2 * kR;        // LDS row length with the x halo
@@ -109,7 +109,8 @@ __global__ __launch_bounds__(256) void k_pv_pres(PvArgs g) {
 // ---------------------------------------------------------------------------
 // z-marching stages.  A workgroup of kNW waves owns a 64 x kTY xy tile and a
 // chunk of kZC planes; lane l of wave w owns column x0 + l and rows
-// w kRY .. w kRY + kRY - 1.  The z taps come from a register queue of the
+// w kRY .. w kRY + kRY - 1 (one row at kRY = 1: more resident waves beat
+// more rows per thread).  The z taps come from a register queue of the
 // field's planes z - 4 .. z + 4 (own rows), the x and y taps from the plane z
 // staged in LDS with its halo (two buffers: one barrier per plane).  Every
 // tap is summed in the order of pv_delta, so the results equal the
@@ -575,10 +576,10 @@ int fdtd_pv_step(fdtd_pv_ctx *ctx, int32_t nsteps) {
     const dim3 grid((ctx->n[0] + 63) / 64, (ctx->n[1] + 3) / 4, ctx->n[2]), block(64, 4);
     const dim3 zgrid((ctx->n[0] + 63) / 64, (ctx->n[1] + kTY - 1) / kTY, (ctx->n[2] + kZC - 1) / kZC),
         zblock(64, kNW);
-    // automatic choice: the z-march from 3 * 2^23 points up (measured crossover between
-    // 256^3 and 320^3: below it its workgroups fill the chip in too few rounds)
+    // automatic choice: the z-march from 2^24 points up (measured crossover between
+    // 224^3 and 256^3: below it its workgroups fill the chip in too few rounds)
     const double npts = (double)ctx->n[0] * ctx->n[1] * ctx->n[2];
-    const bool naive = ctx->c.variant == 1 || (ctx->c.variant == 0 && npts < 3.0 * (double)(1L << 23));
+    const bool naive = ctx->c.variant == 1 || (ctx->c.variant == 0 && npts < (double)(1L << 24));
     for (int s = 0; s < nsteps; ++s) {
         PvArgs g = pv_args(ctx);
         if (naive) {
