@@ -36,7 +36,7 @@ constexpr int kNW = 8;       // z-march: waves per workgroup
 constexpr int kTY = kRY * kNW;          // tile rows (tile: 64 x kTY)
 constexpr int kLW = 64 + 2 * kR;        // LDS row length with the x halo
 constexpr int kLH = kTY + 2 * kR;       // LDS rows with the y halo
-constexpr int kZC = 24;                 // z-march: planes per chunk (measured: 8 .. 32)
+constexpr int kZC = 16;                 // z-march: planes per chunk (measured: 8 .. 64)
 
 // central first-derivative weights of order 8 at unit spacing (a_1 .. a_4)
 constexpr double kA1[kR + 1] = {0.0, 4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
