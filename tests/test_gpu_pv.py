@@ -75,6 +75,19 @@ def test_pv_matches_oracle(name, variant):
     assert e_tr <= 1e-5 and e_st <= 1e-5 and e_p <= 1e-5
 
 
+def test_pv_corner_source_and_receivers():
+    """Source one node from a corner, inside the layers of all three axes;
+    receivers on the grid's corners and faces; both variants."""
+    n = (33, 29, 27)
+    rec = np.array([[0, 0, 0], [32, 28, 26], [0, 28, 0], [32, 0, 26], [16, 0, 13], [16, 14, 0], [32, 14, 13],
+                    [1, 1, 1], [5, 5, 5]], np.int32)
+    wav = synth.ricker(90, 0.3, 0.1)
+    ref = P.forward(n, (4,) * 6, 0.3, 90, (1, 1, 1), wav, rec, snap_every=30)
+    for variant in (1, 2):
+        tr, snaps, p = _gpu(n, (4,) * 6, 0.3, 90, (1, 1, 1), wav, rec, snap_every=30, variant=variant)
+        assert rel_l2(tr, ref["traces"]) <= 1e-5 and rel_l2(snaps, ref["snaps"]) <= 1e-5, variant
+
+
 @pytest.mark.parametrize("n,cpml", [((70, 45, 38), (5, 7, 3, 6, 8, 4)),     # ragged x, y tiles; two z chunks
                                     ((33, 29, 97), (0, 9, 6, 0, 0, 7)),     # one partial x tile; 4 z chunks
                                     ((130, 17, 31), (12, 12, 0, 0, 6, 6))])  # three x tiles, one y tile
