@@ -30,9 +30,14 @@ Readings where the paper is silent (each listed in the design notes):
     receivers record p^{n+1}.
 
 Array convention: numpy arrays of shape (nz, ny, nx), x fastest.
-Parity status: pinned by tests/test_pv_oracle_pins.py (exact Fourier-mode
-recurrence, exact discrete energy without layers, mirror symmetry, energy
-loss and its fall with layer width).
+Parity status: pinned by tests/test_pv_oracle_pins.py: one step with layers
+of a different width on every face equals an independently assembled sparse
+step matrix (Kronecker products of the 1-D derivative matrix with diagonal
+b, a, 1/kappa) plus the source vector; kappa_max = 1 on a line equals a 1-D
+scalar loop with its own profile; exact Fourier-mode recurrence; exact
+discrete energy without layers; the stability limit; mirror symmetry; energy
+loss and its fall with layer width.  The psi index and the source placement
+are readings (the paper fixes neither); the matrix pins the oracle to them.
 """
 from __future__ import annotations
 
