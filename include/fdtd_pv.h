@@ -44,7 +44,8 @@ typedef struct {
     int32_t n[3];            /* nx, ny, nz (points, 9 .. 32768 each)                    */
     int32_t cpml[6];         /* layer width per face -x,+x,-y,+y,-z,+z (0 = none); the
                                 two layers of an axis together narrower than the axis  */
-    double lambda;           /* wave-update scaling c dt / h, in (0, 0.7]               */
+    double lambda;           /* wave-update scaling c dt / h, in (0, 0.66722]: at most
+                                2 / (sqrt(3) max_theta 2 sum_l a_l sin(l theta))        */
     double R;                /* target reflection, default 1e-8                         */
     double kappa_max;        /* default 5                                               */
     double alpha_frac;       /* alpha_max / sigma_max, default 0.05                     */
@@ -54,7 +55,10 @@ typedef struct {
 } fdtd_pv_config;
 
 /* Create a context on hip_stream (a hipStream_t, may be NULL).  EINVAL for a
- * bad shape, layer or lambda.  *out receives host memory owned by the
+ * bad shape, layer or a lambda <= 0; EUNSTABLE for a lambda above the
+ * leapfrog's stability limit 2 / (sqrt(3) max s) = 0.667226..., with s the
+ * symbol of the first derivative, s(theta) = 2 sum_l a_l sin(l theta)
+ * (computed from the weights on the host).  *out receives host memory owned by the
  * library (free with fdtd_pv_destroy). */
 int fdtd_pv_create(const fdtd_pv_config *cfg, void *hip_stream, fdtd_pv_ctx **out);
 

@@ -394,6 +394,34 @@ void pv_profile(int n, int lo, int hi, double lam, double R, double kmax, double
     }
 }
 
+// Largest lambda for which the 3-D leapfrog of the two stages keeps every
+// Fourier mode bounded.  A mode exp(i k.x) sees delta_d as i s(k_d) with
+// s(theta) = 2 sum_l a_l sin(l theta); eliminating v gives
+// p^{n+1} - 2 p^n + p^{n-1} = -lambda^2 S^2 p^n, S^2 = sum_d s(k_d)^2, which is
+// bounded iff lambda^2 S^2 <= 4.  S^2 reaches 3 max(s)^2, so the limit is
+// 2 / (sqrt(3) max s).  The maximum of s is found by a dense scan of
+// [0, pi] refined by golden-section search around the best sample.
+double pv_lambda_limit() {
+    auto sym = [](double t) {
+        double acc = 0.0;
+        for (int l = 1; l <= kR; ++l) acc += 2.0 * kA1[l] * std::sin(l * t);
+        return acc;
+    };
+    const int M = 4096;
+    const double pi = 3.14159265358979323846;
+    int best = 0;
+    for (int i = 1; i <= M; ++i)
+        if (sym(pi * i / M) > sym(pi * best / M)) best = i;
+    double lo = pi * std::max(best - 1, 0) / M, hi = pi * std::min(best + 1, M) / M;
+    const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+    for (int it = 0; it < 100; ++it) {
+        const double c = hi - gr * (hi - lo), d = lo + gr * (hi - lo);
+        if (sym(c) > sym(d)) hi = d;
+        else lo = c;
+    }
+    return 2.0 / (std::sqrt(3.0) * sym(0.5 * (lo + hi)));
+}
+
 }  // namespace
 
 struct fdtd_pv_ctx {
@@ -466,7 +494,12 @@ int fdtd_pv_create(const fdtd_pv_config *cfg, void *hip_stream, fdtd_pv_ctx **ou
         // (the per-point stages launch one workgroup row per plane: nz stays below the grid limit)
         if (n < 9 || n > (1 << 15) || lo < 0 || hi < 0 || lo + hi >= n) return FDTD_EINVAL;
     }
-    if (!(cfg->lambda > 0.0 && cfg->lambda <= 0.7)) return FDTD_EINVAL;
+    if (!(cfg->lambda > 0.0)) return FDTD_EINVAL;
+    if (cfg->lambda > pv_lambda_limit()) {
+        fprintf(stderr, "fdtd_pv_create: lambda = %g above the stability limit %.6f\n", cfg->lambda,
+                pv_lambda_limit());
+        return FDTD_EUNSTABLE;
+    }
     if (cfg->R < 0 || cfg->R >= 1 || cfg->kappa_max < 0 || cfg->alpha_frac < 0) return FDTD_EINVAL;
     if (cfg->variant < 0 || cfg->variant > 2) return FDTD_EINVAL;
     fdtd_pv_ctx *ctx = new fdtd_pv_ctx;
