@@ -23,6 +23,40 @@ def run_oracle(w, nt=None, snap_every=0):
     return out
 
 
+def band_masks(n, cpml):
+    """Masks (nz, ny, nx) of the band points of each face with a layer (the
+    layer plus the 4-cell margin whose stencils read layer memory), keyed
+    '-x', '+x', ..., and their union."""
+    nx, ny, nz = [int(x) for x in n]
+    shape = (nz, ny, nx)
+    masks = {}
+    for d in range(3):
+        c = np.arange(int(n[d]))
+        for side in (0, 1):
+            L = int(cpml[2 * d + side])
+            if L <= 0:
+                continue
+            sel = c < L + 4 if side == 0 else c >= int(n[d]) - L - 4
+            bshape = [1, 1, 1]
+            bshape[2 - d] = int(n[d])
+            masks["-+"[side] + "xyz"[d]] = np.broadcast_to(sel.reshape(bshape), shape)
+    union = np.zeros(shape, bool)
+    for m in masks.values():
+        union |= m
+    return masks, union
+
+
+def per_receiver_rel_l2(got, ref, floor=1e-2):
+    """Relative L2 error of each receiver's trace, over the receivers whose
+    reference trace norm is at least ``floor`` times the largest one (a trace
+    the wave has barely reached is all rounding)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    nr = np.linalg.norm(ref, axis=0)
+    keep = nr >= floor * nr.max()
+    return np.linalg.norm(got - ref, axis=0)[keep] / nr[keep]
+
+
 def rel_l2(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from helpers import rel_l2, run_gpu, run_oracle
+from helpers import band_masks, per_receiver_rel_l2, rel_l2, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -31,9 +31,15 @@ def test_plain64_matches_oracle(plain64_ref, variant):
     tr, snaps, fin = run_gpu(w, snap_every=10, variant=variant)
     e_tr = rel_l2(tr, ref["traces"])
     e_st = rel_l2(snaps, ref["snaps"])
-    print("plain64 variant %d: traces %.3e  space-time %.3e" % (variant, e_tr, e_st), flush=True)
+    _, union = band_masks(w.n, w.cpml)
+    e_band = rel_l2(snaps[:, union], ref["snaps"][:, union])
+    per = per_receiver_rel_l2(tr, ref["traces"])
+    print("plain64 variant %d: traces %.3e  space-time %.3e  band %.3e  per-receiver max %.3e over %d" %
+          (variant, e_tr, e_st, e_band, per.max(), per.size), flush=True)
     assert e_tr <= TOL
     assert e_st <= TOL
+    assert e_band <= TOL
+    assert per.max() <= TOL
 
 
 def test_plain64_variants_bitwise(plain64_ref):
@@ -93,6 +99,18 @@ def test_cases_match_oracle_and_variants_agree(name):
     n = run_gpu(w, snap_every=10, variant=NAIVE)
     assert rel_l2(z[0], ref["traces"]) <= TOL
     assert rel_l2(z[1], ref["snaps"]) <= TOL
+    # beside the global norms: each receiver that the wave has reached, and the
+    # snapshot samples on the band points alone (the layers hold a small share
+    # of the norm, so an error there could hide in the global figure)
+    per = per_receiver_rel_l2(z[0], ref["traces"])
+    msg = "case %s: per-receiver max %.2e over %d" % (name, per.max(), per.size)
+    _, union = band_masks(w.n, w.cpml)
+    if union.any():
+        e_band = rel_l2(z[1][:, union], ref["snaps"][:, union])
+        msg += "  band snapshots %.2e" % e_band
+        assert e_band <= TOL, (name, e_band)
+    print(msg, flush=True)
+    assert per.max() <= TOL, (name, per.max())
     assert np.array_equal(z[0], n[0]) and np.array_equal(z[1], n[1]) and np.array_equal(z[2], n[2])
 
 
