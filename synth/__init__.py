@@ -264,3 +264,64 @@ def batch_shot(i: int, shape_xyz, nt: int = 600, L: int = 15, nrec: int = 64, se
     w = Workload("shot%d" % i, tuple(shape_xyz), (h, h, h), dt, nt, (L,) * 6, vt, src,
                  ricker(nt, dt, f0), rec, f0=f0)
     return w, v0
+
+
+# ---------------------------------------------------------------------------
+# layer reflection study: normal incidence on the low face of one axis
+# ---------------------------------------------------------------------------
+REFL_WIDTHS = (0, 8, 12, 16, 24)     # layer widths of the study (the paper's reflection table)
+# Uniform 2000 m/s, h = 10 m, Ricker 12.5 Hz (16 points per wavelength at the
+# peak frequency), Courant number 0.5.  The run lasts until the widest layer's
+# return from its Dirichlet wall (path 24 + 2 L + 4 cells) and the pulse's
+# half-width (15 cells) have passed the receiver: 91 cells of travel after the
+# source peak.  Every other path back to the receiver (off a transverse face,
+# the opposite face, or a transverse face and then the layer) is longer than
+# 106 cells, so that nothing else it returns arrives within the run.
+REFL_NT = 400
+REFL_F0 = 12.5
+REFL_GAP_REC = 4      # receiver: first point past the layer band (layer + 4-cell margin)
+REFL_GAP_SRC = 24     # source: 24 cells from the layer's inner edge, on the same normal line
+REFL_BEHIND = 46      # cells from the source to the opposite (Dirichlet) face
+REFL_HALF = 56        # transverse half-width (Dirichlet transverse faces)
+REFL_EXTEND = 48      # reference run: the low face moved this many cells further out, no layer
+
+
+def reflection_case(axis: int, L: int, reference: bool = False, v0: float = 2000.0, f0: float = REFL_F0,
+                    h: float = 10.0) -> Workload:
+    """Normal-incidence reflection off the low face of `axis` with a layer of L
+    cells there (no layer anywhere else).  Uniform v0; source and receivers on
+    the face normal through the transverse centre; every other face is far
+    enough that nothing it returns reaches the receivers within REFL_NT steps.
+    reference=True: the same geometry relative to the source, with the low
+    face REFL_EXTEND cells further out and no layer, so that within the run
+    its traces hold the incident wave only (the layer width then only names
+    which run it serves)."""
+    lo = REFL_EXTEND if reference else L
+    nn = lo + REFL_GAP_SRC + REFL_BEHIND
+    t = 2 * REFL_HALF + 1
+    n = [t, t, t]
+    n[axis] = nn
+    cpml = [0] * 6
+    if not reference:
+        cpml[2 * axis] = L
+    dt = dt_from_courant(v0, (h, h, h))
+    src = [REFL_HALF] * 3
+    src[axis] = lo + REFL_GAP_SRC
+    recs = []
+    for gap in (REFL_GAP_REC, REFL_GAP_REC + 8):
+        r = [REFL_HALF] * 3
+        r[axis] = lo + gap
+        recs.append(r)
+    nx, ny, nz = n
+    v = np.full((nz, ny, nx), v0)
+    name = "refl_%s_%s" % ("xyz"[axis], "ref" if reference else "L%d" % L)
+    return Workload(name, tuple(n), (h, h, h), dt, REFL_NT, tuple(cpml), v, np.array([src], np.int32),
+                    ricker(REFL_NT, dt, f0), np.array(recs, np.int32), f0=f0)
+
+
+def reflection_ratio(trace: np.ndarray, ref_trace: np.ndarray) -> float:
+    """Reflected-to-incident amplitude ratio at one receiver: the peak of the
+    difference from the reference run (which holds the incident wave only)
+    over the peak of the reference trace."""
+    d = np.asarray(trace, np.float64) - np.asarray(ref_trace, np.float64)
+    return float(np.abs(d).max() / np.abs(np.asarray(ref_trace, np.float64)).max())
