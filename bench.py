@@ -74,16 +74,51 @@ def step_bytes(n, cpml, field_bytes=4):
     return (3 * field_bytes + 4) * N + 16 * slab_points(n, cpml)
 
 
+def exchange_bytes(n, cpml, s, field_bytes=4):
+    """Algorithmic bytes of one ghost exchange of the pencil share (ghost
+    faces on y and z, depth g = 4 s): u^n to depth g, and for s > 1 u^{n-1}
+    (16-bit: d^n) and the x layer memory (psi_x, zeta_x, FP32) to depth g - 4;
+    y faces over the owned z range, z faces spanning the y ghosts; each byte
+    is read and written once when packed and once when unpacked."""
+    nx, ny, nz = n
+    g = 4 * s
+    fields = [(field_bytes, nx, g)]
+    if g > 4:
+        fields.append((field_bytes, nx, g - 4))
+        for _ in range(2):
+            for L in (cpml[0], cpml[1]):
+                if L > 0:
+                    fields.append((4, L, g - 4))
+    payload = 0
+    for e, ex, dep in fields:
+        payload += 2 * dep * nz * ex * e + 2 * dep * (ny + 2 * dep) * ex * e
+    return 4 * payload
+
+
+def roofline(nbytes, ms, kernel, traffic=None):
+    """Roofline record of one kernel from its algorithmic bytes per launch and mean duration."""
+    gbs = nbytes / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": kernel, "kernel_ms": round(ms, 5),
+            "algorithmic_bytes_per_launch": int(nbytes)}
+
+
 KERNEL_CLASSES = ("update", "psi", "record", "exchange", "band", "tblock")
 
 
-def make_propagator(w, K, W, variant, storage=0, tblock_k=1):
+PLAN = None   # (variant, tile_ry, zchunk, tblock_k, tile_cols) forced on the headline runs (--plan)
+
+
+def make_propagator(w, K, W, variant, storage=0, tblock_k=1, **shot_kw):
     import numpy as np
     import torch
 
     from paper_2606_06910_amd import Propagator, Shot
 
-    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, variant=variant, storage=storage, tblock_k=tblock_k)])
+    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, variant=variant, storage=storage, tblock_k=tblock_k,
+                         **shot_kw)])
+    if PLAN is not None and variant in (0, 2):
+        p.set_plan(0, *PLAN)
     p.set_velocity(0, torch.from_numpy(w.v.astype(np.float32)).cuda())
     p.inject_source(0, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)).cuda())
     p.set_receivers(0, w.rec)
@@ -91,13 +126,13 @@ def make_propagator(w, K, W, variant, storage=0, tblock_k=1):
     return p
 
 
-def kernel_timing(w, K, W, variant=0):
+def kernel_timing(w, K, W, variant=0, storage=0, **shot_kw):
     """Per-kernel mean durations (ms, count) from an eager pass of K steps with
     HIP events around every launch on the stream it runs on; the library runs
     the kernels of a step one after another while timing is on."""
     import torch
 
-    p = make_propagator(w, K, W, variant)
+    p = make_propagator(w, K, W, variant, storage, **shot_kw)
     p.set_timing(True)     # warm-up launches run like the timed ones
     p.step(W)
     torch.cuda.synchronize()
@@ -148,21 +183,23 @@ def sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic(n, plan):
-    """HBM bytes per z-march launch from the committed counter summary
+def measured_traffic(n, plan, path=None):
+    """HBM bytes per z-march launch from a committed counter summary
     (FETCH_SIZE and WRITE_SIZE KiB per dispatch times their copy-kernel
     calibration factors), or None when that summary is missing or was taken on
     other kernel sources, another grid or another plan."""
+    path = COUNTERS if path is None else path
     try:
         kv = {}
-        with open(COUNTERS) as fh:
+        with open(path) as fh:
             for line in fh:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
         if kv.get("sources_sha256") != sources_digest():
             return None
-        if kv.get("grid") != "%dx%dx%d" % tuple(n) or kv.get("tile_ry") != str(plan[1]):
+        if kv.get("grid") != "%dx%dx%d" % tuple(n) or kv.get("tile_ry") != str(plan[1]) or \
+                kv.get("tile_cols", "1") != str(plan[3] if len(plan) > 3 else 1):
             return None
         fetch = float(kv["fetch_kib_per_launch"]) * 1024 * float(kv["fetch_factor"])
         write = float(kv["write_kib_per_launch"]) * 1024 * float(kv["write_factor"])
@@ -201,6 +238,26 @@ def precision_leg(K=200):
         e1.record(p.stream)
         torch.cuda.synchronize()
         out[name] = {"mpts": round(n ** 3 * K / (e0.elapsed_time(e1) / 1e3) / 1e6, 1)}
+        # per-kernel durations (eager, kernels one after another) and the
+        # z-march's roofline: 16 B (FP32) or 12 B (16-bit: u^n, d^n in and out,
+        # m in) per point outside the bands
+        p.reset()
+        p.set_timing(True)
+        p.step(8)
+        p.set_timing(True)
+        p.step(40)
+        tm = {kn: p.timing(c) for c, kn in enumerate(KERNEL_CLASSES)}
+        p.set_timing(False)
+        fb = 4 if st == 0 else 2
+        per_pt = 16 if st == 0 else 12
+        nb = per_pt * band_split((n, n, n), (20,) * 6)[0]
+        out[name]["kernel_ms"] = {k: round(v[0], 5) for k, v in tm.items() if v[1] > 0}
+        traffic = None
+        if st == 1:
+            traffic = measured_traffic((n, n, n), p.plan(0), os.path.join(ROOT, "profiles",
+                                                                          "zmarch_f16_blob768_counters.txt"))
+        out[name]["roofline"] = roofline(nb, tm["update"][0], "k_zmarch<%s> (points outside the layer bands)" %
+                                         {0: "float", 1: "_Float16", 2: "__bf16"}[st], traffic)
         p.close()
     del v
     torch.cuda.empty_cache()
@@ -294,10 +351,16 @@ def pencil_leg(K=100):
         p.set_timing(True)
         p.step(4 * 4)
         ex = p.timing(3)
+        upd = p.timing(0)
         p.set_timing(False)
         exch_ms_per_step = ex[0] * ex[1] / 16.0
         out["s%d" % s_] = {"mpts": round(w.npts * K / (ms / 1e3) / 1e6, 1),
-                           "exchange_ms_per_step": round(exch_ms_per_step, 5)}
+                           "exchange_ms_per_step": round(exch_ms_per_step, 5),
+                           "exchange_roofline": roofline(exchange_bytes(w.n, w.cpml, s_), ex[0],
+                                                         "k_copy_jobs (pack + unpack of one exchange, 4 launches)")}
+        if s_ == 1:
+            out["s1"]["roofline"] = roofline(interior_kernel_bytes(w.n, w.cpml), upd[0],
+                                             "k_zmarch<float> (points outside the layer bands)")
         p.close()
     for s_ in (2, 4):
         out["s%d" % s_]["S"] = round(out["s%d" % s_]["mpts"] / out["s1"]["mpts"], 3)
@@ -402,9 +465,81 @@ def batched_leg(K=600, nshots=24):
             "sequential_mpts": round(npts * K / (ms_s / 1e3) / 1e6, 1)}
 
 
+def batched_fwd_adj_leg(K=600, every=25, nshots=24):
+    """The batched forward + adjoint workload end to end: 24 shots (each axis
+    uniform in [96, 288]), 15-cell layers, layered true models, 64 receivers on
+    a seeded interior plane.  Observed data from the true models; the
+    inversion models v0 = v_true (1 + 0.03 G) advance together in one batched
+    context with the full state saved every 25 steps, the L2 misfit is formed,
+    and every shot's FP64 velocity gradient comes from the adjoint (segments
+    recomputed from the checkpoints).  Mpts/s of the forward (with
+    checkpoints) and of the 24 gradients, over points x steps."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2606_06910_amd import Propagator, Shot
+
+    shapes = synth.batch_shapes(nshots)
+    data = [synth.batch_shot(i, sh, nt=K) for i, sh in enumerate(shapes)]
+    shots = [Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml,
+                  v_ref=float(max(w.v.astype(np.float32).max(), v0.astype(np.float32).max())))
+             for w, v0 in data]
+    npts = sum(w.npts for w, _ in data)
+
+    def setup(p, models):
+        trs = []
+        for k, ((w, _), v) in enumerate(zip(data, models)):
+            p.set_velocity(k, torch.from_numpy(v.astype(np.float32)).cuda())
+            p.inject_source(k, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)).cuda())
+            p.set_receivers(k, w.rec)
+            trs.append(p.record(k, K))
+        return trs
+
+    # observed data from the true models
+    po = Propagator(shots)
+    obs = setup(po, [w.v for w, _ in data])
+    po.step(K, graph=True)
+    torch.cuda.synchronize()
+    obs = [t.clone() for t in obs]
+    po.close()
+    del po
+    torch.cuda.empty_cache()
+    # inversion models: batched forward with checkpoints, misfit, gradients
+    p = Propagator(shots)
+    trs = setup(p, [v0 for _, v0 in data])
+    for k in range(nshots):
+        p.set_checkpointing(k, every, K)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record(p.stream)
+    p.step(K)
+    e[1].record(p.stream)
+    torch.cuda.synchronize()
+    misfit = 0.5 * sum(float(((t.double() - o.double()) ** 2).sum()) for t, o in zip(trs, obs))
+    grads = []
+    e[1].record(p.stream)
+    for k in range(nshots):
+        grads.append(p.adjoint(k, K, trs[k] - obs[k]))
+    e[2].record(p.stream)
+    torch.cuda.synchronize()
+    fwd_ms, adj_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+    gnorm = float(torch.sqrt(sum((g * g).sum() for g in grads)))
+    finite = all(bool(torch.isfinite(g).all()) for g in grads)
+    p.close()
+    return {"shots": nshots, "points": npts, "steps": K, "checkpoint_every": every, "receivers_per_shot": 64,
+            "forward_with_checkpoints_mpts": round(npts * K / (fwd_ms / 1e3) / 1e6, 1),
+            "gradient_mpts": round(npts * K / (adj_ms / 1e3) / 1e6, 1),
+            "forward_s": round(fwd_ms / 1e3, 3), "gradient_s": round(adj_ms / 1e3, 3),
+            "misfit": float("%.6e" % misfit), "gradient_l2": float("%.6e" % gnorm), "gradient_finite": finite}
+
+
 def zmarch_instance(plan):
-    """Template instance of the z-march kernel a plan (variant, tile_ry, tblock_k) launches:
-    tile_ry 1, 2, 4, 8 -> (waves, rows per thread) (4, 2), (4, 4), (8, 4), (16, 4)."""
+    """Template instance of the z-march kernel a plan (variant, tile_ry, tblock_k, tile_cols)
+    launches: one column per lane, tile_ry 1, 2, 4, 8 -> k_zmarch (waves, rows per thread)
+    (4, 2), (4, 4), (8, 4), (16, 4); two columns, tile_ry 1, 2, 4 -> k_zmarch2 (4, 2), (8, 2), (16, 2)."""
+    if len(plan) > 3 and plan[3] == 2:
+        nw, ry = {1: (4, 2), 2: (8, 2), 4: (16, 2)}.get(plan[1], (0, 0))
+        return "k_zmarch2<float, %d, %d>" % (nw, ry)
     nw, ry = {1: (4, 2), 2: (4, 4), 4: (8, 4), 8: (16, 4)}.get(plan[1], (0, 0))
     return "k_zmarch<float, %d, %d>" % (nw, ry)
 
@@ -475,7 +610,147 @@ def pv_leg(sizes=(320, 480, 544, 640, 800), K=64, W=4):
     return out
 
 
+PAPER_REFLECTION = {0: 9.438e-1, 8: 8.049e-2, 12: 6.714e-3, 16: 5.581e-4, 24: 3.328e-5}   # first-order system, 4 GPUs
+
+
+def reflection_leg():
+    """Reflected-to-incident amplitude ratio of the absorbing layer against its
+    width (0, 8, 12, 16, 24 cells) at normal incidence on the low face of each
+    axis (synth.reflection_case: uniform 2000 m/s, Ricker 12.5 Hz, every other
+    face out of reach), from the GPU path: the 18 runs (5 widths and a
+    reference per axis) in one batched context.  The paper's ratios for its
+    own first-order system and unstated setup ride along as context."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2606_06910_amd import Propagator, Shot
+
+    ws = []
+    for axis in range(3):
+        ws += [synth.reflection_case(axis, L) for L in synth.REFL_WIDTHS]
+        ws.append(synth.reflection_case(axis, 0, reference=True))
+    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml) for w in ws])
+    trs = []
+    for k, w in enumerate(ws):
+        p.set_velocity(k, torch.from_numpy(w.v.astype(np.float32)).cuda())
+        p.inject_source(k, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)).cuda())
+        p.set_receivers(k, w.rec)
+        trs.append(p.record(k, w.nt))
+    p.step(synth.REFL_NT, graph=True)
+    torch.cuda.synchronize()
+    got = {w.name: trs[k][:, 0].cpu().double().numpy() for k, w in enumerate(ws)}
+    p.close()
+    out = {}
+    for a in "xyz":
+        ref = got["refl_%s_ref" % a]
+        out[a] = {"L%d" % L: float("%.4e" % synth.reflection_ratio(got["refl_%s_L%d" % (a, L)], ref))
+                  for L in synth.REFL_WIDTHS}
+    out["paper_first_order"] = {"L%d" % L: v for L, v in PAPER_REFLECTION.items()}
+    out["workload"] = ("normal incidence on the low face of each axis, uniform 2000 m/s, h 10 m, Ricker 12.5 Hz, "
+                       "receiver 4 cells past the layer band, source 24 cells from the layer, %d steps" % synth.REFL_NT)
+    return out
+
+
+def stream_ceiling_leg(mib=400):
+    """This library's own streaming kernel (fdtd_stream_probe: o = a + b * c,
+    16-byte lanes, three FP32 streams read and one written, the interior
+    update's access mix) over arrays far larger than the caches: TB/s of the
+    best of several grid sizes and in-flight depths (HIP events, 20 launches)."""
+    import ctypes
+
+    import torch
+
+    from paper_2606_06910_amd import lib
+
+    L = lib()
+    n = mib * (1 << 20) // 4
+    a, b, c = (torch.rand(n, device="cuda") for _ in range(3))
+    o = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    ptr = [ctypes.c_void_p(t.data_ptr()) for t in (a, b, c, o)]
+    best = None
+    for blocks in (1024, 2048, 4096, 8192):
+        for unroll in (1, 2, 4):
+            for _ in range(3):
+                assert L.fdtd_stream_probe(*ptr, n, blocks, unroll, ctypes.c_void_p(st.cuda_stream)) == 0
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 20
+            e0.record(st)
+            for _ in range(reps):
+                L.fdtd_stream_probe(*ptr, n, blocks, unroll, ctypes.c_void_p(st.cuda_stream))
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            tbs = 16 * n / (ms / 1e3) / 1e12
+            if best is None or tbs > best["TB_per_s"]:
+                best = {"TB_per_s": round(tbs, 3), "ms": round(ms, 4), "blocks": blocks, "unroll": unroll}
+    assert torch.allclose(o, a + b * c)
+    return {"kernel": "k_stream_probe (o = a + b * c, float4 lanes)", "bytes_per_launch": 16 * n, "best": best}
+
+
+def oracle_timings_leg(full=False):
+    """The FP64 oracle timed on this machine's host cores for each workload:
+    the 64^3 run in full (200 steps), 10 steps at the pencil share's shape,
+    the 160^3 blob crop and the smallest batched shot's forward + adjoint
+    (full runs with full=True; otherwise 100 steps of each)."""
+    import numpy as np
+
+    import synth
+    from oracle import oracle as O
+
+    def grid(w, periodic=(0, 0, 0)):
+        v = w.v.astype(np.float32).astype(np.float64)
+        return O.Grid(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, periodic=periodic, vref=float(v.max())), v
+
+    out = {"cores": O.threads()}
+    w = synth.plain64()
+    g, v = grid(w)
+    t0 = time.perf_counter()
+    O.forward(g, v, w.nt, w.src, w.wavelet, w.rec)
+    dt = time.perf_counter() - t0
+    out["plain64_full"] = {"steps": w.nt, "s": round(dt, 2), "mpts": round(w.npts * w.nt / dt / 1e6, 2)}
+    w = synth.pencil(nt=11)
+    g, v = grid(w, periodic=(0, 1, 1))
+    S = O.Stepper(g, v)
+    st = O.State.zeros(g)
+    S.step(st)
+    t0 = time.perf_counter()
+    for _ in range(10):
+        S.step(st)
+    dt = time.perf_counter() - t0
+    out["pencil_10_steps"] = {"steps": 10, "s": round(dt, 2), "mpts": round(w.npts * 10 / dt / 1e6, 2)}
+    del S, st
+    nt = 1500 if full else 100
+    w = synth.blob(crop=160, nt=nt)
+    g, v = grid(w)
+    t0 = time.perf_counter()
+    O.forward(g, v, nt, w.src, w.wavelet, w.rec)
+    dt = time.perf_counter() - t0
+    out["blob160_crop"] = {"steps": nt, "s": round(dt, 2), "mpts": round(w.npts * nt / dt / 1e6, 2)}
+    shapes = synth.batch_shapes(24)
+    i = min(range(24), key=lambda k: np.prod(shapes[k]))
+    nt = 600 if full else 100
+    wt, v0 = synth.batch_shot(i, shapes[i], nt=nt)
+    g = O.Grid(n=wt.n, h=wt.h, dt=wt.dt, cpml=wt.cpml, vref=float(wt.v.max()))
+    vv = v0.astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    fwd = O.forward(g, vv, nt, wt.src, wt.wavelet, wt.rec, keep_lapf=True)
+    t1 = time.perf_counter()
+    O.gradient(g, vv, nt, wt.src, wt.wavelet, wt.rec, fwd["traces"], fwd=fwd)
+    t2 = time.perf_counter()
+    out["smallest_shot_fwd_adj"] = {"shape": list(shapes[i]), "steps": nt, "forward_s": round(t1 - t0, 2),
+                                    "adjoint_s": round(t2 - t1, 2),
+                                    "mpts_fwd_adj": round(wt.npts * nt / (t2 - t0) / 1e6, 2)}
+    out["sample"] = "full runs" if full else "100-step samples of the blob crop and the batched shot"
+    return out
+
+
 LEGS = {
+    "cpml_reflection": lambda: reflection_leg(),
+    "batched_fwd_adj_24": lambda: batched_fwd_adj_leg(),
+    "stream_ceiling": lambda: stream_ceiling_leg(),
+    "oracle_timings": lambda: oracle_timings_leg(full=os.environ.get("FDTD_ORACLE_FULL") == "1"),
     "storage_768": lambda: precision_leg(),
     "batched_24": lambda: batched_leg(),
     "small_64": lambda: small_leg(),
@@ -517,11 +792,22 @@ def main():
                     help="only time o = a + b * c over FP32 arrays of MIB MiB (3 read + 1 write streams)")
     ap.add_argument("--kernel-timing", action="store_true",
                     help="only run the per-kernel timing pass (the launches a profiler summary is taken over)")
+    ap.add_argument("--workload", default="layered", choices=("layered", "blob", "pencil"),
+                    help="workload of --kernel-timing: the layered N^3 grid, the Gaussian-blob N^3 grid of the "
+                         "storage leg, or the 1024x384x384 pencil share")
+    ap.add_argument("--storage", type=int, default=0, help="field storage of --kernel-timing: 0 FP32, 1 FP16, 2 BF16")
+    ap.add_argument("--exchange-every", type=int, default=1, help="s of the pencil workload (--kernel-timing)")
     ap.add_argument("--leg", choices=sorted(LEGS), help="only run one extra leg and print its JSON")
+    ap.add_argument("--plan", default="", metavar="V,RY,ZC,K,COLS",
+                    help="force a kernel plan on the headline runs (fdtd_set_plan arguments)")
     ap.add_argument("--no-storage-leg", action="store_true",
                     help="skip the 768^3 FP32/FP16/BF16 storage leg")
     ap.add_argument("--storage-leg", action="store_true", help="(default; kept for old command lines)")
     args = ap.parse_args()
+    if args.plan:
+        global PLAN
+        PLAN = tuple(int(x) for x in args.plan.split(","))
+        assert len(PLAN) == 5, "--plan takes variant,tile_ry,zchunk,tblock_k,tile_cols"
     if args.leg:
         print(json.dumps(LEGS[args.leg]()), flush=True)
         return
@@ -569,14 +855,24 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     K, W = args.steps, args.warmup
     n = (args.n, args.n, args.n)
-    w = synth.layered(n_xyz=n, nt=K + W + 2)
-    print("bench: layered %s, %d+%d steps" % (str(n), W, K), file=sys.stderr, flush=True)
     Kt = min(K, 200)
     if args.kernel_timing:
-        tm, plan = kernel_timing(w, Kt, W, args.variant)
+        kw = {}
+        if args.workload == "blob":
+            w = synth.blob(n=args.n, nt=Kt + W + 2)
+        elif args.workload == "pencil":
+            w = synth.pencil(nt=Kt + W + 2)
+            kw = dict(face=(0, 0, 1, 1, 1, 1), exchange_every=args.exchange_every)
+        else:
+            w = synth.layered(n_xyz=n, nt=Kt + W + 2)
+        print("bench: kernel timing, %s %s, storage %d" % (args.workload, str(w.n), args.storage), file=sys.stderr,
+              flush=True)
+        tm, plan = kernel_timing(w, Kt, W, args.variant, args.storage, **kw)
         print(json.dumps({"kernel_ms": {k: round(v[0], 5) for k, v in tm.items() if v[1] > 0},
                           "launches": {k: v[1] for k, v in tm.items() if v[1] > 0}, "plan": plan}), flush=True)
         return
+    w = synth.layered(n_xyz=n, nt=K + W + 2)
+    print("bench: layered %s, %d+%d steps" % (str(n), W, K), file=sys.stderr, flush=True)
     ms = time_gpu(w, K, W, args.variant, graph=not args.eager)
     tm, plan = kernel_timing(w, Kt, W, args.variant)
     N = w.npts
@@ -604,7 +900,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "layered %dx%dx%d, 20-cell CPML on 6 faces, Ricker 10 Hz, FP32 fields" % n,
-                   "grid": list(n), "cpml": 20, "variant": args.variant, "graph": not args.eager},
+                   "grid": list(n), "cpml": 20, "variant": args.variant, "graph": not args.eager,
+                   "plan": list(plan)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "measured_frac": (round(traffic / (upd[0] / 1e3) / 1e9 / PEAK_HBM_GBS, 4)
@@ -627,7 +924,8 @@ def main():
         out["variants_mpts"] = var
     if not args.no_extra:
         torch.cuda.empty_cache()
-        legs = ["batched_24", "small_64", "pencil_1024x384x384", "adjoint_3_smallest", "pv_paper_grids"]
+        legs = ["batched_24", "batched_fwd_adj_24", "small_64", "pencil_1024x384x384", "adjoint_3_smallest",
+                "pv_paper_grids", "cpml_reflection", "stream_ceiling"]
         if not args.no_storage_leg:
             legs.insert(0, "storage_768")
         for name in legs:
@@ -636,6 +934,9 @@ def main():
     if not args.no_cpu:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)
+        if not args.no_extra:
+            print("bench: oracle_timings leg", file=sys.stderr, flush=True)
+            out["oracle_timings"] = run_leg("oracle_timings")
     print(json.dumps(out), flush=True)
 
 

@@ -164,6 +164,21 @@ int fdtd_reset(fdtd_ctx *ctx);
 /* Steps taken since the last fdtd_reset. */
 int fdtd_get_step(const fdtd_ctx *ctx, int64_t *step);
 
+/* Resume support.  The full state of every shot of the context (u^n, u^{n-1}
+ * or, with 16-bit storage, d^n, and the layer memory psi, zeta, in the
+ * library's own padded layout) and the step count, as one blob of
+ * fdtd_state_size bytes in caller device memory (256-byte aligned pointers
+ * are not required).  fdtd_save_state enqueues the copy on the stream;
+ * fdtd_load_state restores a blob saved by a context created with the same
+ * shot configurations (EINVAL for a blob of another configuration or storage,
+ * checked from its header; it synchronises once to read the header), after
+ * which stepping continues bit for bit as it would have from the saved step
+ * (receiver rows are still indexed by the step count).  Model, source,
+ * receivers and plans are not part of the blob. */
+int fdtd_state_size(const fdtd_ctx *ctx, size_t *bytes);
+int fdtd_save_state(fdtd_ctx *ctx, void *dst_dev, size_t bytes);
+int fdtd_load_state(fdtd_ctx *ctx, const void *src_dev, size_t bytes);
+
 /* Synchronise and scan the wavefields of every shot; FDTD_ENONFINITE if any
  * NaN or Inf is present. */
 int fdtd_check_finite(fdtd_ctx *ctx);
@@ -185,7 +200,9 @@ int fdtd_set_checkpointing(fdtd_ctx *ctx, int32_t shot, int32_t every, void *buf
  * grad_v_dev (float64 [nz][ny][nx], overwritten) receives dJ/dv.  Reverse-time
  * sweep of the exact transposed step with segment recomputation from the
  * checkpoints; the layer profiles (v_ref) and dt are held fixed.  Leaves the
- * forward state of the shot undefined (call fdtd_reset before stepping). */
+ * forward state of this shot undefined (call fdtd_reset before stepping); the
+ * step count and the other shots' states are kept, so that after one batched
+ * forward run every shot's adjoint can be taken in turn. */
 int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev, double *grad_v_dev);
 
 /* Time candidate kernel shapes / temporal-block depths for every shot on
@@ -195,14 +212,19 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
 int fdtd_autotune(fdtd_ctx *ctx, const char *cache_path);
 
 /* Fix the kernel plan of one shot by hand (what fdtd_autotune chooses):
- * variant (naive / z-march / temporal blocking), z-march tile size
- * (1, 2, 4 or 8: tiles of 64 x 8*tile_ry points), z-chunk length (16..4096 planes
- * per workgroup) and temporal depth (2 or 4, temporal blocking only).
- * Results do not depend on the plan (same bits). */
-int fdtd_set_plan(fdtd_ctx *ctx, int32_t shot, int32_t variant, int32_t tile_ry, int32_t zchunk, int32_t tblock_k);
+ * variant (naive / z-march / temporal blocking), z-march tile height
+ * (tile_ry 1, 2, 4 or 8: tiles of 8*tile_ry rows), x points per lane
+ * (tile_cols 1: tiles 64 wide; 2: tiles 128 wide with paired loads, tile_ry
+ * 1, 2 or 4), z-chunk length (16..4096 planes per workgroup) and temporal
+ * depth (2 or 4, temporal blocking only).  Results do not depend on the plan
+ * (same bits). */
+int fdtd_set_plan(fdtd_ctx *ctx, int32_t shot, int32_t variant, int32_t tile_ry, int32_t zchunk, int32_t tblock_k,
+                  int32_t tile_cols);
 
-/* Choice made for one shot: variant, tile rows per thread, temporal depth. */
-int fdtd_get_plan(const fdtd_ctx *ctx, int32_t shot, int32_t *variant, int32_t *tile_ry, int32_t *tblock_k);
+/* Choice made for one shot: variant, tile height (tile_ry), temporal depth,
+ * x points per lane (tile_cols).  Any output pointer may be NULL. */
+int fdtd_get_plan(const fdtd_ctx *ctx, int32_t shot, int32_t *variant, int32_t *tile_ry, int32_t *tblock_k,
+                  int32_t *tile_cols);
 
 /* Storage scale of one shot (stored value = scale * u). */
 int fdtd_get_scale(const fdtd_ctx *ctx, int32_t shot, double *scale);
@@ -222,6 +244,16 @@ int fdtd_get_scale(const fdtd_ctx *ctx, int32_t shot, double *scale);
  * launch).  Enabling again clears the counters. */
 int fdtd_set_timing(fdtd_ctx *ctx, int32_t enable);
 int fdtd_get_timing(fdtd_ctx *ctx, int32_t kernel_class, double *mean_ms, int64_t *count);
+
+/* Measurement: the streaming ceiling that the interior update is judged
+ * against.  o[i] = a[i] + b[i] * c[i] over n float32 elements (three streams
+ * read, one written: the interior update's mix of u^n, u^{n-1}, m in and
+ * u^{n+1} out), 16 bytes per lane, a grid-stride loop over `blocks` blocks of
+ * 256 threads with `unroll` (1, 2 or 4) independent 16-byte pieces per thread
+ * in flight.  All four arrays are device arrays of n floats, 16-byte aligned,
+ * n a multiple of 4 (EINVAL otherwise).  Asynchronous on hip_stream. */
+int fdtd_stream_probe(const float *a_dev, const float *b_dev, const float *c_dev, float *o_dev, size_t n,
+                      int32_t blocks, int32_t unroll, void *hip_stream);
 
 const char *fdtd_strerror(int status);
 const char *fdtd_last_error(const fdtd_ctx *ctx);

@@ -93,19 +93,24 @@ _SIGS = {
     "fdtd_reset": (ctypes.c_int, [_P]),
     "fdtd_get_step": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
     "fdtd_check_finite": (ctypes.c_int, [_P]),
+    "fdtd_state_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "fdtd_save_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "fdtd_load_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "fdtd_adjoint_workspace_size": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                    ctypes.POINTER(ctypes.c_size_t)]),
     "fdtd_set_checkpointing": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t]),
     "fdtd_adjoint": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "fdtd_autotune": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "fdtd_set_plan": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                     ctypes.c_int32]),
+                                     ctypes.c_int32, ctypes.c_int32]),
     "fdtd_get_plan": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
-                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]),
     "fdtd_get_scale": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "fdtd_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "fdtd_get_timing": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]),
+    "fdtd_stream_probe": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _P]),
     "fdtd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fdtd_last_error": (ctypes.c_char_p, [_P]),
     "fdtd_destroy": (None, [_P]),

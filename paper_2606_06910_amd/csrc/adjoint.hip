@@ -316,12 +316,8 @@ static AdjLayout adj_layout(const ShotH &s, int every, int nt) {
 }
 }  // namespace
 
-static char *origin4(const ShotH &s, char *base) {
-    return base + ((size_t)kOFF + (size_t)s.fz * s.S + (size_t)s.fy * s.P) * 4;
-}
-static char *origin_t(const ShotH &s, char *base) {
-    return base + ((size_t)kOFF + (size_t)s.fz * s.S + (size_t)s.fy * s.P) * s.esz;
-}
+static char *origin4(const ShotH &s, char *base) { return base + origin_elems(s) * 4; }
+static char *origin_t(const ShotH &s, char *base) { return base + origin_elems(s) * s.esz; }
 
 template <typename T>
 static void launch_p3(const AdjArgs &a, const ShotH &s, float inv, hipStream_t st) {
@@ -454,6 +450,11 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
     a.G = grad_v_dev;
     const size_t fb = a256(s.elems * s.esz);
     char *seg = B + L.seg;
+    // the context's step count and level roles, restored on exit: the other shots
+    // of the context keep their forward state, so that each shot's adjoint can
+    // follow one batched forward run
+    const long step_in = ctx->step;
+    const int iu_in = ctx->iu, ium1_in = ctx->ium1;
     const bool was_saving = ctx->saving;
     ctx->saving = false;
     // largest per-axis thread counts of passes 1 (band points) and 2 (slab points)
@@ -506,6 +507,11 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
     hipLaunchKernelGGL(k_adj_finish, dim3((s.nx + 255) / 256, s.ny, s.nz), dim3(256), 0, st, sp, grad_v_dev,
                        s.c.dt);
     ctx->saving = was_saving;
+    ctx->step = step_in;
+    ctx->iu = iu_in;
+    ctx->ium1 = ium1_in;
+    fdtd_launch_set_int(stepc, (int)step_in, st);
+    fdtd_clear_graphs(ctx);
     ctx->hdesc[shot] = saved;
     AHIP(ctx, hipMemcpyAsync(dd + shot, &ctx->hdesc[shot], sizeof(DevShot), hipMemcpyHostToDevice, st));
     AHIP(ctx, hipStreamSynchronize(st));

@@ -15,7 +15,7 @@
 
 namespace {
 struct Plan {
-    int ry, zchunk, tk;
+    int ry, zchunk, tk, cols;
     double ms;
 };
 
@@ -28,7 +28,8 @@ std::string shape_key(const fdtd_ctx *ctx, const ShotH &s) {
     return buf;
 }
 
-// minimal reader for the cache written below: {"entries": [{"key": "...", "ry": R, "zchunk": Z, "tk": K, "ms": T}, ...]}
+// minimal reader for the cache written below:
+// {"entries": [{"key": "...", "ry": R, "zchunk": Z, "tk": K, "cols": C, "ms": T}, ...]}
 std::map<std::string, Plan> read_cache(const char *path) {
     std::map<std::string, Plan> out;
     if (!path) return out;
@@ -53,8 +54,11 @@ std::map<std::string, Plan> read_cache(const char *path) {
             size_t q0 = obj.find('"', k + 6);
             size_t q1 = q0 == std::string::npos ? q0 : obj.find('"', q0 + 1);
             if (q0 != std::string::npos && q1 != std::string::npos) {
-                Plan p{(int)num(obj, "ry", 2), (int)num(obj, "zchunk", 64), (int)num(obj, "tk", 1), num(obj, "ms", 0)};
-                if ((p.ry == 1 || p.ry == 2 || p.ry == 4 || p.ry == 8) && p.zchunk >= 16 && p.zchunk <= 4096)
+                Plan p{(int)num(obj, "ry", 2), (int)num(obj, "zchunk", 64), (int)num(obj, "tk", 1),
+                       (int)num(obj, "cols", 1), num(obj, "ms", 0)};
+                const bool ok_ry = p.cols == 2 ? (p.ry == 1 || p.ry == 2 || p.ry == 4)
+                                               : (p.cols == 1 && (p.ry == 1 || p.ry == 2 || p.ry == 4 || p.ry == 8));
+                if (ok_ry && p.zchunk >= 16 && p.zchunk <= 4096)
                     out[obj.substr(q0 + 1, q1 - q0 - 1)] = p;
             }
         }
@@ -71,8 +75,9 @@ void write_cache(const char *path, const std::map<std::string, Plan> &m) {
     fprintf(f, "{\"entries\": [\n");
     size_t i = 0;
     for (auto &kv : m) {
-        fprintf(f, "  {\"key\": \"%s\", \"ry\": %d, \"zchunk\": %d, \"tk\": %d, \"ms\": %.6f}%s\n", kv.first.c_str(),
-                kv.second.ry, kv.second.zchunk, kv.second.tk, kv.second.ms, ++i < m.size() ? "," : "");
+        fprintf(f, "  {\"key\": \"%s\", \"ry\": %d, \"zchunk\": %d, \"tk\": %d, \"cols\": %d, \"ms\": %.6f}%s\n",
+                kv.first.c_str(), kv.second.ry, kv.second.zchunk, kv.second.tk, kv.second.cols, kv.second.ms,
+                ++i < m.size() ? "," : "");
     }
     fprintf(f, "]}\n");
     fclose(f);
@@ -90,8 +95,10 @@ extern "C" int fdtd_autotune(fdtd_ctx *ctx, const char *cache_path) {
         ctx->err = "hipEventCreate failed";
         return FDTD_EHIP;
     }
-    // candidates: the default plan, then tile sizes x z-chunk lengths (4096: whole columns)
-    const int ry_c[4] = {1, 2, 4, 8};
+    // candidates: the default plan, then tile shapes (x points per lane, rows) x z-chunk
+    // lengths (4096: whole columns)
+    const int ry_c[7] = {1, 2, 4, 8, 1, 2, 4};
+    const int cx_c[7] = {1, 1, 1, 1, 2, 2, 2};
     const int zc_c[4] = {32, 64, 128, 4096};
     for (size_t i = 0; i < ctx->shots.size(); ++i) {
         ShotH &s = ctx->shots[i];
@@ -101,12 +108,14 @@ extern "C" int fdtd_autotune(fdtd_ctx *ctx, const char *cache_path) {
         if (it != cache.end()) {
             s.ry = it->second.ry;
             s.zchunk = it->second.zchunk;
+            s.zcols = it->second.cols;
             continue;
         }
-        Plan best{s.ry, s.zchunk, 1, 1e30};
-        const int ry0 = s.ry, zc0 = s.zchunk;
-        for (int c = -1; c < 16; ++c) {
+        Plan best{s.ry, s.zchunk, 1, s.zcols, 1e30};
+        const int ry0 = s.ry, zc0 = s.zchunk, cx0 = s.zcols;
+        for (int c = -1; c < 28; ++c) {
             s.ry = c < 0 ? ry0 : ry_c[c / 4];
+            s.zcols = c < 0 ? cx0 : cx_c[c / 4];
             s.zchunk = c < 0 ? zc0 : zc_c[c % 4];
             {
                 rc = fdtd_rewrite_work(ctx);
@@ -123,11 +132,12 @@ extern "C" int fdtd_autotune(fdtd_ctx *ctx, const char *cache_path) {
                 float ms = 0;
                 (void)hipEventElapsedTime(&ms, e0, e1);
                 double per = ms / reps;
-                if (per < best.ms) best = Plan{s.ry, s.zchunk, 1, per};
+                if (per < best.ms) best = Plan{s.ry, s.zchunk, 1, s.zcols, per};
             }
         }
         s.ry = best.ry;
         s.zchunk = best.zchunk;
+        s.zcols = best.cols;
         cache[key] = best;
     }
     (void)hipEventDestroy(e0);

@@ -14,6 +14,7 @@
 #include "fdtd_host.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -59,11 +60,11 @@ static void plan_shot(ShotH &s) {
     s.P = roundup(s.nx + 4, s.esz == 4 ? 64 : 128);
     s.PY = s.ny + 2 * s.fy;
     s.S = s.PY * s.P;
-    s.elems = (size_t)kOFF + (size_t)(s.nz + 2 * s.fz) * s.S + (size_t)(kTYMAX + 16) * s.P + 128;
     for (int d = 0; d < 3; ++d) {
         s.Llo[d] = c.cpml[2 * d];
         s.Lhi[d] = c.cpml[2 * d + 1];
     }
+    s.elems = (size_t)kOFF + (size_t)(s.nz + 2 * s.fz) * s.S + (size_t)(kTYMAX + 16) * s.P + 128;
     s.LX = s.Llo[0] + s.Lhi[0];
     s.LY = s.Llo[1] + s.Lhi[1];
     s.LZ = s.Llo[2] + s.Lhi[2];
@@ -248,12 +249,13 @@ static std::vector<BandItem> band_tiles(const ShotH &s, int shot) {
 }
 static size_t band_capacity(const ShotH &s) { return band_tiles(s, 0).size() + 8; }
 
-static std::vector<WorkItem> shot_tiles(const ShotH &s, int shot, int ry, int zchunk) {
+static std::vector<WorkItem> shot_tiles(const ShotH &s, int shot, int ry, int zchunk, int cols) {
     int ext = s.g - 4;
     int Ny = s.ny + (s.gy ? 2 * ext : 0);
     int Nz = s.nz + (s.gz ? 2 * ext : 0);
-    int TY = 8 * ry;   // z-march tile rows (64 x 8 ry points)
-    int ntx = (s.nx + 63) / 64, nty = (Ny + TY - 1) / TY, ntz = (Nz + zchunk - 1) / zchunk;
+    int TY = 8 * ry;   // z-march tile rows: tiles of 64 cols x 8 ry points
+    const int TX = 64 * cols;
+    int ntx = (s.nx + TX - 1) / TX, nty = (Ny + TY - 1) / TY, ntz = (Nz + zchunk - 1) / zchunk;
     std::vector<WorkItem> v;
     v.reserve((size_t)ntx * nty * ntz);
     for (int zc = 0; zc < ntz; ++zc)
@@ -347,10 +349,10 @@ static double d2_symbol_max() {
 static char *wsp(fdtd_ctx *ctx, size_t off) { return ctx->ws + off; }
 
 static void *field_origin(fdtd_ctx *ctx, const ShotH &s, size_t off) {
-    return wsp(ctx, off) + ((size_t)kOFF + (size_t)s.fz * s.S + (size_t)s.fy * s.P) * s.esz;
+    return wsp(ctx, off) + origin_elems(s) * s.esz;
 }
 static float *m_origin(fdtd_ctx *ctx, const ShotH &s) {
-    return (float *)(wsp(ctx, s.o_m) + ((size_t)kOFF + (size_t)s.fz * s.S + (size_t)s.fy * s.P) * 4);
+    return (float *)(wsp(ctx, s.o_m) + origin_elems(s) * 4);
 }
 
 static void fill_desc(fdtd_ctx *ctx, int i) {
@@ -425,6 +427,20 @@ static int upload_desc(fdtd_ctx *ctx) {
     return FDTD_OK;
 }
 
+// largest piece (16, 8, 4 or 2 bytes, at least the element) that divides both
+// row starts, every stride and the row length of a copy job, in bytes
+static void set_copy_vec(CopyJob &j) {
+    const uintptr_t bits = (uintptr_t)j.src | (uintptr_t)j.dst | (uintptr_t)(j.sy * j.esz) |
+                           (uintptr_t)(j.sz * j.esz) | (uintptr_t)(j.dy * j.esz) | (uintptr_t)(j.dz * j.esz) |
+                           (uintptr_t)(j.ex * j.esz);
+    j.vb = j.esz;
+    for (int vb : {16, 8, 4})
+        if (vb > j.esz && (bits & (uintptr_t)(vb - 1)) == 0) {
+            j.vb = vb;
+            break;
+        }
+}
+
 // ghost-exchange copy jobs (loopback): [parity][phase] with phases
 // 0 pack-y, 1 unpack-y, 2 pack-z, 3 unpack-z
 static void build_jobs(fdtd_ctx *ctx, int i, std::vector<CopyJob> (&jobs)[2][4], long (&maxe)[2][4]) {
@@ -473,13 +489,15 @@ static void build_jobs(fdtd_ctx *ctx, int i, std::vector<CopyJob> (&jobs)[2][4],
                     int yd = side == 0 ? s.ny : -f.dep;
                     char *buf = xb + off;
                     CopyJob pk{f.org + ((long)ys * f.rowst) * f.esz, buf, f.esz, f.ex, f.dep, s.nz,
-                               f.rowst, f.plst, (long)f.ex, (long)f.ex * f.dep};
+                               f.rowst, f.plst, (long)f.ex, (long)f.ex * f.dep, 0};
                     CopyJob up{buf, f.org + ((long)yd * f.rowst) * f.esz, f.esz, f.ex, f.dep, s.nz,
-                               (long)f.ex, (long)f.ex * f.dep, f.rowst, f.plst};
+                               (long)f.ex, (long)f.ex * f.dep, f.rowst, f.plst, 0};
+                    set_copy_vec(pk);
+                    set_copy_vec(up);
                     jobs[p][0].push_back(pk);
                     jobs[p][1].push_back(up);
-                    maxe[p][0] = std::max(maxe[p][0], face);
-                    maxe[p][1] = std::max(maxe[p][1], face);
+                    maxe[p][0] = std::max(maxe[p][0], (long)f.dep * s.nz);
+                    maxe[p][1] = std::max(maxe[p][1], (long)f.dep * s.nz);
                     off += align256(face * f.esz);
                 }
             }
@@ -496,12 +514,14 @@ static void build_jobs(fdtd_ctx *ctx, int i, std::vector<CopyJob> (&jobs)[2][4],
                     char *buf = xb + off;
                     char *src = f.org + ((long)zs * f.plst - (long)dy * f.rowst) * f.esz;
                     char *dst = f.org + ((long)zd * f.plst - (long)dy * f.rowst) * f.esz;
-                    CopyJob pk{src, buf, f.esz, f.ex, Ny, f.dep, f.rowst, f.plst, (long)f.ex, (long)f.ex * Ny};
-                    CopyJob up{buf, dst, f.esz, f.ex, Ny, f.dep, (long)f.ex, (long)f.ex * Ny, f.rowst, f.plst};
+                    CopyJob pk{src, buf, f.esz, f.ex, Ny, f.dep, f.rowst, f.plst, (long)f.ex, (long)f.ex * Ny, 0};
+                    CopyJob up{buf, dst, f.esz, f.ex, Ny, f.dep, (long)f.ex, (long)f.ex * Ny, f.rowst, f.plst, 0};
+                    set_copy_vec(pk);
+                    set_copy_vec(up);
                     jobs[p][2].push_back(pk);
                     jobs[p][3].push_back(up);
-                    maxe[p][2] = std::max(maxe[p][2], face);
-                    maxe[p][3] = std::max(maxe[p][3], face);
+                    maxe[p][2] = std::max(maxe[p][2], (long)Ny * f.dep);
+                    maxe[p][3] = std::max(maxe[p][3], (long)Ny * f.dep);
                     off += align256(face * f.esz);
                 }
             }
@@ -629,12 +649,13 @@ static void enqueue_psi_update(fdtd_ctx *ctx, int shot, const Roles &R) {
         if (grouped) {
             const WorkItem *wa = (const WorkItem *)wsp(ctx, ctx->o_work_all);
             for (const auto &g : ctx->groups)
-                fdtd_launch_zmarch(stor, dd, wa + g.off, g.nwork, g.ry, R, g.zchunk, stepc, side);
+                fdtd_launch_zmarch(stor, dd, wa + g.off, g.nwork, g.ry, g.cols, R, g.zchunk, stepc, side);
         } else {
             for (int i = lo; i < hi; ++i) {
                 const ShotH &s = ctx->shots[i];
                 if (s.variant == FDTD_VARIANT_NAIVE) continue;
-                fdtd_launch_zmarch(stor, dd, (const WorkItem *)wsp(ctx, s.o_work), s.nwork, s.ry, R, s.zchunk, stepc,
+                fdtd_launch_zmarch(stor, dd, (const WorkItem *)wsp(ctx, s.o_work), s.nwork, s.ry, s.zcols, R, s.zchunk,
+                                   stepc,
                                    side);
             }
         }
@@ -906,11 +927,12 @@ int fdtd_create(const fdtd_shot_config *shots, int32_t nshots, void *hip_stream,
     if (nshots > 1) {
         long W = 0;
         for (const auto &sh : ctx->shots)
-            if (sh.variant == FDTD_VARIANT_ZMARCH) W += (long)shot_tiles(sh, 0, sh.ry, sh.zchunk).size();
+            if (sh.variant == FDTD_VARIANT_ZMARCH) W += (long)shot_tiles(sh, 0, sh.ry, sh.zchunk, sh.zcols).size();
         if (W > kCUs)
             for (auto &sh : ctx->shots) {
                 sh.ry = 1;
                 sh.zchunk = 64;
+                sh.zcols = 1;
             }
     }
     for (auto &sh : ctx->shots)
@@ -972,7 +994,7 @@ int fdtd_workspace_size(const fdtd_ctx *ctx, size_t *bytes) {
 }
 
 static int write_work_lists(fdtd_ctx *ctx) {
-    std::map<std::pair<int, int>, std::vector<WorkItem>> byplan;
+    std::map<std::array<int, 3>, std::vector<WorkItem>> byplan;
     std::vector<BandItem> band_all;
     for (size_t i = 0; i < ctx->shots.size(); ++i) {
         ShotH &s = ctx->shots[i];
@@ -986,7 +1008,7 @@ static int write_work_lists(fdtd_ctx *ctx) {
                                            hipMemcpyHostToDevice, ctx->stream));
             if (s.variant != FDTD_VARIANT_NAIVE) band_all.insert(band_all.end(), bt.begin(), bt.end());
         }
-        std::vector<WorkItem> sp = shot_tiles(s, (int)i, s.ry, s.zchunk);
+        std::vector<WorkItem> sp = shot_tiles(s, (int)i, s.ry, s.zchunk, s.zcols);
         std::vector<WorkItem> w = xcd_order(sp);
         if (w.size() > work_capacity(s)) FAIL(ctx, FDTD_EINVAL, "work list overflow");
         s.nwork = (int)w.size();
@@ -994,7 +1016,7 @@ static int write_work_lists(fdtd_ctx *ctx) {
                                    ctx->stream));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
         if (s.variant != FDTD_VARIANT_NAIVE) {
-            auto &v = byplan[std::make_pair(s.ry, s.zchunk)];
+            auto &v = byplan[std::array<int, 3>{s.ry, s.zchunk, s.zcols}];
             v.insert(v.end(), sp.begin(), sp.end());
         }
         s.ntbwork = 0;
@@ -1014,7 +1036,7 @@ static int write_work_lists(fdtd_ctx *ctx) {
     std::vector<WorkItem> all;
     for (auto &kv : byplan) {
         std::vector<WorkItem> wa = xcd_order(kv.second);
-        fdtd_ctx::Group g{kv.first.first, kv.first.second, all.size(), (int)wa.size()};
+        fdtd_ctx::Group g{kv.first[0], kv.first[1], kv.first[2], all.size(), (int)wa.size()};
         ctx->groups.push_back(g);
         all.insert(all.end(), wa.begin(), wa.end());
     }
@@ -1139,21 +1161,26 @@ int fdtd_set_velocity(fdtd_ctx *ctx, int32_t shot, const float *v_dev) {
         std::vector<CopyJob> jy, jz;
         const int g = s.g;
         if (s.gy) {
-            jy.push_back(CopyJob{mo, mo + (long)s.ny * s.P, 4, s.nx, g, s.nz, (long)s.P, (long)s.S, (long)s.P, (long)s.S});
+            jy.push_back(CopyJob{mo, mo + (long)s.ny * s.P, 4, s.nx, g, s.nz, (long)s.P, (long)s.S, (long)s.P, (long)s.S,
+                                 0});
             jy.push_back(CopyJob{mo + (long)(s.ny - g) * s.P, mo - (long)g * s.P, 4, s.nx, g, s.nz, (long)s.P, (long)s.S,
-                                 (long)s.P, (long)s.S});
+                                 (long)s.P, (long)s.S, 0});
         }
         if (s.gz) {
             const int dy = s.gy ? g : 0, Ny = s.ny + 2 * dy;
             float *b = mo - (long)dy * s.P;
-            jz.push_back(CopyJob{b, b + (long)s.nz * s.S, 4, s.nx, Ny, g, (long)s.P, (long)s.S, (long)s.P, (long)s.S});
+            jz.push_back(CopyJob{b, b + (long)s.nz * s.S, 4, s.nx, Ny, g, (long)s.P, (long)s.S, (long)s.P, (long)s.S,
+                                 0});
             jz.push_back(CopyJob{b + (long)(s.nz - g) * s.S, b - (long)g * s.S, 4, s.nx, Ny, g, (long)s.P, (long)s.S,
-                                 (long)s.P, (long)s.S});
+                                 (long)s.P, (long)s.S, 0});
         }
         for (auto *jobs : {&jy, &jz}) {
             if (jobs->empty()) continue;
             long mx = 0;
-            for (auto &j : *jobs) mx = std::max(mx, (long)j.ex * j.ey * j.ez);
+            for (auto &j : *jobs) {
+                set_copy_vec(j);
+                mx = std::max(mx, (long)j.ey * j.ez);
+            }
             HIPCHK(ctx, hipMemcpyAsync(wsp(ctx, s.o_jobs[0][0]), jobs->data(), sizeof(CopyJob) * jobs->size(),
                                        hipMemcpyHostToDevice, ctx->stream));
             fdtd_launch_copy_jobs(wsp(ctx, s.o_jobs[0][0]), (int)jobs->size(), mx, ctx->stream);
@@ -1413,12 +1440,15 @@ int fdtd_check_finite(fdtd_ctx *ctx) {
     return FDTD_OK;
 }
 
-int fdtd_set_plan(fdtd_ctx *ctx, int32_t shot, int32_t variant, int32_t tile_ry, int32_t zchunk, int32_t tblock_k) {
+int fdtd_set_plan(fdtd_ctx *ctx, int32_t shot, int32_t variant, int32_t tile_ry, int32_t zchunk, int32_t tblock_k,
+                  int32_t tile_cols) {
     if (!ctx || shot < 0 || shot >= (int)ctx->shots.size()) return FDTD_EINVAL;
     if (variant < 1 || variant > 3) FAIL(ctx, FDTD_EINVAL, "variant must be naive, z-march or temporal blocking");
     if (tile_ry != 1 && tile_ry != 2 && tile_ry != 4 && tile_ry != 8)
         FAIL(ctx, FDTD_EINVAL, "tile size must be 1, 2, 4 or 8 (64 x 8 tile_ry points)");
     if (zchunk < 16 || zchunk > 4096) FAIL(ctx, FDTD_EINVAL, "z chunk must be in [16, 4096]");
+    if (tile_cols != 1 && tile_cols != 2) FAIL(ctx, FDTD_EINVAL, "tile_cols must be 1 or 2 (x points per lane)");
+    if (tile_cols == 2 && tile_ry == 8) FAIL(ctx, FDTD_EINVAL, "two-column tiles are 128 x 8, 16 or 32 points");
     if (variant == FDTD_VARIANT_TBLOCK && tblock_k != 2 && tblock_k != 4) FAIL(ctx, FDTD_EINVAL, "tblock_k must be 2 or 4");
     ShotH &s = ctx->shots[shot];
     if (variant == FDTD_VARIANT_TBLOCK && !s.tb_bufs)
@@ -1426,17 +1456,24 @@ int fdtd_set_plan(fdtd_ctx *ctx, int32_t shot, int32_t variant, int32_t tile_ry,
     s.variant = variant;
     s.ry = tile_ry;
     s.zchunk = zchunk;
+    s.zcols = tile_cols;
     s.tk = variant == FDTD_VARIANT_TBLOCK ? tblock_k : 1;
     fdtd_clear_graphs(ctx);
     if (!ctx->ws) return FDTD_OK;
-    return write_work_lists(ctx);
+    const int rc = write_work_lists(ctx);
+    if (rc) return rc;
+    // the variant decides whether the band kernel advances psi_x and psi_z itself
+    // (DevShot::fused), which the kernels read from the descriptor
+    return upload_desc(ctx);
 }
 
-int fdtd_get_plan(const fdtd_ctx *ctx, int32_t shot, int32_t *variant, int32_t *tile_ry, int32_t *tblock_k) {
+int fdtd_get_plan(const fdtd_ctx *ctx, int32_t shot, int32_t *variant, int32_t *tile_ry, int32_t *tblock_k,
+                  int32_t *tile_cols) {
     if (!ctx || shot < 0 || shot >= (int)ctx->shots.size()) return FDTD_EINVAL;
     const ShotH &s = ctx->shots[shot];
     if (variant) *variant = s.variant;
     if (tile_ry) *tile_ry = s.ry;
+    if (tile_cols) *tile_cols = s.zcols;
     if (tblock_k) *tblock_k = s.variant == FDTD_VARIANT_TBLOCK ? s.tk : 1;
     return FDTD_OK;
 }
@@ -1445,6 +1482,87 @@ int fdtd_get_scale(const fdtd_ctx *ctx, int32_t shot, double *scale) {
     if (!ctx || !scale || shot < 0 || shot >= (int)ctx->shots.size()) return FDTD_EINVAL;
     *scale = ctx->shots[shot].scale;
     return FDTD_OK;
+}
+
+// saved-state blob: a header (256-byte aligned), then each shot's state in the checkpoint layout
+struct StateHeader {
+    char magic[8];       // "FDTDSTAT"
+    int64_t step;
+    int32_t nshots, storage;
+    uint64_t shot_bytes[FDTD_MAXSHOTS];   // fdtd_state_bytes of each shot (identifies the layout)
+};
+static_assert(sizeof(StateHeader) <= 8 + 8 + 8 + 8 * FDTD_MAXSHOTS, "header layout");
+static size_t state_blob_bytes(const fdtd_ctx *ctx) {
+    size_t b = align256(sizeof(StateHeader));
+    for (const ShotH &s : ctx->shots) b += fdtd_state_bytes(s);
+    return b;
+}
+
+int fdtd_state_size(const fdtd_ctx *ctx, size_t *bytes) {
+    if (!ctx || !bytes) return FDTD_EINVAL;
+    *bytes = state_blob_bytes(ctx);
+    return FDTD_OK;
+}
+
+int fdtd_save_state(fdtd_ctx *ctx, void *dst_dev, size_t bytes) {
+    if (!ctx || !dst_dev) return FDTD_EINVAL;
+    if (!ctx->ws) FAIL(ctx, FDTD_ESTATE, "no workspace bound");
+    if (bytes < state_blob_bytes(ctx)) FAIL(ctx, FDTD_ENOMEM, "state buffer of %zu bytes, need %zu", bytes,
+                                            state_blob_bytes(ctx));
+    StateHeader h;
+    memset(&h, 0, sizeof h);
+    memcpy(h.magic, "FDTDSTAT", 8);
+    h.step = ctx->step;
+    h.nshots = (int32_t)ctx->shots.size();
+    h.storage = ctx->storage;
+    for (size_t i = 0; i < ctx->shots.size(); ++i) h.shot_bytes[i] = fdtd_state_bytes(ctx->shots[i]);
+    static_assert(sizeof(StateHeader) <= sizeof(ctx->state_hdr), "header fits");
+    memcpy(ctx->state_hdr, &h, sizeof h);   // kept in the context until the copy has run
+    char *dst = (char *)dst_dev;
+    HIPCHK(ctx, hipMemcpyAsync(dst, ctx->state_hdr, sizeof h, hipMemcpyHostToDevice, ctx->stream));
+    size_t off = align256(sizeof(StateHeader));
+    for (size_t i = 0; i < ctx->shots.size(); ++i) {
+        copy_state(ctx, (int)i, dst + off, true);
+        off += fdtd_state_bytes(ctx->shots[i]);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    return FDTD_OK;
+}
+
+int fdtd_load_state(fdtd_ctx *ctx, const void *src_dev, size_t bytes) {
+    if (!ctx || !src_dev) return FDTD_EINVAL;
+    if (!ctx->ws) FAIL(ctx, FDTD_ESTATE, "no workspace bound");
+    if (bytes < state_blob_bytes(ctx)) FAIL(ctx, FDTD_EINVAL, "state buffer of %zu bytes, need %zu", bytes,
+                                            state_blob_bytes(ctx));
+    StateHeader h;
+    HIPCHK(ctx, hipMemcpyAsync(&h, src_dev, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (memcmp(h.magic, "FDTDSTAT", 8) != 0) FAIL(ctx, FDTD_EINVAL, "not a saved state");
+    if (h.nshots != (int32_t)ctx->shots.size() || h.storage != ctx->storage || h.step < 0)
+        FAIL(ctx, FDTD_EINVAL, "saved state is of another context configuration");
+    for (size_t i = 0; i < ctx->shots.size(); ++i)
+        if (h.shot_bytes[i] != fdtd_state_bytes(ctx->shots[i]))
+            FAIL(ctx, FDTD_EINVAL, "saved state of shot %zu has another layout", i);
+    const char *src = (const char *)src_dev;
+    size_t off = align256(sizeof(StateHeader));
+    for (size_t i = 0; i < ctx->shots.size(); ++i) {
+        copy_state(ctx, (int)i, (char *)src + off, false);
+        off += fdtd_state_bytes(ctx->shots[i]);
+    }
+    ctx->step = h.step;
+    fdtd_launch_set_int((int *)wsp(ctx, ctx->o_stepc), (int)h.step, ctx->stream);
+    fdtd_clear_graphs(ctx);
+    HIPCHK(ctx, hipGetLastError());
+    return FDTD_OK;
+}
+
+int fdtd_stream_probe(const float *a_dev, const float *b_dev, const float *c_dev, float *o_dev, size_t n,
+                      int32_t blocks, int32_t unroll, void *hip_stream) {
+    if (!a_dev || !b_dev || !c_dev || !o_dev || n == 0 || (n & 3) || blocks <= 0 || blocks > (1 << 20))
+        return FDTD_EINVAL;
+    if ((((uintptr_t)a_dev | (uintptr_t)b_dev | (uintptr_t)c_dev | (uintptr_t)o_dev) & 15) != 0) return FDTD_EINVAL;
+    fdtd_launch_stream_probe(a_dev, b_dev, c_dev, o_dev, n / 4, blocks, unroll, (hipStream_t)hip_stream);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EHIP;
 }
 
 void fdtd_destroy(fdtd_ctx *ctx) {

@@ -96,13 +96,16 @@ struct DevShot {
     float w1[3][5];        // d_l / h_d   (w1[d][0] unused)
 };
 
-// Strided box copy (ghost pack/unpack, checkpoints).
+// Strided box copy (ghost pack/unpack).  Rows (ex elements) are copied in
+// vb-byte pieces: vb in {16, 8, 4, 2} divides both row starts, every stride
+// and the row length in bytes (set by the host, copy_vec_bytes).
 struct CopyJob {
     const void *src;
     void *dst;
     int esz;              // bytes per element (2 or 4)
     int ex, ey, ez;       // box extent (elements)
     long sy, sz, dy, dz;  // row / plane strides (elements) of source and destination
+    int vb;               // bytes per copied piece
 };
 
 // Roles of the level buffers in one launch and an optional box of points the
@@ -310,7 +313,9 @@ __device__ __forceinline__ float lap_interior(const DevShot &s, float c, const f
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 // A lane offset at or past a descriptor's record count reads zero and drops a
 // store without touching memory; lanes that need no data use this one (any
-// scalar offset the kernels add keeps the sum below 2^32).
+// scalar offset the kernels add keeps the sum below 2^32).  Only the lane
+// offset is range-checked: the scalar offset is not, so it must always
+// address memory inside the buffer and never carries this value.
 constexpr uint32_t kBufSkip = 0x80000000u;
 __device__ __forceinline__ Rsrc make_rsrc(const void *base) {
     return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, 0x7fffffff, 0x00020000);
@@ -338,6 +343,32 @@ template <> struct Buf<__bf16> {
     }
     static __device__ __forceinline__ void st(Rsrc r, uint32_t vo, uint32_t so, float v) {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (__bf16)v), r, vo, so, 0);
+    }
+};
+
+// Two consecutive x elements (an even element offset, so that the pair is 8-
+// (FP32) or 4-byte (16-bit) aligned) loaded with one buffer load and widened
+// to FP32.  The scalar offset must stay in range as for Buf.  (The 64-bit
+// load is reinterpreted whole: taking its two elements one by one makes the
+// compiler emit a single-dword load and repeat it in both.)
+template <typename T> struct Buf2;
+template <> struct Buf2<float> {
+    static __device__ __forceinline__ float2 ld(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+};
+template <> struct Buf2<_Float16> {
+    static __device__ __forceinline__ float2 ld(Rsrc r, uint32_t vo, uint32_t so) {
+        const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);
+        return make_float2((float)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xffffu)),
+                           (float)__builtin_bit_cast(_Float16, (unsigned short)(v >> 16)));
+    }
+};
+template <> struct Buf2<__bf16> {
+    static __device__ __forceinline__ float2 ld(Rsrc r, uint32_t vo, uint32_t so) {
+        const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);
+        return make_float2((float)__builtin_bit_cast(__bf16, (unsigned short)(v & 0xffffu)),
+                           (float)__builtin_bit_cast(__bf16, (unsigned short)(v >> 16)));
     }
 };
 

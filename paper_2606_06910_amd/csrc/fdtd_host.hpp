@@ -53,6 +53,7 @@ struct ShotH {
     int cap = 0;
     // plan
     int variant = FDTD_VARIANT_ZMARCH, ry = 2, zchunk = 64, tk = 1;
+    int zcols = 1;             // z-march x points per lane (1: 64-wide tiles, 2: 128-wide tiles)
     // temporal blocking (FP32, Dirichlet, single-shot contexts): 4 level buffers,
     // interior box B (outside every band, x bounds multiples of 4), tile list over B_K,
     // receivers sorted by z
@@ -79,7 +80,7 @@ struct fdtd_ctx {
     int nwork_all = 0, nband_all = 0;
     // multi-shot z-march launches: one per distinct (ry, zchunk) plan
     struct Group {
-        int ry, zchunk;
+        int ry, zchunk, cols;
         size_t off;   // offset into the o_work_all region (items)
         int nwork;
     };
@@ -90,6 +91,7 @@ struct fdtd_ctx {
     long step = 0;
     bool saving = true; // checkpoint saving enabled (off during adjoint recomputation)
     std::string err;
+    unsigned char state_hdr[1024] = {};  // header of the last fdtd_save_state (read by its copy)
     struct GraphEntry {
         hipGraphExec_t exec;
         int end_iu, end_ium1;
@@ -103,6 +105,13 @@ struct fdtd_ctx {
     double t_sum[kTimingClasses] = {};
     long t_cnt[kTimingClasses] = {};
 };
+
+// Element offset of (x, y, z) = (0, 0, 0) from the start of a field buffer of
+// the shot (every field, m and the adjoint's full-grid arrays share it); row
+// starts, and so x = 0, are 64-element aligned.
+inline size_t origin_elems(const ShotH &s) {
+    return (size_t)kOFF + (size_t)s.fz * s.S + (size_t)s.fy * s.P;
+}
 
 // helpers exported by fdtd_api.hip for the other translation units
 size_t fdtd_state_bytes(const ShotH &s);

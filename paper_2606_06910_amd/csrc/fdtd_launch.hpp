@@ -10,8 +10,10 @@ void fdtd_launch_psi(int stor, const DevShot *d_shots, int nshots, long max_coun
 void fdtd_launch_psi_y(int stor, const DevShot *d_shots, int nshots, long max_lines, int iu, int ext, hipStream_t st);
 void fdtd_launch_naive(int stor, const DevShot *d_shots, int shot, int nx, int Ny, int Nz, const Roles &R,
                        const int *stepc, hipStream_t st);
-void fdtd_launch_zmarch(int stor, const DevShot *d_shots, const WorkItem *work, int nwork, int ry, const Roles &R,
-                        int zchunk, const int *stepc, hipStream_t st);
+// z-march of the points outside the bands: cols x points per lane (1: tiles of
+// 64 x 8 ry points, 2: 128 x 8 ry)
+void fdtd_launch_zmarch(int stor, const DevShot *d_shots, const WorkItem *work, int nwork, int ry, int cols,
+                        const Roles &R, int zchunk, const int *stepc, hipStream_t st);
 // band points (tiles of every box kind in one list)
 void fdtd_launch_band(int stor, const DevShot *d_shots, const BandItem *work, int nwork, const Roles &R, int zchunk,
                       const int *stepc, hipStream_t st);
@@ -40,5 +42,8 @@ void fdtd_launch_get_prev(int stor, const void *u, const void *d, float *dst, in
                           float inv, hipStream_t st);
 void fdtd_launch_set_prev(int stor, const void *u, void *d, const float *src, int nx, int ny, int nz, int P, int S,
                           float sc, hipStream_t st);
-void fdtd_launch_copy_jobs(const void *jobs, int njobs, long max_elems, hipStream_t st);
+// strided box copies (CopyJob list); max_rows = most rows (ey * ez) of a job
+void fdtd_launch_copy_jobs(const void *jobs, int njobs, long max_rows, hipStream_t st);
 void fdtd_launch_set_int(int *p, int v, hipStream_t st);
+void fdtd_launch_stream_probe(const float *a, const float *b, const float *c, float *o, size_t n4, int blocks,
+                              int unroll, hipStream_t st);

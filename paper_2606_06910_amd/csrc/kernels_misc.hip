@@ -85,20 +85,33 @@ __global__ __launch_bounds__(256) void k_set_prev(const T *__restrict__ u, T *__
     Store<T>::st(d + i, Store<T>::ld(u + i) - src[((long)blockIdx.z * ny + blockIdx.y) * nx + x] * scale);
 }
 
-// grid: (ceil(ex*ey*ez / 256), njobs)
+// One row of a job per group of lanes: `lanes` consecutive threads copy a row
+// in vb-byte pieces (16-byte pieces for FP32 rows that allow them), a block
+// takes 256 / lanes rows per pass and strides over the job's rows; the only
+// index arithmetic is one 32-bit division per row.  grid: (row blocks, njobs)
+template <typename V>
+__device__ __forceinline__ void copy_row(const char *s, char *d, int nv, int tv, int lanes) {
+    for (int v = tv; v < nv; v += lanes) ((V *)d)[v] = ((const V *)s)[v];
+}
 __global__ __launch_bounds__(256) void k_copy_jobs(const CopyJob *__restrict__ jobs) {
     const CopyJob j = jobs[blockIdx.y];
-    const long n = (long)j.ex * j.ey * j.ez;
-    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const int x = (int)(t % j.ex);
-    const long r = t / j.ex;
-    const int y = (int)(r % j.ey);
-    const int z = (int)(r / j.ey);
-    const long so = (long)z * j.sz + (long)y * j.sy + x;
-    const long dof = (long)z * j.dz + (long)y * j.dy + x;
-    if (j.esz == 4) ((uint32_t *)j.dst)[dof] = ((const uint32_t *)j.src)[so];
-    else ((uint16_t *)j.dst)[dof] = ((const uint16_t *)j.src)[so];
+    const int nrows = j.ey * j.ez;
+    const int nv = j.ex * j.esz / j.vb;            // pieces per row
+    const int lanes = nv < 256 ? nv : 256;         // threads per row
+    const int rp = 256 / lanes;                    // rows per block pass
+    const int tr = (int)threadIdx.x / lanes, tv = (int)threadIdx.x - tr * lanes;
+    if (tr >= rp) return;
+    for (int r = (int)blockIdx.x * rp + tr; r < nrows; r += (int)gridDim.x * rp) {
+        const int z = r / j.ey, y = r - z * j.ey;
+        const char *s = (const char *)j.src + ((long)z * j.sz + (long)y * j.sy) * j.esz;
+        char *d = (char *)j.dst + ((long)z * j.dz + (long)y * j.dy) * j.esz;
+        switch (j.vb) {
+        case 16: copy_row<uint4>(s, d, nv, tv, lanes); break;
+        case 8: copy_row<uint2>(s, d, nv, tv, lanes); break;
+        case 4: copy_row<uint32_t>(s, d, nv, tv, lanes); break;
+        default: copy_row<uint16_t>(s, d, nv, tv, lanes); break;
+        }
+    }
 }
 
 template <typename T>
@@ -177,12 +190,47 @@ void fdtd_launch_set_prev(int stor, const void *u, void *d, const float *src, in
                           float sc, hipStream_t st) {
     MISC_DISPATCH(stor, sp, u, d, src, nx, ny, nz, P, S, sc, st);
 }
-void fdtd_launch_copy_jobs(const void *jobs, int njobs, long max_elems, hipStream_t st) {
-    if (njobs <= 0 || max_elems <= 0) return;
-    hipLaunchKernelGGL(k_copy_jobs, dim3((unsigned)((max_elems + 255) / 256), njobs), dim3(256), 0, st,
-                       (const CopyJob *)jobs);
+void fdtd_launch_copy_jobs(const void *jobs, int njobs, long max_rows, hipStream_t st) {
+    if (njobs <= 0 || max_rows <= 0) return;
+    const unsigned gx = (unsigned)(max_rows < 1024 ? max_rows : 1024);
+    hipLaunchKernelGGL(k_copy_jobs, dim3(gx, njobs), dim3(256), 0, st, (const CopyJob *)jobs);
 }
 
+
+// Streaming ceiling of the interior update's access mix: o = a + b * c over
+// float4 lanes (three streams read, one written, 16 bytes per lane), a
+// grid-stride loop with `unroll` independent float4 per thread in flight.
+template <int U>
+__global__ __launch_bounds__(256) void k_stream_probe(const float4 *__restrict__ a, const float4 *__restrict__ b,
+                                                     const float4 *__restrict__ c, float4 *__restrict__ o, size_t n4) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (U - 1) * stride < n4; i += U * stride) {
+        float4 x[U], y[U], z[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            x[k] = a[i + k * stride];
+            y[k] = b[i + k * stride];
+            z[k] = c[i + k * stride];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            o[i + k * stride] = make_float4(fmaf(y[k].x, z[k].x, x[k].x), fmaf(y[k].y, z[k].y, x[k].y),
+                                            fmaf(y[k].z, z[k].z, x[k].z), fmaf(y[k].w, z[k].w, x[k].w));
+    }
+    for (; i < n4; i += stride) {
+        const float4 x = a[i], y = b[i], z = c[i];
+        o[i] = make_float4(fmaf(y.x, z.x, x.x), fmaf(y.y, z.y, x.y), fmaf(y.z, z.z, x.z), fmaf(y.w, z.w, x.w));
+    }
+}
+void fdtd_launch_stream_probe(const float *a, const float *b, const float *c, float *o, size_t n4, int blocks,
+                              int unroll, hipStream_t st) {
+    const dim3 g((unsigned)blocks), t(256);
+    const float4 *A = (const float4 *)a, *B = (const float4 *)b, *C = (const float4 *)c;
+    if (unroll >= 4) hipLaunchKernelGGL(k_stream_probe<4>, g, t, 0, st, A, B, C, (float4 *)o, n4);
+    else if (unroll == 2) hipLaunchKernelGGL(k_stream_probe<2>, g, t, 0, st, A, B, C, (float4 *)o, n4);
+    else hipLaunchKernelGGL(k_stream_probe<1>, g, t, 0, st, A, B, C, (float4 *)o, n4);
+}
 
 __global__ void k_set_int(int *p, int v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;

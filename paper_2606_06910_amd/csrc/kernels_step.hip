@@ -211,9 +211,11 @@ __device__ __forceinline__ void zbody(ZCtx<T, NW, RY> &C, const DevShot &s, floa
     // that it is found in L2), u^{n-1} (or d^n) and m plane z + 2
     float umn[RY], mn[RY];
     {
-        // (past the last plane the segment's stencils read, the u^n loads take an
-        // out-of-range offset: zero, no traffic, nothing read beyond the frame)
-        const uint32_t s6 = z + 6 <= C.zlast ? (PH + 6) * C.Sb : kBufSkip;
+        // (past the last plane the segment's stencils read, the u^n loads re-read
+        // that last plane instead: no stencil of the segment uses the value, and
+        // the plane offset stays inside the field, because the scalar offset of
+        // a buffer load is not covered by the descriptor's range check)
+        const uint32_t s6 = (uint32_t)(min(z + 6, C.zlast) - z + PH) * C.Sb;
         const uint32_t s2 = (PH + 2) * C.Sb, m2 = (PH + 2) * C.Smb;
 #pragma unroll
         for (int r = 0; r < RY; ++r) q[slot(6)][r] = Buf<T>::ld(C.ru, C.off[r], s6);
@@ -391,7 +393,7 @@ __global__ __launch_bounds__(64 * NW) void k_zmarch(const DevShot *__restrict__ 
             for (int o = -4; o < 6; ++o)
 #pragma unroll
                 for (int r = 0; r < RY; ++r)
-                    q[o + 4][r] = Buf<T>::ld(ru, C.off[r], a + o <= C.zlast ? (o + 4) * C.Sb : kBufSkip);
+                    q[o + 4][r] = Buf<T>::ld(ru, C.off[r], (uint32_t)(min(a + o, C.zlast) - a + 4) * C.Sb);
             const Rsrc rs = make_rsrc(C.sec + (long)a * C.Sb);
             const Rsrc rm = make_rsrc(C.m + (long)a * C.Smb);
 #pragma unroll
@@ -407,7 +409,7 @@ __global__ __launch_bounds__(64 * NW) void k_zmarch(const DevShot *__restrict__ 
             for (int o = 0; o < 6; ++o)
 #pragma unroll
                 for (int k = 0; k < G::HS; ++k)
-                    hq[o + 4][k] = Buf<T>::ld(ru, C.hoff[k], a + o <= C.zlast ? (o + 4) * C.Sb : kBufSkip);
+                    hq[o + 4][k] = Buf<T>::ld(ru, C.hoff[k], (uint32_t)(min(a + o, C.zlast) - a + 4) * C.Sb);
         }
         for (int z0 = a; z0 < b; z0 += ZQ) {
             C.ru = make_rsrc(C.u + (long)z0 * C.Sb);
@@ -423,6 +425,291 @@ __global__ __launch_bounds__(64 * NW) void k_zmarch(const DevShot *__restrict__ 
             ZSTEP(0) ZSTEP(1) ZSTEP(2) ZSTEP(3) ZSTEP(4) ZSTEP(5)
             ZSTEP(6) ZSTEP(7) ZSTEP(8) ZSTEP(9) ZSTEP(10)
 #undef ZSTEP
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// z-march with two x points per lane.  The same scheme as k_zmarch, on tiles
+// of 128 x TY points: lane l of wave w owns columns x0 + 2l and x0 + 2l + 1 of
+// rows w RY .. w RY + RY - 1, and every global load and LDS access moves the
+// pair at once (8 bytes per lane for FP32, 4 for 16-bit storage), so a point
+// costs half the load instructions of the one-column kernel.  Rows start on
+// 64-element boundaries and tiles at multiples of 128, so every pair's element
+// offset is even and its load aligned.  Each point goes through the same arithmetic as
+// every other variant, so the bits are the same.
+// ---------------------------------------------------------------------------
+template <int NW, int RY> struct ZM2 {
+    static constexpr int NT = 64 * NW;                     // threads
+    static constexpr int TY = NW * RY;                     // tile rows
+    static constexpr int LW = 128 + 2 * FDTD_R;            // LDS row length
+    static constexpr int LH = TY + 2 * FDTD_R;             // LDS rows
+    static constexpr int LB = LH * LW + 8;                 // one LDS buffer (+ a dummy pair)
+    static constexpr int NHX = 4 * TY;                     // x-halo pairs: 2 left and 2 right per row
+    static constexpr int NH = NHX + 2 * FDTD_R * 64;       // + 8 halo rows of 64 pairs
+    static constexpr int HS = (NH + NT - 1) / NT;          // halo pairs per thread
+};
+
+template <typename T, int NW, int RY> struct ZCtx2 {
+    Coef K;
+    const char *u, *m;
+    char *w, *sec;
+    uint32_t Sb, Smb;
+    Rsrc ru, rm, rw, rs;
+    uint32_t off[RY];             // own pair: u^n byte offset (kBufSkip when neither point needs it)
+    uint32_t offs[RY], offm[RY];  // own pair: second-state / u^{n+1} and m offsets (kBufSkip off the box)
+    uint32_t hoff[ZM2<NW, RY>::HS];
+    int hslot[ZM2<NW, RY>::HS];   // LDS index of the halo pair (even; the dummy pair for a lane without one)
+    float2 umc[RY], mc[RY];       // second state and m of plane z
+    float2 um1[RY], m1[RY];       // the same of plane z + 1
+    const Roles *R;
+    int zlast;
+    int x, y0, lane, r0;          // first column of the lane's pair, tile origin row, lane, first own row
+    int nlo[3], nhi[3];
+    int sx, sy, sz;
+    bool full, partial, src_tile;
+    float src;
+};
+
+template <typename T, int NW, int RY>
+__device__ __forceinline__ bool zm2_ok(const ZCtx2<T, NW, RY> &C, int x, int y, int z) {
+    return C.full || (x >= C.nlo[0] && x < C.nhi[0] && y >= C.nlo[1] && y < C.nhi[1] &&
+                      !(C.partial && in_box(*C.R, x, y, z)));
+}
+
+template <typename T, int NW, int RY, int PH>
+__device__ __forceinline__ void zbody2(ZCtx2<T, NW, RY> &C, const DevShot &s, float2 (&q)[ZQ][RY],
+                                       float2 (&hq)[ZQ][ZM2<NW, RY>::HS], float *L, int z) {
+    using G = ZM2<NW, RY>;
+    auto slot = [](int o) { return (PH + 4 + o + ZQ) % ZQ; };
+    float2 umn[RY], mn[RY];
+    {
+        // u^n and its halo of plane z + 6 (clamped to the segment's last read plane,
+        // whose value no stencil of the segment then uses), second state and m of z + 2
+        const uint32_t s6 = (uint32_t)(min(z + 6, C.zlast) - z + PH) * C.Sb;
+        const uint32_t s2 = (PH + 2) * C.Sb, m2 = (PH + 2) * C.Smb;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) q[slot(6)][r] = Buf2<T>::ld(C.ru, C.off[r], s6);
+#pragma unroll
+        for (int k = 0; k < G::HS; ++k) hq[slot(6)][k] = Buf2<T>::ld(C.ru, C.hoff[k], s6);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            umn[r] = Buf2<T>::ld(C.rs, C.offs[r], s2);
+            mn[r] = Buf2<float>::ld(C.rm, C.offm[r], m2);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) *(float2 *)&L[(FDTD_R + C.r0 + r) * G::LW + FDTD_R + 2 * C.lane] = q[slot(0)][r];
+#pragma unroll
+    for (int k = 0; k < G::HS; ++k) *(float2 *)&L[C.hslot[k]] = hq[slot(0)][k];
+    __syncthreads();
+    const bool srcplane = C.src_tile && wrap_ghost(s, 2, z) == C.sz;
+    const uint32_t s0 = PH * C.Sb;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int y = C.y0 + C.r0 + r;
+        const float *row = L + (FDTD_R + C.r0 + r) * G::LW + FDTD_R + 2 * C.lane;
+        const float2 cen = q[slot(0)][r];
+        const float2 pm4 = *(const float2 *)(row - 4), pm2 = *(const float2 *)(row - 2);
+        const float2 pp2 = *(const float2 *)(row + 2), pp4 = *(const float2 *)(row + 4);
+        float2 ylo[4], yhi[4], zlo[4], zhi[4];
+#pragma unroll
+        for (int l = 1; l <= 4; ++l) {
+            ylo[l - 1] = r - l >= 0 ? q[slot(0)][r - l >= 0 ? r - l : 0] : *(const float2 *)(row - l * G::LW);
+            yhi[l - 1] = r + l < RY ? q[slot(0)][r + l < RY ? r + l : 0] : *(const float2 *)(row + l * G::LW);
+            zlo[l - 1] = q[slot(-l)][r];
+            zhi[l - 1] = q[slot(l)][r];
+        }
+        float yl[4], yh[4], zl[4], zh[4];
+        // column 0 of the pair
+        const float xl0[4] = {pm2.y, pm2.x, pm4.y, pm4.x}, xh0[4] = {cen.y, pp2.x, pp2.y, pp4.x};
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            yl[l] = ylo[l].x;
+            yh[l] = yhi[l].x;
+            zl[l] = zlo[l].x;
+            zh[l] = zhi[l].x;
+        }
+        const float lt0 = lap_interior(C.K, cen.x, xl0, xh0, yl, yh, zl, zh);
+        // column 1
+        const float xl1[4] = {cen.x, pm2.y, pm2.x, pm4.y}, xh1[4] = {pp2.x, pp2.y, pp4.x, pp4.y};
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            yl[l] = ylo[l].y;
+            yh[l] = yhi[l].y;
+            zl[l] = zlo[l].y;
+            zh[l] = zhi[l].y;
+        }
+        const float lt1 = lap_interior(C.K, cen.y, xl1, xh1, yl, yh, zl, zh);
+        const bool srow = srcplane && wrap_ghost(s, 1, y) == C.sy;
+        const Upd u0 = time_update<T>(C.mc[r].x, lt0, cen.x, C.umc[r].x, srow && C.x == C.sx, C.src);
+        const Upd u1 = time_update<T>(C.mc[r].y, lt1, cen.y, C.umc[r].y, srow && C.x + 1 == C.sx, C.src);
+        // (a masked point's store takes an out-of-range offset)
+        const uint32_t so0 = zm2_ok(C, C.x, y, z) ? C.offs[r] : kBufSkip;
+        const uint32_t so1 = zm2_ok(C, C.x + 1, y, z) ? C.offs[r] + (uint32_t)sizeof(T) : kBufSkip;
+        Buf<T>::st(C.rw, so0, s0, u0.u);
+        Buf<T>::st(C.rw, so1, s0, u1.u);
+        if constexpr (IsInc<T>::v) {
+            Buf<T>::st(C.rs, so0, s0, u0.d);
+            Buf<T>::st(C.rs, so1, s0, u1.d);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        C.umc[r] = C.um1[r];
+        C.um1[r] = umn[r];
+        C.mc[r] = C.m1[r];
+        C.m1[r] = mn[r];
+    }
+}
+
+template <typename T, int NW, int RY>
+__global__ __launch_bounds__(64 * NW) void k_zmarch2(const DevShot *__restrict__ shots,
+                                                     const WorkItem *__restrict__ work, Roles R, int zchunk,
+                                                     const int *__restrict__ stepc) {
+    using G = ZM2<NW, RY>;
+    __shared__ float sm[2 * G::LB];
+    const WorkItem wi = work[blockIdx.x];
+    const DevShot &s = shots[wi.shot];
+    const int ext = R.ext;
+    const Box bx = shot_box(s, ext);
+    ZCtx2<T, NW, RY> C;
+    const int x0 = wi.tx * 128;
+    C.y0 = bx.ylo + wi.ty * G::TY;
+    if (C.y0 >= bx.yhi) return;
+    const int zb = bx.zlo + wi.zc * zchunk;
+    if (zb >= bx.zhi) return;
+    const int ze = min(zb + zchunk, bx.zhi);
+    const int n3[3] = {s.nx, s.ny, s.nz};
+    band_box(n3, s.Llo, s.Lhi, s.ghost, ext, 6, C.nlo, C.nhi);
+    const int fx1 = min(x0 + 128, s.nx), fy1 = min(C.y0 + G::TY, bx.yhi);
+    if (x0 >= C.nhi[0] || fx1 <= C.nlo[0] || C.y0 >= C.nhi[1] || fy1 <= C.nlo[1]) return;
+
+    const bool boxz = R.lo[2] < R.hi[2] && R.lo[2] < ze && R.hi[2] > zb;
+    const bool ovxy = x0 < R.hi[0] && fx1 > R.lo[0] && C.y0 < R.hi[1] && fy1 > R.lo[1];
+    const bool inxy = x0 >= R.lo[0] && fx1 <= R.hi[0] && C.y0 >= R.lo[1] && fy1 <= R.hi[1];
+    int seg_a[2] = {zb, 0}, seg_b[2] = {ze, 0};
+    int nseg = 1;
+    C.partial = false;
+    if (boxz && ovxy) {
+        if (inxy) {
+            seg_b[0] = min(ze, R.lo[2]);
+            seg_a[1] = max(zb, R.hi[2]);
+            seg_b[1] = ze;
+            nseg = 2;
+        } else {
+            C.partial = true;
+        }
+    }
+    for (int sg = 0; sg < nseg; ++sg) {
+        seg_a[sg] = max(seg_a[sg], C.nlo[2]);
+        seg_b[sg] = min(seg_b[sg], C.nhi[2]);
+    }
+    C.full = !C.partial && x0 >= C.nlo[0] && x0 + 128 <= C.nhi[0] && C.y0 >= C.nlo[1] && C.y0 + G::TY <= C.nhi[1];
+
+    C.K = load_coef(s);
+    const long P = s.P, esz = sizeof(T);
+    const long lead = (long)s.fy * P + FDTD_R;     // elements before (x = -4, y = -fy) within a plane
+    C.Sb = (uint32_t)((long)s.S * esz);
+    C.Smb = (uint32_t)((long)s.S * 4);
+    C.u = (const char *)s.u[R.iu] - lead * esz;
+    C.w = (char *)s.u[R.iout] - lead * esz;
+    C.sec = (char *)(IsInc<T>::v ? s.dinc : s.u[R.ium1]) - lead * esz;
+    C.m = (const char *)s.m - lead * 4;
+    C.R = &R;
+    C.lane = threadIdx.x & 63;
+    C.r0 = (threadIdx.x >> 6) * RY;
+    C.x = x0 + 2 * C.lane;
+    C.sx = s.sx;
+    C.sy = s.sy;
+    C.sz = s.sz;
+    {
+        bool iny = false;
+        for (int o = -1; o <= 1; ++o) {
+            if (o != 0 && !s.ghost[1]) continue;
+            const int yy = s.sy + o * s.ny;
+            iny = iny || (yy >= C.y0 && yy < C.y0 + G::TY);
+        }
+        C.src_tile = s.wav != nullptr && s.sx >= x0 && s.sx < x0 + 128 && iny;
+    }
+    // a pair is loaded when either of its points needs the value
+    auto need = [&](int hx, int hy, int m) {
+        return hx + 1 >= C.nlo[0] - m && hx < C.nhi[0] + m && hy >= C.nlo[1] - m && hy < C.nhi[1] + m;
+    };
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int y = C.y0 + C.r0 + r;
+        const long e = (long)(y + s.fy) * P + C.x + FDTD_R;
+        C.off[r] = need(C.x, y, FDTD_R) ? (uint32_t)(e * esz) : kBufSkip;
+        C.offs[r] = need(C.x, y, 0) ? (uint32_t)(e * esz) : kBufSkip;
+        C.offm[r] = need(C.x, y, 0) ? (uint32_t)(e * 4) : kBufSkip;
+    }
+    // halo pairs: 0 .. 4 TY - 1 the x halo (row i / 4: pairs at columns -4, -2 and
+    // 128, 130 of the tile), then 8 rows of 64 pairs (4 above, 4 below the tile)
+#pragma unroll
+    for (int k = 0; k < G::HS; ++k) {
+        const int i = threadIdx.x + G::NT * k;
+        C.hslot[k] = G::LH * G::LW;     // dummy pair
+        C.hoff[k] = kBufSkip;
+        if (i < G::NHX) {
+            const int row = i >> 2, k4 = i & 3;
+            const int col = k4 < 2 ? 2 * k4 : 128 + 2 * k4;     // LDS column
+            C.hslot[k] = (FDTD_R + row) * G::LW + col;
+            const int hx = x0 - FDTD_R + col, hy = C.y0 + row;
+            if (need(hx, hy, FDTD_R)) C.hoff[k] = (uint32_t)(((long)(hy + s.fy) * P + hx + FDTD_R) * esz);
+        } else if (i < G::NH) {
+            const int j = i - G::NHX, r8 = j >> 6, c = j & 63;
+            const int lrow = r8 < FDTD_R ? r8 : G::TY + r8;
+            C.hslot[k] = lrow * G::LW + FDTD_R + 2 * c;
+            const int hx = x0 + 2 * c, hy = C.y0 - FDTD_R + lrow;
+            if (need(hx, hy, FDTD_R)) C.hoff[k] = (uint32_t)(((long)(hy + s.fy) * P + hx + FDTD_R) * esz);
+        }
+    }
+    C.src = source_at(s, *stepc);
+
+    float2 q[ZQ][RY], hq[ZQ][G::HS];
+    int it = 0;
+    for (int sg = 0; sg < nseg; ++sg) {
+        const int a = seg_a[sg], b = seg_b[sg];
+        if (a >= b) continue;
+        C.zlast = b + FDTD_R - 1;
+        {
+            const Rsrc ru = make_rsrc(C.u + (long)(a - 4) * C.Sb);
+#pragma unroll
+            for (int o = -4; o < 6; ++o)
+#pragma unroll
+                for (int r = 0; r < RY; ++r)
+                    q[o + 4][r] = Buf2<T>::ld(ru, C.off[r], (uint32_t)(min(a + o, C.zlast) - a + 4) * C.Sb);
+            const Rsrc rs = make_rsrc(C.sec + (long)a * C.Sb);
+            const Rsrc rm = make_rsrc(C.m + (long)a * C.Smb);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                q[ZQ - 1][r] = make_float2(0.0f, 0.0f);
+                C.umc[r] = Buf2<T>::ld(rs, C.offs[r], 0);
+                C.mc[r] = Buf2<float>::ld(rm, C.offm[r], 0);
+                C.um1[r] = Buf2<T>::ld(rs, C.offs[r], C.Sb);
+                C.m1[r] = Buf2<float>::ld(rm, C.offm[r], C.Smb);
+            }
+#pragma unroll
+            for (int o = 0; o < 6; ++o)
+#pragma unroll
+                for (int k = 0; k < G::HS; ++k)
+                    hq[o + 4][k] = Buf2<T>::ld(ru, C.hoff[k], (uint32_t)(min(a + o, C.zlast) - a + 4) * C.Sb);
+        }
+        for (int z0 = a; z0 < b; z0 += ZQ) {
+            C.ru = make_rsrc(C.u + (long)z0 * C.Sb);
+            C.rs = make_rsrc(C.sec + (long)z0 * C.Sb);
+            C.rm = make_rsrc(C.m + (long)z0 * C.Smb);
+            C.rw = make_rsrc(C.w + (long)z0 * C.Sb);
+            const int n = b - z0;
+#define ZSTEP2(PH)                                                                \
+    if (n > PH) {                                                                 \
+        zbody2<T, NW, RY, PH>(C, s, q, hq, sm + (it & 1) * G::LB, z0 + PH);       \
+        ++it;                                                                     \
+    }
+            ZSTEP2(0) ZSTEP2(1) ZSTEP2(2) ZSTEP2(3) ZSTEP2(4) ZSTEP2(5)
+            ZSTEP2(6) ZSTEP2(7) ZSTEP2(8) ZSTEP2(9) ZSTEP2(10)
+#undef ZSTEP2
         }
     }
 }
@@ -472,9 +759,24 @@ static void launch_naive_t(const DevShot *d_shots, int shot, int nx, int Ny, int
     hipLaunchKernelGGL(k_update_naive<T>, grid, dim3(64, 4), 0, st, d_shots, shot, R, stepc);
 }
 template <typename T>
-static void launch_zmarch_t(const DevShot *d_shots, const WorkItem *work, int nwork, int ry, const Roles &R,
+static void launch_zmarch_t(const DevShot *d_shots, const WorkItem *work, int nwork, int ry, int cols, const Roles &R,
                             int zchunk, const int *stepc, hipStream_t st) {
     if (nwork <= 0) return;
+    if (cols == 2) {
+        // plan rows ry = 1, 2, 4: tiles of 128 x 8 ry points; (waves, rows per thread) = (4, 2), (8, 2), (16, 2)
+        switch (ry) {
+        case 1:
+            hipLaunchKernelGGL((k_zmarch2<T, 4, 2>), dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_zmarch2<T, 16, 2>), dim3(nwork), dim3(1024), 0, st, d_shots, work, R, zchunk, stepc);
+            break;
+        default:
+            hipLaunchKernelGGL((k_zmarch2<T, 8, 2>), dim3(nwork), dim3(512), 0, st, d_shots, work, R, zchunk, stepc);
+            break;
+        }
+        return;
+    }
     // plan rows ry = 1, 2, 4, 8: tiles of 64 x 8 ry points; (waves, rows per thread)
     // = (4, 2), (4, 4), (8, 4), (16, 4)
     switch (ry) {
@@ -515,9 +817,9 @@ void fdtd_launch_naive(int stor, const DevShot *d_shots, int shot, int nx, int N
                        const int *stepc, hipStream_t st) {
     FDTD_DISPATCH(stor, launch_naive_t, d_shots, shot, nx, Ny, Nz, R, stepc, st);
 }
-void fdtd_launch_zmarch(int stor, const DevShot *d_shots, const WorkItem *work, int nwork, int ry, const Roles &R,
-                        int zchunk, const int *stepc, hipStream_t st) {
-    FDTD_DISPATCH(stor, launch_zmarch_t, d_shots, work, nwork, ry, R, zchunk, stepc, st);
+void fdtd_launch_zmarch(int stor, const DevShot *d_shots, const WorkItem *work, int nwork, int ry, int cols,
+                        const Roles &R, int zchunk, const int *stepc, hipStream_t st) {
+    FDTD_DISPATCH(stor, launch_zmarch_t, d_shots, work, nwork, ry, cols, R, zchunk, stepc, st);
 }
 void fdtd_launch_record(int stor, const DevShot *d_shots, int nshots, const Roles &R, int *stepc, hipStream_t st) {
     FDTD_DISPATCH(stor, launch_record_t, d_shots, nshots, R, stepc, st);

@@ -137,16 +137,32 @@ class Propagator:
         check(self.L.fdtd_set_field(self.ctx, shot, which, _ptr(f)), self.ctx)
         self.stream.synchronize()
 
+    def save_state(self) -> torch.Tensor:
+        """The full state of every shot and the step count, as an opaque device blob."""
+        nb = ctypes.c_size_t()
+        check(self.L.fdtd_state_size(self.ctx, ctypes.byref(nb)), self.ctx)
+        blob = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        check(self.L.fdtd_save_state(self.ctx, ctypes.c_void_p(blob.data_ptr()), int(nb.value)), self.ctx)
+        return blob
+
+    def load_state(self, blob: torch.Tensor) -> None:
+        """Restore a blob from save_state of a context with the same shot configurations."""
+        assert blob.is_cuda and blob.dtype == torch.uint8 and blob.is_contiguous()
+        check(self.L.fdtd_load_state(self.ctx, ctypes.c_void_p(blob.data_ptr()), int(blob.numel())), self.ctx)
+
     def check_finite(self) -> None:
         check(self.L.fdtd_check_finite(self.ctx), self.ctx)
 
-    def set_plan(self, shot: int, variant: int, tile_ry: int = 2, zchunk: int = 64, tblock_k: int = 1) -> None:
-        check(self.L.fdtd_set_plan(self.ctx, shot, variant, tile_ry, zchunk, tblock_k), self.ctx)
+    def set_plan(self, shot: int, variant: int, tile_ry: int = 2, zchunk: int = 64, tblock_k: int = 1,
+                 tile_cols: int = 1) -> None:
+        check(self.L.fdtd_set_plan(self.ctx, shot, variant, tile_ry, zchunk, tblock_k, tile_cols), self.ctx)
 
     def plan(self, shot: int = 0):
-        v, ry, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        check(self.L.fdtd_get_plan(self.ctx, shot, ctypes.byref(v), ctypes.byref(ry), ctypes.byref(k)), self.ctx)
-        return int(v.value), int(ry.value), int(k.value)
+        """(variant, tile_ry, tblock_k, tile_cols) of one shot."""
+        v, ry, k, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(self.L.fdtd_get_plan(self.ctx, shot, ctypes.byref(v), ctypes.byref(ry), ctypes.byref(k), ctypes.byref(c)),
+              self.ctx)
+        return int(v.value), int(ry.value), int(k.value), int(c.value)
 
     def scale(self, shot: int = 0) -> float:
         s = ctypes.c_double()

@@ -119,7 +119,7 @@ def test_default_plan_tile_shape(n, face, s, ry):
     L, rc, ctx = _create([_cfg(n=n, cpml=cp, face=face, exchange_every=s)])
     assert rc == 0
     v, r, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    assert L.fdtd_get_plan(ctx, 0, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k)) == 0
+    assert L.fdtd_get_plan(ctx, 0, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k), None) == 0
     assert (v.value, r.value, k.value) == (2, ry, 1)
     L.fdtd_destroy(ctx)
 
@@ -135,7 +135,7 @@ def test_auto_variant(cfgs, variants):
     assert rc == 0
     for i, want in enumerate(variants):
         v, r, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        assert L.fdtd_get_plan(ctx, i, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k)) == 0
+        assert L.fdtd_get_plan(ctx, i, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k), None) == 0
         assert v.value == want
     L.fdtd_destroy(ctx)
 
@@ -149,12 +149,12 @@ def test_batch_default_plan():
     assert rc == 0
     v, r, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     for i in range(len(shapes)):
-        assert L.fdtd_get_plan(ctx, i, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k)) == 0
+        assert L.fdtd_get_plan(ctx, i, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k), None) == 0
         assert (v.value, r.value) == (2, 1)
     L.fdtd_destroy(ctx)
     L, rc, ctx = _create([_cfg(n=(512, 512, 256), cpml=(20,) * 6)] * 2)
     assert rc == 0
-    assert L.fdtd_get_plan(ctx, 0, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k)) == 0
+    assert L.fdtd_get_plan(ctx, 0, ctypes.byref(v), ctypes.byref(r), ctypes.byref(k), None) == 0
     assert r.value != 1
     L.fdtd_destroy(ctx)
 

@@ -42,5 +42,7 @@ def test_measured_traffic_needs_matching_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic((8, 8, 8), (2, 2, 1)) == 10 * 1024 * 2 + 5 * 1024
     assert bench.measured_traffic((8, 8, 9), (2, 2, 1)) is None
     assert bench.measured_traffic((8, 8, 8), (2, 1, 1)) is None
+    assert bench.measured_traffic((8, 8, 8), (2, 2, 1, 2)) is None      # counters of one-column tiles
+    assert bench.measured_traffic((8, 8, 8), (2, 2, 1, 1)) == 10 * 1024 * 2 + 5 * 1024
     f.write_text(f.read_text().replace(bench.sources_digest(), "0" * 64))
     assert bench.measured_traffic((8, 8, 8), (2, 2, 1)) is None

@@ -67,6 +67,8 @@ def _run(indices, variants, graph=False, autotune=False, plans=None, tmp_path=No
     if autotune:
         p.autotune(str(tmp_path / "tune.json"))
         p.reset()
+        print("autotuned plans (variant, tile_ry, tblock_k, tile_cols):", [p.plan(k) for k in range(len(shots))],
+              flush=True)
     p.step(NT, graph=graph)
     torch.cuda.synchronize()
     out = [(trs[k].cpu().numpy().copy(), p.get_field(k).cpu().numpy().copy()) for k in range(len(shots))]

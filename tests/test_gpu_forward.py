@@ -114,13 +114,42 @@ def test_cases_match_oracle_and_variants_agree(name):
     assert np.array_equal(z[0], n[0]) and np.array_equal(z[1], n[1]) and np.array_equal(z[2], n[2])
 
 
-@pytest.mark.parametrize("ry,zc", [(1, 16), (2, 32), (4, 64), (1, 128), (4, 16), (2, 4096), (8, 32), (8, 4096)])
-def test_zmarch_plans_bitwise_equal_naive(ry, zc):
-    """Every tile height / z-chunk plan gives the naive kernel's bits (several
-    x/y tiles with ragged tails, several z chunks, source inside a layer)."""
+@pytest.mark.parametrize("ry,zc,cols", [(1, 16, 1), (2, 32, 1), (4, 64, 1), (1, 128, 1), (4, 16, 1), (2, 4096, 1),
+                                        (8, 32, 1), (8, 4096, 1), (1, 16, 2), (2, 32, 2), (4, 64, 2), (2, 4096, 2),
+                                        (1, 4096, 2)])
+def test_zmarch_plans_bitwise_equal_naive(ry, zc, cols):
+    """Every tile shape (64 or 128 wide: one or two x points per lane) and
+    z-chunk plan gives the naive kernel's bits (several x/y tiles with ragged
+    tails, several z chunks, source inside a layer)."""
     w = _ragged((100, 70, 150), (10.0, 10.0, 10.0), (10,) * 6, 30, 2, src=(6, 35, 75))
     a = run_gpu(w, variant=NAIVE)
-    b = run_gpu(w, plan=(ZMARCH, ry, zc, 1))
+    b = run_gpu(w, plan=(ZMARCH, ry, zc, 1, cols))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+
+
+def test_variant_switched_by_plan():
+    """A context created for one variant and switched to the other by
+    fdtd_set_plan (naive <-> z-march: whether the band kernel advances the x
+    and z layer memory itself changes with it) gives that variant's bits."""
+    w = _ragged((70, 45, 38), (10.0, 12.0, 9.0), (5, 7, 3, 6, 8, 4), 40, 1)
+    naive = run_gpu(w, variant=NAIVE)
+    zm = run_gpu(w, variant=ZMARCH)
+    to_naive = run_gpu(w, variant=ZMARCH, plan=(NAIVE, 2, 64, 1, 1))
+    to_zm = run_gpu(w, variant=NAIVE, plan=(ZMARCH, 4, 64, 1, 1))
+    for got in (to_naive, to_zm):
+        assert np.array_equal(got[0], naive[0]) and np.array_equal(got[2], naive[2])
+    assert np.array_equal(zm[2], naive[2])
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+@pytest.mark.parametrize("name", ["ragged", "xcut", "zchunks"])
+def test_two_column_plan_16bit_bitwise(storage, name):
+    """16-bit storage: the two-column z-march (4-byte pair loads) gives the
+    one-column kernel's bits."""
+    c = dict(CASES[name])
+    w = _ragged(c.pop("n"), c.pop("h"), c.pop("cpml"), c.pop("nt"), c.pop("seed"), src=c.pop("src", None))
+    a = run_gpu(w, plan=(ZMARCH, 2, 64, 1, 1), storage=storage)
+    b = run_gpu(w, plan=(ZMARCH, 2, 64, 1, 2), storage=storage)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
 
 

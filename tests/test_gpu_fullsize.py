@@ -36,12 +36,14 @@ def _state(shape_zyx, seed):
     return u, um1
 
 
-def _run_gpu_state(n, h, dt, cpml, v, u0, um1, nt, **shot_kw):
+def _run_gpu_state(n, h, dt, cpml, v, u0, um1, nt, plan=None, **shot_kw):
     import torch
 
     from paper_2606_06910_amd import Propagator, Shot
 
     p = Propagator([Shot(n=n, h=h, dt=dt, cpml=cpml, **shot_kw)])
+    if plan is not None:
+        p.set_plan(0, *plan)
     p.set_velocity(0, torch.from_numpy(v.astype(np.float32)).cuda())
     p.set_field(0, 0, torch.from_numpy(u0).cuda())
     p.set_field(0, 1, torch.from_numpy(um1).cuda())
@@ -119,6 +121,17 @@ def test_pencil_state_in_layers_matches_periodic_oracle(pencil_case, pencil_s1, 
     masks, union = band_masks(w.n, w.cpml)
     _check("pencil s=%d u^n" % s, un, ru, masks, union)
     _check("pencil s=%d u^{n-1}" % s, unm1, rum1, masks, union)
+
+
+def test_two_column_plan_full_size_state_in_layers():
+    """The two-column z-march (128-wide tiles) at 512^3 from a noise state:
+    the default plan's bits after 8 steps."""
+    w = synth.layered(n_xyz=(512, 512, 512), nt=8)
+    u0, um1 = _state(w.v.shape, 2027)
+    a = _run_gpu_state(w.n, w.h, w.dt, w.cpml, w.v, u0, um1, 8)
+    b = _run_gpu_state(w.n, w.h, w.dt, w.cpml, w.v, u0, um1, 8, plan=(2, 2, 4096, 1, 2))
+    assert b[2][3] == 2 and a[2][3] == 1, (a[2], b[2])
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
 @pytest.mark.parametrize("K", [2, 4])
