@@ -259,6 +259,44 @@ const char *fdtd_strerror(int status);
 const char *fdtd_last_error(const fdtd_ctx *ctx);
 void fdtd_destroy(fdtd_ctx *ctx);
 
+/* Size of the device array that holds the state of fdtd_forward_static. */
+#define FDTD_STATIC_BYTES ((size_t)256 << 20)
+
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): one complete forward run of one shot,
+ * equivalent to fdtd_create + fdtd_bind_workspace + fdtd_set_velocity +
+ * fdtd_inject_source + fdtd_set_receivers + fdtd_record_receivers +
+ * fdtd_step(nt) + fdtd_get_field + fdtd_destroy, with the same kernels and
+ * the same results bit for bit, except that the context's workspace is a
+ * fixed array of FDTD_STATIC_BYTES (256 MiB) compiled into the library
+ * instead of caller memory.  Each GPU the library runs on holds its own copy
+ * of that array from the library's first use on it until the process ends.
+ * The call allocates no device memory (no hipMalloc, no allocating library
+ * routine; host bookkeeping only) and creates no stream: everything runs on
+ * hip_stream, and the call synchronises that stream before it returns (it
+ * cannot be captured into a graph).
+ *   shot         the shot's configuration, as for fdtd_create (one shot).
+ *   v_dev        float32 [nz][ny][nx] velocity (m/s), as for fdtd_set_velocity.
+ *   src_i/j/k, wavelet_dev, nt, amplitude
+ *                point source as for fdtd_inject_source; wavelet_dev may be
+ *                NULL (no source).  nt is also the number of steps run.
+ *   rec_ijk_dev  int32 [nrec][3] receiver nodes (device), nrec >= 0.
+ *   traces_dev   float32 [nt][nrec] (device): row n receives u^{n+1} at the
+ *                receivers (required when nrec > 0).
+ *   u_final_dev  float32 [nz][ny][nx] (device) receiving u^{nt}, or NULL.
+ * Errors: those of the calls it stands for (EINVAL, EUNSTABLE, ...), and
+ * FDTD_ENOMEM when the shot's workspace (fdtd_workspace_size of the same
+ * configuration) exceeds FDTD_STATIC_BYTES, e.g. FP32 grids above about
+ * 250^3 points, checked before any GPU work; the reason is printed to stderr.
+ * Every call on one GPU shares that GPU's array and overwrites what the
+ * previous call left there (everything that must start at zero is cleared on
+ * entry): calls that overlap on one GPU, from several host threads or on
+ * several streams, race and must be serialised by the caller. */
+int fdtd_forward_static(const fdtd_shot_config *shot, const float *v_dev, int32_t src_i, int32_t src_j,
+                        int32_t src_k, const float *wavelet_dev, int32_t nt, float amplitude,
+                        const int32_t *rec_ijk_dev, int32_t nrec, float *traces_dev, float *u_final_dev,
+                        void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

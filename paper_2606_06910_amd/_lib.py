@@ -114,6 +114,9 @@ _SIGS = {
     "fdtd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fdtd_last_error": (ctypes.c_char_p, [_P]),
     "fdtd_destroy": (None, [_P]),
+    "fdtd_forward_static": (ctypes.c_int, [ctypes.POINTER(ShotConfig), _P, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_float, _P, ctypes.c_int32,
+                                           _P, _P, _P]),
     # first-order pressure-velocity path (include/fdtd_pv.h)
     "fdtd_pv_create": (ctypes.c_int, [ctypes.POINTER(PVConfig), _P, ctypes.POINTER(_P)]),
     "fdtd_pv_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdtd.so")
 SOURCES = ["fdtd_api.hip", "kernels_step.hip", "kernels_misc.hip", "adjoint.hip", "autotune.hip", "kernels_tblock.hip",
-           "kernels_band.hip", "pv_api.hip"]
+           "kernels_band.hip", "pv_api.hip", "static_api.hip"]
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",

@@ -1079,7 +1079,7 @@ static int zero_state(fdtd_ctx *ctx) {
 
 int fdtd_bind_workspace(fdtd_ctx *ctx, void *dev_ptr, size_t bytes) {
     if (!ctx || !dev_ptr) return FDTD_EINVAL;
-    if (!ctx->side) {
+    if (!ctx->side && !ctx->single_stream) {
         HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
         HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
         HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));

@@ -74,6 +74,7 @@ struct fdtd_ctx {
     hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
     hipStream_t side = nullptr;         // second stream: interior update concurrent with psi + band
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool single_stream = false;         // never create the side stream (everything on `stream`)
     char *ws = nullptr;
     size_t ws_bytes = 0, need = 0;
     size_t o_stepc = 0, o_scratch = 0, o_desc = 0, o_work_all = 0, o_band_all = 0;
