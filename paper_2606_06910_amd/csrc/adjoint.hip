@@ -9,9 +9,16 @@
 //   lambda^n = 2 lambda^{n+1} - lambda^{n+2}
 //            + sum_d [ D2_d(kinv E_d) - D1_d(dkinv E_d) - D1_d(F_d) ]
 // (D2 symmetric, D1 antisymmetric; outside band d the axis term is D2_d Lbar).
-// The residual at the receivers is added to lambda^{n+1} first.  The model
-// enters only through m = v^2 dt^2 multiplying (Lt u^n + f^n) = (u^{n+1} - 2u^n
-// + u^{n-1}) / m, so dJ/dv = (2/v) sum_n lambda^{n+1} (u^{n+1} - 2u^n + u^{n-1}),
+// The sweep runs on mu^n = m lambda^n, which is Lbar itself one step later:
+//   mu^n = 2 mu^{n+1} - mu^{n+2} + m sum_d [ D2_d(K_d) - D1_d(W_d) ],
+//   K_d = kinv E_d in the slab and mu^{n+1} elsewhere (kinv = 1, E_d = Lbar in
+//   the rest of the band), W_d = dkinv E_d + F_d in the slab and 0 elsewhere.
+// Away from every band this is the forward leapfrog applied to mu (D2 is
+// symmetric).  The residual at the receivers enters lambda^{n+1}, i.e. m times
+// it enters mu^{n+1}, first.  The model enters only through m = v^2 dt^2
+// multiplying (Lt u^n + f^n) = (u^{n+1} - 2u^n + u^{n-1}) / m, so
+// dJ/dv = (2/v) sum_n lambda^{n+1} (u^{n+1} - 2u^n + u^{n-1})
+//       = 2 dt / (m sqrt(m)) sum_n mu^{n+1} (u^{n+1} - 2u^n + u^{n-1}),
 // accumulated in FP64.  Forward levels are recomputed per segment from
 // checkpoints saved every `every` steps.
 #include "fdtd_host.hpp"
@@ -27,153 +34,126 @@
 
 struct AdjArgs {
     const DevShot *s;        // forward descriptor (geometry, m, profiles, coefficients)
-    float *lam;              // lambda^{n+1}   (origin-adjusted, FP32, forward layout)
-    float *lamp;             // lambda^{n+2} in, lambda^n out
+    float *mu1;              // mu^{n+1} = m lambda^{n+1}  (origin-adjusted, FP32, forward layout)
+    float *mu2;              // mu^{n+2} in, mu^n out
     float *psib[3], *zetab[3];          // compact slab layouts (as psi)
-    float *E[3];             // origin-adjusted FP32 fields (band points; zero elsewhere)
-    float *F[3];             // origin-adjusted FP32 fields (slab points; zero elsewhere)
-    const int *band[3];      // band coordinates per axis
-    int nband[3];
-    const void *um, *u0, *up;   // forward u^{n-1}, u^n, u^{n+1} (storage type)
-    float *Lb;               // Lbar = m lambda^{n+1} at every grid point (origin-adjusted; zero in the frame)
-    double *G;               // dense accumulator sum lambda * (u^{n+1} - 2u^n + u^{n-1})
+    float *E[3];             // origin-adjusted full-grid arrays, written at slab points of axis d only:
+    float *K[3];             //   E_d, kinv E_d and W_d = dkinv E_d + a (psi_b - D1_d E_d);
+    float *W[3];             //   W_d stays zero elsewhere
+    const float *um, *u0, *up;   // forward u^{n-1}, u^n, u^{n+1} (FP32)
+    double *G;               // dense accumulator sum mu^{n+1} (u^{n+1} - 2u^n + u^{n-1})
 };
 
 __device__ __forceinline__ long fidx(const DevShot &s, int x, int y, int z) {
     return (long)z * s.S + (long)y * s.P + x;
 }
 
-// residual injection: one thread per distinct receiver location, adding the
-// residuals of the receivers there in receiver order (repeated receivers add
-// up, with the rounding of a serial pass over the receivers).  gstart[g] ..
-// gstart[g + 1] index ridx, the receivers of location g.
-__global__ __launch_bounds__(256) void k_adj_resid(float *lam, const DevShot *sp, const float *resid_row,
+// residual injection: one thread per distinct receiver location; the residuals
+// of the receivers there are summed in receiver order (repeated receivers add
+// up) and m times the sum enters mu^{n+1}.  gstart[g] .. gstart[g + 1] index
+// ridx, the receivers of location g.
+__global__ __launch_bounds__(256) void k_adj_resid(float *mu, const DevShot *sp, const float *resid_row,
                                                    const int *gstart, const int *ridx, int ngroups) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ngroups) return;
     const DevShot &s = *sp;
     const int k0 = gstart[g], k1 = gstart[g + 1];
     const int32_t *q = s.rec + 3 * ridx[k0];
-    float *l = lam + fidx(s, q[0], q[1], q[2]);
-    float v = *l;
-    for (int k = k0; k < k1; ++k) v += resid_row[ridx[k]];
-    *l = v;
+    const long i = fidx(s, q[0], q[1], q[2]);
+    float r = 0.0f;
+    for (int k = k0; k < k1; ++k) r += resid_row[ridx[k]];
+    mu[i] = fmaf(s.m[i], r, mu[i]);
 }
 
-// Lbar = m lambda^{n+1} once per point, so that the passes below read it
-// instead of forming it at every stencil tap (the same product, so the same bits)
-__global__ __launch_bounds__(256) void k_adj_lbar(AdjArgs a) {
-    const DevShot &s = *a.s;
-    const int x = blockIdx.x * 256 + threadIdx.x;
-    if (x >= s.nx) return;
-    const long i = fidx(s, x, (int)blockIdx.y, (int)blockIdx.z);
-    a.Lb[i] = s.m[i] * a.lam[i];
-}
-
-// pass 1 on band points of axis d = blockIdx.y: E_d and the zeta adjoint
-__global__ __launch_bounds__(256) void k_adj_p1(AdjArgs a) {
-    const DevShot &s = *a.s;
-    const int d = (int)blockIdx.y;
-    const int nb = a.nband[d];
-    if (nb == 0) return;
-    const int n1 = d == 0 ? s.ny : s.nx;          // the two other axes, fastest first
-    const int n2 = d == 2 ? s.ny : s.nz;
-    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    long total = (long)nb * n1 * n2;
-    if (t >= total) return;
-    int x, y, z, c;
-    if (d == 0) {
-        c = a.band[0][t % nb];
-        long r = t / nb;
-        x = c;
-        y = (int)(r % n1);
-        z = (int)(r / n1);
-    } else if (d == 1) {
-        x = (int)(t % n1);
-        long r = t / n1;
-        c = a.band[1][r % nb];
-        y = c;
-        z = (int)(r / nb);
-    } else {
-        x = (int)(t % n1);
-        long r = t / n1;
-        y = (int)(r % n2);
-        c = a.band[2][r / n2];
-        z = c;
-    }
-    const long i = fidx(s, x, y, z);
-    const float lb = a.Lb[i];
-    const int n = coord_n(s, d);
-    float e = lb;
-    if (in_slab(c, n, s.Llo[d], s.Lhi[d])) {
-        float *zb = &a.zetab[d][psi_index(s, d, x, y, z)];
-        const float zt = *zb + lb;
-        e = fmaf(prof_at(s, d, 2, c), lb, prof_at(s, d, 1, c) * zt);
-        *zb = prof_at(s, d, 0, c) * zt;
-    }
-    a.E[d][i] = e;
-}
-
-// pass 2 on slab points of axis d = blockIdx.y: psi adjoint and F_d = a (psi_b - D1 E_d)
-__global__ __launch_bounds__(256) void k_adj_p2(AdjArgs a) {
-    const DevShot &s = *a.s;
-    const int d = (int)blockIdx.y;
+// slab point t of axis d: its coordinates and its coordinate along d
+__device__ __forceinline__ bool slab_point(const DevShot &s, int d, long t, int &x, int &y, int &z, int &k) {
     const int lo = s.Llo[d], hi = s.Lhi[d];
-    if (lo + hi == 0) return;
+    if (lo + hi == 0) return false;
     long count;
     if (d == 0) count = (long)s.LX * s.ny * s.nz;
     else if (d == 1) count = (long)s.nx * s.LY * s.nz;
     else count = (long)s.nx * s.ny * s.LZ;
-    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count) return;
-    int x, y, z, k;
+    if (t >= count) return false;
     if (d == 0) {
-        int is = (int)(t % s.LX);
-        long r = t / s.LX;
+        const int is = (int)(t % s.LX);
+        const long r = t / s.LX;
         y = (int)(r % s.ny);
         z = (int)(r / s.ny);
         x = is < lo ? is : s.nx - hi + (is - lo);
         k = x;
     } else if (d == 1) {
         x = (int)(t % s.nx);
-        long r = t / s.nx;
-        int js = (int)(r % s.LY);
+        const long r = t / s.nx;
+        const int js = (int)(r % s.LY);
         z = (int)(r / s.LY);
         y = js < lo ? js : s.ny - hi + (js - lo);
         k = y;
     } else {
         x = (int)(t % s.nx);
-        long r = t / s.nx;
+        const long r = t / s.nx;
         y = (int)(r % s.ny);
-        int ks = (int)(r / s.ny);
+        const int ks = (int)(r / s.ny);
         z = ks < lo ? ks : s.nz - hi + (ks - lo);
         k = z;
     }
+    return true;
+}
+
+// whether coordinate c (possibly outside [0, n)) lies in a slab of the axis
+__device__ __forceinline__ bool slab_in_grid(int c, int n, int lo, int hi) {
+    return c >= 0 && c < n && in_slab(c, n, lo, hi);
+}
+
+// pass 1 on slab points of axis d = blockIdx.y: the zeta adjoint, E_d and K_d
+__global__ __launch_bounds__(256) void k_adj_p1(AdjArgs a) {
+    const DevShot &s = *a.s;
+    const int d = (int)blockIdx.y;
+    int x, y, z, k;
+    if (!slab_point(s, d, (long)blockIdx.x * blockDim.x + threadIdx.x, x, y, z, k)) return;
+    const long i = fidx(s, x, y, z);
+    const float lb = a.mu1[i];
+    float *zb = &a.zetab[d][psi_index(s, d, x, y, z)];
+    const float kinv = prof_at(s, d, 2, k);
+    const float zt = *zb + lb;
+    const float e = fmaf(kinv, lb, prof_at(s, d, 1, k) * zt);
+    *zb = prof_at(s, d, 0, k) * zt;
+    a.E[d][i] = e;
+    a.K[d][i] = kinv * e;
+}
+
+// pass 2 on slab points of axis d = blockIdx.y: the psi adjoint and
+// W_d = dkinv E_d + a (psi_b - D1_d E_d), E_d being Lbar at the taps outside the slab
+__global__ __launch_bounds__(256) void k_adj_p2(AdjArgs a) {
+    const DevShot &s = *a.s;
+    const int d = (int)blockIdx.y;
+    int x, y, z, k;
+    if (!slab_point(s, d, (long)blockIdx.x * blockDim.x + threadIdx.x, x, y, z, k)) return;
+    const int n = coord_n(s, d), lo = s.Llo[d], hi = s.Lhi[d];
     const long i = fidx(s, x, y, z);
     const long stride = d == 0 ? 1 : (d == 1 ? s.P : s.S);
+    const float *E = a.E[d];
     float el[4], eh[4];
 #pragma unroll
     for (int l = 1; l <= 4; ++l) {
-        el[l - 1] = a.E[d][i - l * stride];
-        eh[l - 1] = a.E[d][i + l * stride];
+        const float *pl = slab_in_grid(k - l, n, lo, hi) ? E : a.mu1;
+        const float *ph = slab_in_grid(k + l, n, lo, hi) ? E : a.mu1;
+        el[l - 1] = pl[i - l * stride];
+        eh[l - 1] = ph[i + l * stride];
     }
     const long pi = psi_index(s, d, x, y, z);
     const float pt = a.psib[d][pi] - d1_axis(s.w1[d], el, eh);
-    a.F[d][i] = prof_at(s, d, 1, k) * pt;
+    a.W[d][i] = fmaf(prof_at(s, d, 3, k), E[i], prof_at(s, d, 1, k) * pt);
     a.psib[d][pi] = prof_at(s, d, 0, k) * pt;
 }
 
-// Pass 3 on every point: lambda^n and the gradient accumulation.  Along an
-// axis d whose band the wave does not touch, the axis term is D2_d Lbar.  A
-// wave that touches it evaluates the band form for all its lanes:
-//   D2_d(K) - D1_d(dkinv E_d) - D1_d(F_d),  K = kinv E_d in the band, Lbar outside,
-// with dkinv E_d and F_d zero outside the slab and every field zero outside
-// the grid.  At a lane outside the band this is D2_d Lbar with the same bits
-// (kinv = 1 and E_d = Lbar in the band outside the slab; the D1 terms are
-// exact zeros), so the per-lane branch is not needed.  A wave is one y row of
-// 64 x points (blockDim = 64 x 4), so the y and z tests are wave-uniform and
-// the x test is taken per 64-point tile.
-template <typename T>
+// Pass 3 on every point: mu^n and the gradient accumulation.  Along an axis d
+// whose band the wave does not touch, the axis term is D2_d mu^{n+1}.  A wave
+// that touches it evaluates D2_d(K_d) - D1_d(W_d) for all its lanes, taking
+// K_d from its array at slab taps and mu^{n+1} at the others.  At a lane
+// outside the band no tap lies in the slab, so this is D2_d mu^{n+1} with the
+// same bits (the W_d taps are exact zeros).  A wave is one y row of 64 x
+// points (blockDim = 64 x 4), so the y and z tests are wave-uniform and the x
+// test is taken per 64-point tile.
 __global__ __launch_bounds__(256) void k_adj_p3(AdjArgs a, float inv_scale) {
     const DevShot &s = *a.s;
     const int x0 = blockIdx.x * 64;
@@ -188,62 +168,52 @@ __global__ __launch_bounds__(256) void k_adj_p3(AdjArgs a, float inv_scale) {
     // the band of an axis is an interval at each end of the grid, so a tile meets it iff one of its end points lies in it
     const bool touch[3] = {in_band(x0, s.nx, s.Llo[0], s.Lhi[0]) || in_band(xe, s.nx, s.Llo[0], s.Lhi[0]),
                            in_band(y, s.ny, s.Llo[1], s.Lhi[1]), in_band(z, s.nz, s.Llo[2], s.Lhi[2])};
-    float acc = fmaf(2.0f, a.lam[i], -a.lamp[i]);
+    const float c = a.mu1[i];
+    float t[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const int n = coord_n(s, d);
-        const int c = cc[d];
-        float t;
+        float lo[4], hi[4];
         if (!touch[d]) {
-            float lo[4], hi[4];
 #pragma unroll
             for (int l = 1; l <= 4; ++l) {
-                lo[l - 1] = a.Lb[i - l * st[d]];
-                hi[l - 1] = a.Lb[i + l * st[d]];
+                lo[l - 1] = a.mu1[i - l * st[d]];
+                hi[l - 1] = a.mu1[i + l * st[d]];
             }
-            t = d2_axis(s.w2[d], a.Lb[i], lo, hi);
+            t[d] = d2_axis(s.w2[d], c, lo, hi);
         } else {
-            const int lo_ = s.Llo[d], hi_ = s.Lhi[d];
-            const float *pk = s.prof + (d * 4 + 2) * s.nmax, *pdk = s.prof + (d * 4 + 3) * s.nmax;
-            const float *E = a.E[d], *F = a.F[d];
-            // one tap at coordinate cq along d, element j: K and dkinv E_d
-            auto tap = [&](int cq, long j, float &kv, float &dv) {
-                const float e = E[j], lb = a.Lb[j];
-                const int cl = min(max(cq, 0), n - 1);
-                const bool ing = cq >= 0 && cq < n;
-                kv = ing && in_band(cq, n, lo_, hi_) ? pk[cl] * e : (ing ? lb : 0.0f);
-                dv = ing && in_slab(cq, n, lo_, hi_) ? pdk[cl] * e : 0.0f;
-            };
-            float kl[4], kh[4], dl[4], dh[4], fl[4], fh[4], kc, dc;
-            tap(c, i, kc, dc);
+            const int n = coord_n(s, d), Llo = s.Llo[d], Lhi = s.Lhi[d];
+            const int k = cc[d];
+            const float *Kd = a.K[d], *Wd = a.W[d];
+            float wl[4], wh[4];
+            const float kc = (slab_in_grid(k, n, Llo, Lhi) ? Kd : a.mu1)[i];
 #pragma unroll
             for (int l = 1; l <= 4; ++l) {
                 const long im = i - l * st[d], ip = i + l * st[d];
-                tap(c - l, im, kl[l - 1], dl[l - 1]);
-                tap(c + l, ip, kh[l - 1], dh[l - 1]);
-                fl[l - 1] = F[im];
-                fh[l - 1] = F[ip];
+                lo[l - 1] = (slab_in_grid(k - l, n, Llo, Lhi) ? Kd : a.mu1)[im];
+                hi[l - 1] = (slab_in_grid(k + l, n, Llo, Lhi) ? Kd : a.mu1)[ip];
+                wl[l - 1] = Wd[im];
+                wh[l - 1] = Wd[ip];
             }
-            t = d2_axis(s.w2[d], kc, kl, kh) - d1_axis(s.w1[d], dl, dh) - d1_axis(s.w1[d], fl, fh);
+            t[d] = d2_axis(s.w2[d], kc, lo, hi) - d1_axis(s.w1[d], wl, wh);
         }
-        acc = acc + t;
     }
-    // gradient: lambda^{n+1} (u^{n+1} - 2 u^n + u^{n-1})
-    const double d2u = ((double)Store<T>::ld((const T *)a.up + i) - 2.0 * (double)Store<T>::ld((const T *)a.u0 + i) +
-                        (double)Store<T>::ld((const T *)a.um + i)) * (double)inv_scale;
+    const float out = leapfrog(s.m[i], (t[0] + t[1]) + t[2], c, a.mu2[i]);
+    // gradient: mu^{n+1} (u^{n+1} - 2 u^n + u^{n-1})
+    const double d2u = (((double)a.up[i] - 2.0 * (double)a.u0[i]) + (double)a.um[i]) * (double)inv_scale;
     const long gi = ((long)z * s.ny + y) * s.nx + x;
-    a.G[gi] += (double)a.lam[i] * d2u;
-    a.lamp[i] = acc;
+    a.G[gi] += (double)c * d2u;
+    a.mu2[i] = out;
 }
 
-// dJ/dv = 2 G dt / sqrt(m)  (v = sqrt(m) / dt)
+// dJ/dv = 2 G dt / (m sqrt(m))  (G sums mu = m lambda; v = sqrt(m) / dt)
 __global__ __launch_bounds__(256) void k_adj_finish(const DevShot *sp, double *G, double dt) {
     const DevShot &s = *sp;
     const int x = blockIdx.x * 256 + threadIdx.x;
     if (x >= s.nx) return;
     const int y = blockIdx.y, z = blockIdx.z;
     const long gi = ((long)z * s.ny + y) * s.nx + x;
-    G[gi] = 2.0 * G[gi] * dt / sqrt((double)s.m[fidx(s, x, y, z)]);
+    const double m = (double)s.m[fidx(s, x, y, z)];
+    G[gi] = 2.0 * G[gi] * dt / (m * sqrt(m));
 }
 
 __global__ __launch_bounds__(256) void k_zero_f64(double *p, long n) {
@@ -272,21 +242,11 @@ static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 namespace {
 struct AdjLayout {
-    size_t ck = 0, seg = 0, lam = 0, lamp = 0, psib[3] = {}, zetab[3] = {}, F[3] = {}, E[3] = {}, band[3] = {};
+    size_t ck = 0, seg = 0, mu1 = 0, mu2 = 0, psib[3] = {}, zetab[3] = {}, E[3] = {}, K[3] = {}, W[3] = {};
     size_t gstart = 0, ridx = 0;   // receivers grouped by location (k_adj_resid)
-    size_t lb = 0;                 // Lbar field
     size_t total = 0;
     int nck = 0;
 };
-
-static std::vector<int> band_coords(const ShotH &s, int d) {
-    const int n = d == 0 ? s.nx : (d == 1 ? s.ny : s.nz);
-    const int lo = s.Llo[d], hi = s.Lhi[d];
-    std::vector<int> v;
-    for (int c = 0; c < n; ++c)
-        if ((lo > 0 && c < lo + FDTD_R) || (hi > 0 && c >= n - hi - FDTD_R)) v.push_back(c);
-    return v;
-}
 
 static AdjLayout adj_layout(const ShotH &s, int every, int nt) {
     AdjLayout L;
@@ -299,30 +259,32 @@ static AdjLayout adj_layout(const ShotH &s, int every, int nt) {
     L.nck = (nt + every - 1) / every;
     L.ck = take(fdtd_state_bytes(s) * (size_t)L.nck);
     L.seg = take(a256(s.elems * s.esz) * (size_t)(every + 2));
-    L.lam = take(s.elems * 4);
-    L.lamp = take(s.elems * 4);
+    L.mu1 = take(s.elems * 4);
+    L.mu2 = take(s.elems * 4);
     for (int d = 0; d < 3; ++d) {
+        const size_t full = (s.Llo[d] + s.Lhi[d]) > 0 ? s.elems * 4 : 0;
         L.psib[d] = take(s.psi_elems[d] * 4);
         L.zetab[d] = take(s.psi_elems[d] * 4);
-        L.F[d] = take((s.Llo[d] + s.Lhi[d]) > 0 ? s.elems * 4 : 0);
-        L.E[d] = take((s.Llo[d] + s.Lhi[d]) > 0 ? s.elems * 4 : 0);
-        L.band[d] = take((size_t)s.nmax * 4);
+        L.E[d] = take(full);
+        L.K[d] = take(full);
+        L.W[d] = take(full);
     }
-    L.lb = take(s.elems * 4);
     L.gstart = take((size_t)(s.nrec + 1) * 4);
     L.ridx = take((size_t)std::max(s.nrec, 1) * 4);
     L.total = off;
     return L;
 }
+
+// slab points of axis d (pass 1 and 2 launch one thread per point)
+static long slab_count(const ShotH &s, int d) {
+    if (s.Llo[d] + s.Lhi[d] == 0) return 0;
+    if (d == 0) return (long)s.LX * s.ny * s.nz;
+    if (d == 1) return (long)s.nx * s.LY * s.nz;
+    return (long)s.nx * s.ny * s.LZ;
+}
 }  // namespace
 
 static char *origin4(const ShotH &s, char *base) { return base + origin_elems(s) * 4; }
-static char *origin_t(const ShotH &s, char *base) { return base + origin_elems(s) * s.esz; }
-
-template <typename T>
-static void launch_p3(const AdjArgs &a, const ShotH &s, float inv, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_p3<T>, dim3((s.nx + 63) / 64, (s.ny + 3) / 4, s.nz), dim3(64, 4), 0, st, a, inv);
-}
 
 extern "C" {
 
@@ -386,33 +348,26 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
     AHIP(ctx, hipMemcpyAsync(dd + shot, &ctx->hdesc[shot], sizeof(DevShot), hipMemcpyHostToDevice, st));
     AHIP(ctx, hipStreamSynchronize(st));
 
-    // adjoint state to zero; band coordinate lists
-    fdtd_launch_fill_zero(B + L.lam, a256(s.elems * 4), st);
-    fdtd_launch_fill_zero(B + L.lamp, a256(s.elems * 4), st);
-    fdtd_launch_fill_zero(B + L.lb, a256(s.elems * 4), st);
+    // adjoint state to zero (W_d stays zero outside the slabs)
+    fdtd_launch_fill_zero(B + L.mu1, a256(s.elems * 4), st);
+    fdtd_launch_fill_zero(B + L.mu2, a256(s.elems * 4), st);
     AdjArgs a;
     memset(&a, 0, sizeof a);
     a.s = sp;
-    a.lam = (float *)origin4(s, B + L.lam);
-    a.lamp = (float *)origin4(s, B + L.lamp);
-    a.Lb = (float *)origin4(s, B + L.lb);
+    a.mu1 = (float *)origin4(s, B + L.mu1);
+    a.mu2 = (float *)origin4(s, B + L.mu2);
     for (int d = 0; d < 3; ++d) {
         fdtd_launch_fill_zero(B + L.psib[d], a256(s.psi_elems[d] * 4), st);
         fdtd_launch_fill_zero(B + L.zetab[d], a256(s.psi_elems[d] * 4), st);
         a.psib[d] = (float *)(B + L.psib[d]);
         a.zetab[d] = (float *)(B + L.zetab[d]);
         if (s.Llo[d] + s.Lhi[d] > 0) {
-            fdtd_launch_fill_zero(B + L.F[d], a256(s.elems * 4), st);
-            a.F[d] = (float *)origin4(s, B + L.F[d]);
-        }
-        std::vector<int> bc = band_coords(s, d);
-        a.nband[d] = (int)bc.size();
-        if (!bc.empty()) {
             fdtd_launch_fill_zero(B + L.E[d], a256(s.elems * 4), st);
+            fdtd_launch_fill_zero(B + L.K[d], a256(s.elems * 4), st);
+            fdtd_launch_fill_zero(B + L.W[d], a256(s.elems * 4), st);
             a.E[d] = (float *)origin4(s, B + L.E[d]);
-            AHIP(ctx, hipMemcpyAsync(B + L.band[d], bc.data(), bc.size() * 4, hipMemcpyHostToDevice, st));
-            AHIP(ctx, hipStreamSynchronize(st));
-            a.band[d] = (const int *)(B + L.band[d]);
+            a.K[d] = (float *)origin4(s, B + L.K[d]);
+            a.W[d] = (float *)origin4(s, B + L.W[d]);
         }
     }
     // receivers grouped by location, in first-appearance order; receiver order within a group
@@ -457,15 +412,9 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
     const int iu_in = ctx->iu, ium1_in = ctx->ium1;
     const bool was_saving = ctx->saving;
     ctx->saving = false;
-    // largest per-axis thread counts of passes 1 (band points) and 2 (slab points)
-    long p1_max = 0, p2_max = 0;
-    for (int d = 0; d < 3; ++d) {
-        const int n1 = d == 0 ? s.ny : s.nx, n2 = d == 2 ? s.ny : s.nz;
-        p1_max = std::max(p1_max, (long)a.nband[d] * n1 * n2);
-        if (s.Llo[d] + s.Lhi[d] > 0)
-            p2_max = std::max(p2_max, d == 0 ? (long)s.LX * s.ny * s.nz
-                                             : (d == 1 ? (long)s.nx * s.LY * s.nz : (long)s.nx * s.ny * s.LZ));
-    }
+    // largest per-axis thread count of passes 1 and 2 (slab points)
+    long slab_max = 0;
+    for (int d = 0; d < 3; ++d) slab_max = std::max(slab_max, slab_count(s, d));
     const int nck = (nt + every - 1) / every;
     const float inv_scale = (float)(1.0 / s.scale);
     int *stepc = (int *)fdtd_ws(ctx, ctx->o_stepc);
@@ -487,20 +436,18 @@ int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev
         // reverse sweep over the segment
         for (int n = s1 - 1; n >= s0; --n) {
             if (ngroups > 0)
-                hipLaunchKernelGGL(k_adj_resid, dim3((ngroups + 255) / 256), dim3(256), 0, st, a.lam, sp,
+                hipLaunchKernelGGL(k_adj_resid, dim3((ngroups + 255) / 256), dim3(256), 0, st, a.mu1, sp,
                                    resid_dev + (size_t)n * s.nrec, gstart_d, ridx_d, ngroups);
-            hipLaunchKernelGGL(k_adj_lbar, dim3((s.nx + 255) / 256, s.ny, s.nz), dim3(256), 0, st, a);
-            a.up = origin_t(s, seg + (size_t)(n - s0 + 2) * fb);
-            a.u0 = origin_t(s, seg + (size_t)(n - s0 + 1) * fb);
-            a.um = origin_t(s, seg + (size_t)(n - s0) * fb);
-            if (p1_max > 0)   // the three axes in one launch (disjoint outputs)
-                hipLaunchKernelGGL(k_adj_p1, dim3((unsigned)((p1_max + 255) / 256), 3), dim3(256), 0, st, a);
-            if (p2_max > 0)
-                hipLaunchKernelGGL(k_adj_p2, dim3((unsigned)((p2_max + 255) / 256), 3), dim3(256), 0, st, a);
-            if (ctx->storage == FDTD_F16) launch_p3<_Float16>(a, s, inv_scale, st);
-            else if (ctx->storage == FDTD_BF16) launch_p3<__bf16>(a, s, inv_scale, st);
-            else launch_p3<float>(a, s, inv_scale, st);
-            std::swap(a.lam, a.lamp);
+            a.up = (const float *)origin4(s, seg + (size_t)(n - s0 + 2) * fb);
+            a.u0 = (const float *)origin4(s, seg + (size_t)(n - s0 + 1) * fb);
+            a.um = (const float *)origin4(s, seg + (size_t)(n - s0) * fb);
+            if (slab_max > 0) {   // the three axes in one launch each (disjoint outputs)
+                hipLaunchKernelGGL(k_adj_p1, dim3((unsigned)((slab_max + 255) / 256), 3), dim3(256), 0, st, a);
+                hipLaunchKernelGGL(k_adj_p2, dim3((unsigned)((slab_max + 255) / 256), 3), dim3(256), 0, st, a);
+            }
+            hipLaunchKernelGGL(k_adj_p3, dim3((s.nx + 63) / 64, (s.ny + 3) / 4, s.nz), dim3(64, 4), 0, st, a,
+                               inv_scale);
+            std::swap(a.mu1, a.mu2);
         }
         AHIP(ctx, hipGetLastError());
     }
