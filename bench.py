@@ -371,7 +371,9 @@ def pencil_leg(K=100):
 def adjoint_leg(nshots=3, K=600, every=25):
     """Forward (with checkpoints every 25 steps) and adjoint (FP64 velocity
     gradient, segment recomputation) of the smallest shots of the 24-shot
-    workload: Mpts/s of each pass over the shots' points x steps."""
+    workload, advanced together in one batched context and swept back in one
+    batched reverse sweep; and the same shots one context at a time.  Mpts/s
+    of each pass over the shots' points x steps."""
     import numpy as np
     import torch
 
@@ -380,33 +382,45 @@ def adjoint_leg(nshots=3, K=600, every=25):
 
     shapes = synth.batch_shapes(24)
     order = sorted(range(len(shapes)), key=lambda i: np.prod(shapes[i]))[:nshots]
-    fwd_ms = adj_ms = 0.0
-    npts = 0
-    for i in order:
-        w, v0 = synth.batch_shot(i, shapes[i], nt=K)
-        p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, v_ref=float(w.v.max()))])
-        p.set_velocity(0, torch.from_numpy(v0.astype(np.float32)).cuda())
-        p.inject_source(0, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)).cuda())
-        p.set_receivers(0, w.rec)
-        p.set_checkpointing(0, every, K)
-        tr = p.record(0, K)
+    data = [synth.batch_shot(i, shapes[i], nt=K) for i in order]
+    npts = sum(w.npts for w, _ in data)
+
+    def run(group):
+        p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, v_ref=float(w.v.max())) for w, _ in group])
+        trs = []
+        for k, (w, v0) in enumerate(group):
+            p.set_velocity(k, torch.from_numpy(v0.astype(np.float32)).cuda())
+            p.inject_source(k, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)).cuda())
+            p.set_receivers(k, w.rec)
+            p.set_checkpointing(k, every, K)
+            trs.append(p.record(k, K))
         e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         e[0].record(p.stream)
         p.step(K)
         e[1].record(p.stream)
         torch.cuda.synchronize()
-        fwd_ms += e[0].elapsed_time(e[1])
-        resid = tr.clone()
+        resid = [t.clone() for t in trs]
         e[1].record(p.stream)
-        p.adjoint(0, K, resid)
+        if len(group) > 1:
+            p.adjoint_all(K, resid)
+        else:
+            p.adjoint(0, K, resid[0])
         e[2].record(p.stream)
         torch.cuda.synchronize()
-        adj_ms += e[1].elapsed_time(e[2])
-        npts += w.npts
         p.close()
+        return e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+
+    fwd_ms, adj_ms = run(data)
+    one_f = one_a = 0.0
+    for d in data:
+        f, a = run([d])
+        one_f += f
+        one_a += a
     return {"shots": [list(shapes[i]) for i in order], "steps": K, "checkpoint_every": every,
             "forward_with_checkpoints_mpts": round(npts * K / (fwd_ms / 1e3) / 1e6, 1),
-            "adjoint_mpts": round(npts * K / (adj_ms / 1e3) / 1e6, 1)}
+            "adjoint_mpts": round(npts * K / (adj_ms / 1e3) / 1e6, 1),
+            "one_context_per_shot": {"forward_with_checkpoints_mpts": round(npts * K / (one_f / 1e3) / 1e6, 1),
+                                     "adjoint_mpts": round(npts * K / (one_a / 1e3) / 1e6, 1)}}
 
 
 def batched_leg(K=600, nshots=24):
@@ -472,8 +486,9 @@ def batched_fwd_adj_leg(K=600, every=25, nshots=24):
     inversion models v0 = v_true (1 + 0.03 G) advance together in one batched
     context with the full state saved every 25 steps, the L2 misfit is formed,
     and every shot's FP64 velocity gradient comes from the adjoint (segments
-    recomputed from the checkpoints).  Mpts/s of the forward (with
-    checkpoints) and of the 24 gradients, over points x steps."""
+    recomputed from the checkpoints) in one batched reverse sweep.  Mpts/s of
+    the forward (with checkpoints) and of the 24 gradients, over points x
+    steps."""
     import numpy as np
     import torch
 
@@ -516,10 +531,9 @@ def batched_fwd_adj_leg(K=600, every=25, nshots=24):
     e[1].record(p.stream)
     torch.cuda.synchronize()
     misfit = 0.5 * sum(float(((t.double() - o.double()) ** 2).sum()) for t, o in zip(trs, obs))
-    grads = []
+    resid = [t - o for t, o in zip(trs, obs)]
     e[1].record(p.stream)
-    for k in range(nshots):
-        grads.append(p.adjoint(k, K, trs[k] - obs[k]))
+    grads = p.adjoint_all(K, resid)
     e[2].record(p.stream)
     torch.cuda.synchronize()
     fwd_ms, adj_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])

@@ -184,9 +184,9 @@ int fdtd_load_state(fdtd_ctx *ctx, const void *src_dev, size_t bytes);
 int fdtd_check_finite(fdtd_ctx *ctx);
 
 /* Size in bytes of the device buffer fdtd_adjoint needs for one shot with
- * checkpoints every `every` steps over nt steps (checkpoints, one segment of
- * recomputed levels, adjoint state, scratch, the receivers grouped by
- * location).  It depends on the shot's receiver count: set the receivers
+ * checkpoints every `every` steps over nt steps (checkpoints, two segments of
+ * recomputed levels, adjoint state, the receivers grouped by location, and
+ * the tables of a sweep over all shots of this context).  It depends on the shot's receiver count: set the receivers
  * first (fdtd_adjoint returns ENOMEM if they outgrew the buffer since). */
 int fdtd_adjoint_workspace_size(const fdtd_ctx *ctx, int32_t shot, int32_t every, int32_t nt, size_t *bytes);
 
@@ -204,6 +204,17 @@ int fdtd_set_checkpointing(fdtd_ctx *ctx, int32_t shot, int32_t every, void *buf
  * step count and the other shots' states are kept, so that after one batched
  * forward run every shot's adjoint can be taken in turn. */
 int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev, double *grad_v_dev);
+
+/* Model gradients of every shot of the context in one reverse sweep (the
+ * batched form of fdtd_adjoint: each pass of a reverse step is one launch over
+ * all shots, and the segments are recomputed by the batched forward step).
+ * resid_dev and grad_v_dev are host arrays of one device pointer per shot, in
+ * shot order, with fdtd_adjoint's layouts.  Every shot needs checkpointing
+ * registered with the same interval (EINVAL otherwise) and a buffer sized by
+ * fdtd_adjoint_workspace_size of this context.  Each gradient equals, bit for
+ * bit, the one fdtd_adjoint gives for that shot.  Leaves the forward states
+ * undefined; keeps the step count. */
+int fdtd_adjoint_batch(fdtd_ctx *ctx, int32_t nt, const float *const *resid_dev, double *const *grad_v_dev);
 
 /* Time candidate kernel shapes / temporal-block depths for every shot on
  * this device and keep the fastest per shape bucket; results are merged into

@@ -100,6 +100,8 @@ _SIGS = {
                                                    ctypes.POINTER(ctypes.c_size_t)]),
     "fdtd_set_checkpointing": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t]),
     "fdtd_adjoint": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "fdtd_adjoint_batch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.POINTER(ctypes.c_void_p)]),
     "fdtd_autotune": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "fdtd_set_plan": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_int32]),

@@ -20,7 +20,8 @@
 // dJ/dv = (2/v) sum_n lambda^{n+1} (u^{n+1} - 2u^n + u^{n-1})
 //       = 2 dt / (m sqrt(m)) sum_n mu^{n+1} (u^{n+1} - 2u^n + u^{n-1}),
 // accumulated in FP64.  Forward levels are recomputed per segment from
-// checkpoints saved every `every` steps.
+// checkpoints saved every `every` steps.  One sweep covers one shot or every
+// shot of the context: each pass is one launch over all of them.
 #include "fdtd_host.hpp"
 #include "fdtd_launch.hpp"
 
@@ -32,67 +33,92 @@
 #include <map>
 #include <vector>
 
-struct AdjArgs {
-    const DevShot *s;        // forward descriptor (geometry, m, profiles, coefficients)
-    float *mu1;              // mu^{n+1} = m lambda^{n+1}  (origin-adjusted, FP32, forward layout)
-    float *mu2;              // mu^{n+2} in, mu^n out
+// Adjoint state of one shot of a sweep (device array, one entry per shot).
+struct AdjShot {
+    DevShot s;               // the forward descriptor (geometry, m, profiles, coefficients)
+    float *mu[2];            // mu^{n+1} = mu[par], mu^{n+2} in / mu^n out = mu[par ^ 1] (origin-adjusted)
     float *psib[3], *zetab[3];          // compact slab layouts (as psi)
     float *E[3];             // origin-adjusted full-grid arrays, written at slab points of axis d only:
     float *K[3];             //   E_d, kinv E_d and W_d = dkinv E_d + a (psi_b - D1_d E_d);
     float *W[3];             //   W_d stays zero elsewhere
-    const float *um, *u0, *up;   // forward u^{n-1}, u^n, u^{n+1} (FP32)
+    const float *lev;        // recomputed forward levels (FP32, origin-adjusted slot 0 of half 0)
+    long lstride;            // elements between level slots
+    int nslot;               // slots per half: every + 2
+    float inv_scale;         // 1 / storage scale of the fields
     double *G;               // dense accumulator sum mu^{n+1} (u^{n+1} - 2u^n + u^{n-1})
+    const float *resid;      // dJ/dtraces [nt][nrec]
+    const int *gstart, *ridx;   // receivers grouped by location (k_adj_resid)
+    int ngroups, nrec;
+    int ubase, ucnt[3], uch[3];   // passes 1, 2: first wave unit, units and chunks per row of each axis
+    int bbase, btx, bty;          // pass 3: first block, tiles along x and y
+};
+// A wave of passes 1, 2 and a block of pass 3 find their shot in a table
+// indexed by wave or block (one scalar load), not by searching the shots.
+// one reverse step: mu^{n+1} = mu[par]; u^{n-1}, u^n, u^{n+1} in slots j, j+1, j+2 of half `half`
+struct AdjStep {
+    int par, half, j, n;
 };
 
 __device__ __forceinline__ long fidx(const DevShot &s, int x, int y, int z) {
     return (long)z * s.S + (long)y * s.P + x;
 }
 
-// residual injection: one thread per distinct receiver location; the residuals
-// of the receivers there are summed in receiver order (repeated receivers add
-// up) and m times the sum enters mu^{n+1}.  gstart[g] .. gstart[g + 1] index
-// ridx, the receivers of location g.
-__global__ __launch_bounds__(256) void k_adj_resid(float *mu, const DevShot *sp, const float *resid_row,
-                                                   const int *gstart, const int *ridx, int ngroups) {
+// residual injection: one thread per distinct receiver location of shot
+// blockIdx.y; the residuals of the receivers there are summed in receiver
+// order (repeated receivers add up) and m times the sum enters mu^{n+1}.
+// gstart[g] .. gstart[g + 1] index ridx, the receivers of location g.
+__global__ __launch_bounds__(256) void k_adj_resid(const AdjShot *__restrict__ A, AdjStep st) {
+    const AdjShot &a = A[blockIdx.y];
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ngroups) return;
-    const DevShot &s = *sp;
-    const int k0 = gstart[g], k1 = gstart[g + 1];
-    const int32_t *q = s.rec + 3 * ridx[k0];
+    if (g >= a.ngroups) return;
+    const DevShot &s = a.s;
+    const float *row = a.resid + (long)st.n * a.nrec;
+    const int k0 = a.gstart[g], k1 = a.gstart[g + 1];
+    const int32_t *q = s.rec + 3 * a.ridx[k0];
     const long i = fidx(s, q[0], q[1], q[2]);
     float r = 0.0f;
-    for (int k = k0; k < k1; ++k) r += resid_row[ridx[k]];
+    for (int k = k0; k < k1; ++k) r += row[a.ridx[k]];
+    float *mu = a.mu[st.par];
     mu[i] = fmaf(s.m[i], r, mu[i]);
 }
 
-// slab point t of axis d: its coordinates and its coordinate along d
-__device__ __forceinline__ bool slab_point(const DevShot &s, int d, long t, int &x, int &y, int &z, int &k) {
+// Passes 1 and 2 take one wave per unit: a run of up to 64 slab points of one
+// axis along x (the x slab points of one row, or 64 points of a y- or z-slab
+// row), so that the lanes read consecutive addresses.  Returns the lane's
+// shot, axis and point.
+__device__ __forceinline__ bool slab_unit(const AdjShot *__restrict__ A, const int *__restrict__ wave_shot, int nwave,
+                                          int &sh, int &d, int &x, int &y, int &z, int &k) {
+    const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    const int lane = (int)(threadIdx.x & 63);
+    if (w >= nwave) return false;
+    sh = wave_shot[w];
+    const AdjShot &a = A[sh];
+    int u = w - a.ubase;
+    d = 0;
+    while (d < 3 && u >= a.ucnt[d]) u -= a.ucnt[d++];
+    if (d == 3) return false;
+    const DevShot &s = a.s;
+    const int ch = u % a.uch[d], row = u / a.uch[d];
     const int lo = s.Llo[d], hi = s.Lhi[d];
-    if (lo + hi == 0) return false;
-    long count;
-    if (d == 0) count = (long)s.LX * s.ny * s.nz;
-    else if (d == 1) count = (long)s.nx * s.LY * s.nz;
-    else count = (long)s.nx * s.ny * s.LZ;
-    if (t >= count) return false;
     if (d == 0) {
-        const int is = (int)(t % s.LX);
-        const long r = t / s.LX;
-        y = (int)(r % s.ny);
-        z = (int)(r / s.ny);
+        const int is = ch * 64 + lane;
+        if (is >= s.LX) return false;
         x = is < lo ? is : s.nx - hi + (is - lo);
+        y = row % s.ny;
+        z = row / s.ny;
         k = x;
-    } else if (d == 1) {
-        x = (int)(t % s.nx);
-        const long r = t / s.nx;
-        const int js = (int)(r % s.LY);
-        z = (int)(r / s.LY);
+        return true;
+    }
+    x = ch * 64 + lane;
+    if (x >= s.nx) return false;
+    if (d == 1) {
+        const int js = row % s.LY;
+        z = row / s.LY;
         y = js < lo ? js : s.ny - hi + (js - lo);
         k = y;
     } else {
-        x = (int)(t % s.nx);
-        const long r = t / s.nx;
-        y = (int)(r % s.ny);
-        const int ks = (int)(r / s.ny);
+        y = row % s.ny;
+        const int ks = row / s.ny;
         z = ks < lo ? ks : s.nz - hi + (ks - lo);
         k = z;
     }
@@ -104,14 +130,15 @@ __device__ __forceinline__ bool slab_in_grid(int c, int n, int lo, int hi) {
     return c >= 0 && c < n && in_slab(c, n, lo, hi);
 }
 
-// pass 1 on slab points of axis d = blockIdx.y: the zeta adjoint, E_d and K_d
-__global__ __launch_bounds__(256) void k_adj_p1(AdjArgs a) {
-    const DevShot &s = *a.s;
-    const int d = (int)blockIdx.y;
-    int x, y, z, k;
-    if (!slab_point(s, d, (long)blockIdx.x * blockDim.x + threadIdx.x, x, y, z, k)) return;
+// pass 1 on slab points: the zeta adjoint, E_d and K_d
+__global__ __launch_bounds__(256) void k_adj_p1(const AdjShot *__restrict__ A, const int *__restrict__ wave_shot,
+                                                int nwave, AdjStep st) {
+    int sh, d, x, y, z, k;
+    if (!slab_unit(A, wave_shot, nwave, sh, d, x, y, z, k)) return;
+    const AdjShot &a = A[sh];
+    const DevShot &s = a.s;
     const long i = fidx(s, x, y, z);
-    const float lb = a.mu1[i];
+    const float lb = a.mu[st.par][i];
     float *zb = &a.zetab[d][psi_index(s, d, x, y, z)];
     const float kinv = prof_at(s, d, 2, k);
     const float zt = *zb + lb;
@@ -121,24 +148,23 @@ __global__ __launch_bounds__(256) void k_adj_p1(AdjArgs a) {
     a.K[d][i] = kinv * e;
 }
 
-// pass 2 on slab points of axis d = blockIdx.y: the psi adjoint and
-// W_d = dkinv E_d + a (psi_b - D1_d E_d), E_d being Lbar at the taps outside the slab
-__global__ __launch_bounds__(256) void k_adj_p2(AdjArgs a) {
-    const DevShot &s = *a.s;
-    const int d = (int)blockIdx.y;
-    int x, y, z, k;
-    if (!slab_point(s, d, (long)blockIdx.x * blockDim.x + threadIdx.x, x, y, z, k)) return;
+// pass 2 on slab points: the psi adjoint and W_d = dkinv E_d + a (psi_b - D1_d E_d),
+// E_d being Lbar = mu^{n+1} at the taps outside the slab
+__global__ __launch_bounds__(256) void k_adj_p2(const AdjShot *__restrict__ A, const int *__restrict__ wave_shot,
+                                                int nwave, AdjStep st) {
+    int sh, d, x, y, z, k;
+    if (!slab_unit(A, wave_shot, nwave, sh, d, x, y, z, k)) return;
+    const AdjShot &a = A[sh];
+    const DevShot &s = a.s;
     const int n = coord_n(s, d), lo = s.Llo[d], hi = s.Lhi[d];
     const long i = fidx(s, x, y, z);
     const long stride = d == 0 ? 1 : (d == 1 ? s.P : s.S);
-    const float *E = a.E[d];
+    const float *E = a.E[d], *mu1 = a.mu[st.par];
     float el[4], eh[4];
 #pragma unroll
     for (int l = 1; l <= 4; ++l) {
-        const float *pl = slab_in_grid(k - l, n, lo, hi) ? E : a.mu1;
-        const float *ph = slab_in_grid(k + l, n, lo, hi) ? E : a.mu1;
-        el[l - 1] = pl[i - l * stride];
-        eh[l - 1] = ph[i + l * stride];
+        el[l - 1] = (slab_in_grid(k - l, n, lo, hi) ? E : mu1)[i - l * stride];
+        eh[l - 1] = (slab_in_grid(k + l, n, lo, hi) ? E : mu1)[i + l * stride];
     }
     const long pi = psi_index(s, d, x, y, z);
     const float pt = a.psib[d][pi] - d1_axis(s.w1[d], el, eh);
@@ -146,29 +172,37 @@ __global__ __launch_bounds__(256) void k_adj_p2(AdjArgs a) {
     a.psib[d][pi] = prof_at(s, d, 0, k) * pt;
 }
 
-// Pass 3 on every point: mu^n and the gradient accumulation.  Along an axis d
+// Pass 3 on every point: mu^n and the gradient accumulation.  A block is a
+// 64 x 4 tile of one plane of one shot (one y row per wave).  Along an axis d
 // whose band the wave does not touch, the axis term is D2_d mu^{n+1}.  A wave
 // that touches it evaluates D2_d(K_d) - D1_d(W_d) for all its lanes, taking
 // K_d from its array at slab taps and mu^{n+1} at the others.  At a lane
 // outside the band no tap lies in the slab, so this is D2_d mu^{n+1} with the
-// same bits (the W_d taps are exact zeros).  A wave is one y row of 64 x
-// points (blockDim = 64 x 4), so the y and z tests are wave-uniform and the x
-// test is taken per 64-point tile.
-__global__ __launch_bounds__(256) void k_adj_p3(AdjArgs a, float inv_scale) {
-    const DevShot &s = *a.s;
-    const int x0 = blockIdx.x * 64;
-    const int x = x0 + threadIdx.x;
-    const int y = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * 4 + threadIdx.y));
-    const int z = blockIdx.z;
+// same bits (the W_d taps are exact zeros).  The y and z tests are
+// wave-uniform and the x test is taken per 64-point tile.
+__global__ __launch_bounds__(256) void k_adj_p3(const AdjShot *__restrict__ A, const int *__restrict__ block_shot,
+                                                AdjStep st) {
+    const int b = (int)blockIdx.x;
+    const AdjShot &a = A[block_shot[b]];
+    const DevShot &s = a.s;
+    const int lb = b - a.bbase, nxy = a.btx * a.bty;
+    const int z = lb / nxy, r = lb - z * nxy;
+    if (z >= s.nz) return;
+    const int by = r / a.btx, bx = r - by * a.btx;
+    const int x0 = bx * 64;
+    const int x = x0 + (int)(threadIdx.x & 63);
+    const int y = __builtin_amdgcn_readfirstlane(by * 4 + (int)(threadIdx.x >> 6));
     if (x >= s.nx || y >= s.ny) return;
     const int xe = min(x0 + 64, s.nx) - 1;   // last x of the tile
     const long i = fidx(s, x, y, z);
     const int cc[3] = {x, y, z};
-    const long st[3] = {1, (long)s.P, (long)s.S};
+    const long stv[3] = {1, (long)s.P, (long)s.S};
     // the band of an axis is an interval at each end of the grid, so a tile meets it iff one of its end points lies in it
     const bool touch[3] = {in_band(x0, s.nx, s.Llo[0], s.Lhi[0]) || in_band(xe, s.nx, s.Llo[0], s.Lhi[0]),
                            in_band(y, s.ny, s.Llo[1], s.Lhi[1]), in_band(z, s.nz, s.Llo[2], s.Lhi[2])};
-    const float c = a.mu1[i];
+    const float *mu1 = a.mu[st.par];
+    float *mu2 = a.mu[st.par ^ 1];
+    const float c = mu1[i];
     float t[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -176,8 +210,8 @@ __global__ __launch_bounds__(256) void k_adj_p3(AdjArgs a, float inv_scale) {
         if (!touch[d]) {
 #pragma unroll
             for (int l = 1; l <= 4; ++l) {
-                lo[l - 1] = a.mu1[i - l * st[d]];
-                hi[l - 1] = a.mu1[i + l * st[d]];
+                lo[l - 1] = mu1[i - l * stv[d]];
+                hi[l - 1] = mu1[i + l * stv[d]];
             }
             t[d] = d2_axis(s.w2[d], c, lo, hi);
         } else {
@@ -185,24 +219,26 @@ __global__ __launch_bounds__(256) void k_adj_p3(AdjArgs a, float inv_scale) {
             const int k = cc[d];
             const float *Kd = a.K[d], *Wd = a.W[d];
             float wl[4], wh[4];
-            const float kc = (slab_in_grid(k, n, Llo, Lhi) ? Kd : a.mu1)[i];
+            const float kc = (slab_in_grid(k, n, Llo, Lhi) ? Kd : mu1)[i];
 #pragma unroll
             for (int l = 1; l <= 4; ++l) {
-                const long im = i - l * st[d], ip = i + l * st[d];
-                lo[l - 1] = (slab_in_grid(k - l, n, Llo, Lhi) ? Kd : a.mu1)[im];
-                hi[l - 1] = (slab_in_grid(k + l, n, Llo, Lhi) ? Kd : a.mu1)[ip];
+                const long im = i - l * stv[d], ip = i + l * stv[d];
+                lo[l - 1] = (slab_in_grid(k - l, n, Llo, Lhi) ? Kd : mu1)[im];
+                hi[l - 1] = (slab_in_grid(k + l, n, Llo, Lhi) ? Kd : mu1)[ip];
                 wl[l - 1] = Wd[im];
                 wh[l - 1] = Wd[ip];
             }
             t[d] = d2_axis(s.w2[d], kc, lo, hi) - d1_axis(s.w1[d], wl, wh);
         }
     }
-    const float out = leapfrog(s.m[i], (t[0] + t[1]) + t[2], c, a.mu2[i]);
+    const float out = leapfrog(s.m[i], (t[0] + t[1]) + t[2], c, mu2[i]);
     // gradient: mu^{n+1} (u^{n+1} - 2 u^n + u^{n-1})
-    const double d2u = (((double)a.up[i] - 2.0 * (double)a.u0[i]) + (double)a.um[i]) * (double)inv_scale;
+    const float *um = a.lev + ((long)st.half * a.nslot + st.j) * a.lstride;
+    const float *u0 = um + a.lstride, *up = u0 + a.lstride;
+    const double d2u = (((double)up[i] - 2.0 * (double)u0[i]) + (double)um[i]) * (double)a.inv_scale;
     const long gi = ((long)z * s.ny + y) * s.nx + x;
     a.G[gi] += (double)c * d2u;
-    a.mu2[i] = out;
+    mu2[i] = out;
 }
 
 // dJ/dv = 2 G dt / (m sqrt(m))  (G sums mu = m lambda; v = sqrt(m) / dt)
@@ -241,14 +277,36 @@ static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
     } while (0)
 
 namespace {
+// waves of passes 1, 2 and blocks of pass 3 of one shot
+struct AdjCounts {
+    int uch[3], ucnt[3], btx, bty;
+    long waves() const { return (long)ucnt[0] + ucnt[1] + ucnt[2]; }
+    long blocks(const ShotH &s) const { return (long)btx * bty * s.nz; }
+};
+static AdjCounts adj_counts(const ShotH &s) {
+    AdjCounts c;
+    const int cx = (s.nx + 63) / 64;
+    c.uch[0] = (s.LX + 63) / 64;
+    c.uch[1] = c.uch[2] = cx;
+    c.ucnt[0] = s.LX > 0 ? s.ny * s.nz * c.uch[0] : 0;
+    c.ucnt[1] = s.LY > 0 ? s.LY * s.nz * cx : 0;
+    c.ucnt[2] = s.LZ > 0 ? s.ny * s.LZ * cx : 0;
+    c.btx = cx;
+    c.bty = (s.ny + 3) / 4;
+    return c;
+}
+
 struct AdjLayout {
-    size_t ck = 0, seg = 0, mu1 = 0, mu2 = 0, psib[3] = {}, zetab[3] = {}, E[3] = {}, K[3] = {}, W[3] = {};
+    size_t ck = 0, seg = 0, mu[2] = {}, psib[3] = {}, zetab[3] = {}, E[3] = {}, K[3] = {}, W[3] = {};
     size_t gstart = 0, ridx = 0;   // receivers grouped by location (k_adj_resid)
+    // tables of a sweep over every shot of the context (those of a sweep's first shot are used):
+    // AdjShot entries, level-copy jobs, checkpoint-restore jobs, wave -> shot and block -> shot maps
+    size_t tab = 0, jobs = 0, rjobs = 0, wmap = 0, bmap = 0;
     size_t total = 0;
     int nck = 0;
 };
 
-static AdjLayout adj_layout(const ShotH &s, int every, int nt) {
+static AdjLayout adj_layout(const fdtd_ctx *ctx, const ShotH &s, int every, int nt) {
     AdjLayout L;
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -256,11 +314,18 @@ static AdjLayout adj_layout(const ShotH &s, int every, int nt) {
         off += a256(b);
         return o;
     };
+    const size_t nctx = ctx->shots.size();
+    long waves = 0, blocks = 0;
+    for (const ShotH &t : ctx->shots) {
+        const AdjCounts c = adj_counts(t);
+        waves += c.waves();
+        blocks += c.blocks(t);
+    }
     L.nck = (nt + every - 1) / every;
     L.ck = take(fdtd_state_bytes(s) * (size_t)L.nck);
-    L.seg = take(a256(s.elems * s.esz) * (size_t)(every + 2));
-    L.mu1 = take(s.elems * 4);
-    L.mu2 = take(s.elems * 4);
+    L.seg = take(a256(s.elems * s.esz) * (size_t)(every + 2) * 2);
+    L.mu[0] = take(s.elems * 4);
+    L.mu[1] = take(s.elems * 4);
     for (int d = 0; d < 3; ++d) {
         const size_t full = (s.Llo[d] + s.Lhi[d]) > 0 ? s.elems * 4 : 0;
         L.psib[d] = take(s.psi_elems[d] * 4);
@@ -271,26 +336,301 @@ static AdjLayout adj_layout(const ShotH &s, int every, int nt) {
     }
     L.gstart = take((size_t)(s.nrec + 1) * 4);
     L.ridx = take((size_t)std::max(s.nrec, 1) * 4);
+    L.tab = take(sizeof(AdjShot) * nctx);
+    L.jobs = take(sizeof(CopyJob) * (size_t)(2 * (every + 2) * 2) * nctx);
+    L.rjobs = take(sizeof(CopyJob) * (size_t)L.nck * 2 * 8 * nctx);
+    L.wmap = take(sizeof(int) * (size_t)std::max(waves, 1L));
+    L.bmap = take(sizeof(int) * (size_t)std::max(blocks, 1L));
     L.total = off;
     return L;
 }
 
-// slab points of axis d (pass 1 and 2 launch one thread per point)
-static long slab_count(const ShotH &s, int d) {
-    if (s.Llo[d] + s.Lhi[d] == 0) return 0;
-    if (d == 0) return (long)s.LX * s.ny * s.nz;
-    if (d == 1) return (long)s.nx * s.LY * s.nz;
-    return (long)s.nx * s.ny * s.LZ;
+// A flat copy of `bytes` (a multiple of 256) as rows of 256 bytes, so that
+// k_copy_jobs spreads it over many blocks.
+static CopyJob flat_job(const void *src, void *dst, size_t bytes) {
+    CopyJob c;
+    c.src = src;
+    c.dst = dst;
+    c.esz = 4;
+    c.ex = 64;
+    c.ey = (int)(bytes / 256);
+    c.ez = 1;
+    c.sy = c.dy = 64;
+    c.sz = c.dz = (long)c.ey * 64;
+    fdtd_set_copy_vec(c);
+    return c;
 }
 }  // namespace
 
 static char *origin4(const ShotH &s, char *base) { return base + origin_elems(s) * 4; }
 
+// One reverse sweep over the shots sh (one shot, or every shot of the context).
+// The reverse sweep of segment k runs on the adjoint stream while the main
+// stream restores checkpoint k - 1 and recomputes its levels into the other
+// half of each level buffer: the two touch disjoint memory (the forward state
+// and one half, the adjoint state and the other half).  ev_adj[b] (ready): the
+// levels of half b are written; ev_adj[2 + b] (free): the sweep that read
+// half b is done.
+static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, const float *const *resid,
+                         double *const *grad) {
+    const int nsh = (int)sh.size(), nctx = (int)ctx->shots.size();
+    if (!ctx->ws) AFAIL(ctx, FDTD_ESTATE, "no workspace bound");
+    int every = 0;
+    for (int q = 0; q < nsh; ++q) {
+        const ShotH &s = ctx->shots[sh[q]];
+        if (!resid[q] || !grad[q]) return FDTD_EINVAL;
+        if (s.ck_every <= 0 || !s.ck_buf) AFAIL(ctx, FDTD_ESTATE, "checkpointing is not set for shot %d", sh[q]);
+        if (q == 0) every = s.ck_every;
+        else if (s.ck_every != every) AFAIL(ctx, FDTD_EINVAL, "the shots of one sweep need one checkpoint interval");
+        if (nt > s.ck_nt)
+            AFAIL(ctx, FDTD_ENOMEM, "shot %d: adjoint buffer holds checkpoints for %d steps, asked %d", sh[q], s.ck_nt,
+                  nt);
+        if (!s.vel_set) AFAIL(ctx, FDTD_ESTATE, "shot %d: no velocity model", sh[q]);
+        const AdjLayout L = adj_layout(ctx, s, every, nt);
+        if (L.total > s.ck_bytes)
+            AFAIL(ctx, FDTD_ENOMEM, "shot %d: adjoint buffer of %zu bytes, %zu needed (receivers set after sizing it?)",
+                  sh[q], s.ck_bytes, L.total);
+    }
+    if (ctx->step < nt) AFAIL(ctx, FDTD_ESTATE, "run the forward for %d steps first (at step %ld)", nt, ctx->step);
+    hipStream_t st = ctx->stream;
+    DevShot *dd = (DevShot *)fdtd_ws(ctx, ctx->o_desc);
+
+    // recomputation must not overwrite the recorded traces
+    std::vector<DevShot> saved(nsh);
+    for (int q = 0; q < nsh; ++q) {
+        saved[q] = ctx->hdesc[sh[q]];
+        ctx->hdesc[sh[q]].traces = nullptr;
+        ctx->hdesc[sh[q]].trace_cap = 0;
+        AHIP(ctx, hipMemcpyAsync(dd + sh[q], &ctx->hdesc[sh[q]], sizeof(DevShot), hipMemcpyHostToDevice, st));
+    }
+    AHIP(ctx, hipStreamSynchronize(st));
+
+    // adjoint state to zero (W_d stays zero outside the slabs), receiver
+    // groups, the AdjShot table, the wave and block maps, the level-copy and
+    // checkpoint-restore jobs
+    const int nck = (nt + every - 1) / every;
+    std::vector<AdjShot> tab(nsh);
+    std::vector<CopyJob> jobs((size_t)2 * (every + 2) * 2 * nsh), rjobs((size_t)nck * 2 * 8 * nsh);
+    std::vector<int> wmap, bmap;
+    int ubase = 0, bbase = 0, maxg = 0;
+    long maxrows = 0, maxck = 0;
+    for (int q = 0; q < nsh; ++q) {
+        const ShotH &s = ctx->shots[sh[q]];
+        const AdjLayout L = adj_layout(ctx, s, every, nt);
+        char *B = s.ck_buf;
+        AdjShot &a = tab[q];
+        memset(&a, 0, sizeof a);
+        a.s = ctx->hdesc[sh[q]];
+        for (int h = 0; h < 2; ++h) {
+            fdtd_launch_fill_zero(B + L.mu[h], a256(s.elems * 4), st);
+            a.mu[h] = (float *)origin4(s, B + L.mu[h]);
+        }
+        for (int d = 0; d < 3; ++d) {
+            fdtd_launch_fill_zero(B + L.psib[d], a256(s.psi_elems[d] * 4), st);
+            fdtd_launch_fill_zero(B + L.zetab[d], a256(s.psi_elems[d] * 4), st);
+            a.psib[d] = (float *)(B + L.psib[d]);
+            a.zetab[d] = (float *)(B + L.zetab[d]);
+            if (s.Llo[d] + s.Lhi[d] > 0) {
+                fdtd_launch_fill_zero(B + L.E[d], a256(s.elems * 4), st);
+                fdtd_launch_fill_zero(B + L.K[d], a256(s.elems * 4), st);
+                fdtd_launch_fill_zero(B + L.W[d], a256(s.elems * 4), st);
+                a.E[d] = (float *)origin4(s, B + L.E[d]);
+                a.K[d] = (float *)origin4(s, B + L.K[d]);
+                a.W[d] = (float *)origin4(s, B + L.W[d]);
+            }
+        }
+        const size_t fb = a256(s.elems * s.esz);
+        a.lev = (const float *)origin4(s, B + L.seg);
+        a.lstride = (long)(fb / 4);
+        a.nslot = every + 2;
+        a.inv_scale = (float)(1.0 / s.scale);
+        a.G = grad[q];
+        a.resid = resid[q];
+        a.nrec = s.nrec;
+        // receivers grouped by location, in first-appearance order; receiver order within a group
+        if (s.nrec > 0) {
+            std::vector<int32_t> h((size_t)s.nrec * 3);
+            AHIP(ctx, hipMemcpy(h.data(), s.rec, h.size() * 4, hipMemcpyDeviceToHost));
+            std::vector<int> gstart, ridx;
+            std::vector<std::vector<int>> members;
+            std::map<std::array<int32_t, 3>, int> where;
+            for (int r = 0; r < s.nrec; ++r) {
+                const std::array<int32_t, 3> key{h[3 * r], h[3 * r + 1], h[3 * r + 2]};
+                auto it = where.find(key);
+                if (it == where.end()) {
+                    where[key] = (int)members.size();
+                    members.push_back({r});
+                } else {
+                    members[it->second].push_back(r);
+                }
+            }
+            for (auto &m : members) {
+                gstart.push_back((int)ridx.size());
+                ridx.insert(ridx.end(), m.begin(), m.end());
+            }
+            gstart.push_back((int)ridx.size());
+            a.ngroups = (int)members.size();
+            AHIP(ctx, hipMemcpyAsync(B + L.gstart, gstart.data(), gstart.size() * 4, hipMemcpyHostToDevice, st));
+            AHIP(ctx, hipMemcpyAsync(B + L.ridx, ridx.data(), ridx.size() * 4, hipMemcpyHostToDevice, st));
+            AHIP(ctx, hipStreamSynchronize(st));
+        }
+        a.gstart = (const int *)(B + L.gstart);
+        a.ridx = (const int *)(B + L.ridx);
+        maxg = std::max(maxg, a.ngroups);
+        // wave units of passes 1, 2 and blocks of pass 3
+        const AdjCounts cnt = adj_counts(s);
+        for (int d = 0; d < 3; ++d) {
+            a.uch[d] = cnt.uch[d];
+            a.ucnt[d] = cnt.ucnt[d];
+        }
+        a.ubase = ubase;
+        ubase += (int)cnt.waves();
+        wmap.insert(wmap.end(), (size_t)cnt.waves(), q);
+        a.btx = cnt.btx;
+        a.bty = cnt.bty;
+        a.bbase = bbase;
+        bbase += (int)cnt.blocks(s);
+        bmap.insert(bmap.end(), (size_t)cnt.blocks(s), q);
+        // checkpoint restore of segment k with u^n going to level buffer iu: u^n,
+        // u^{n-1}, then psi_d and zeta_d of each axis, as the checkpoint stores them
+        for (int k = 0; k < nck; ++k)
+            for (int iu = 0; iu < 2; ++iu) {
+                const char *ck = B + L.ck + (size_t)k * fdtd_state_bytes(s);
+                char *dst[8] = {fdtd_ws(ctx, s.o_u[iu]), fdtd_ws(ctx, s.o_u[iu ^ 1])};
+                size_t len[8] = {a256(s.elems * s.esz), a256(s.elems * s.esz)};
+                for (int d = 0; d < 3; ++d) {
+                    dst[2 + 2 * d] = fdtd_ws(ctx, s.o_psi[d]);
+                    dst[3 + 2 * d] = fdtd_ws(ctx, s.o_zeta[d]);
+                    len[2 + 2 * d] = len[3 + 2 * d] = a256(s.psi_elems[d] * 4);
+                }
+                size_t off = 0;
+                for (int f = 0; f < 8; ++f) {
+                    CopyJob &c = rjobs[(((size_t)k * 2 + iu) * 8 + f) * nsh + q];
+                    c = flat_job(ck + off, dst[f], len[f]);
+                    maxck = std::max(maxck, (long)c.ey);
+                    off += len[f];
+                }
+            }
+        // level copies: the grid box of level buffer qb into slot j of half b
+        for (int b = 0; b < 2; ++b)
+            for (int j = 0; j < every + 2; ++j)
+                for (int qb = 0; qb < 2; ++qb) {
+                    CopyJob &c = jobs[((size_t)(b * (every + 2) + j) * 2 + qb) * nsh + q];
+                    c.src = fdtd_field_origin(ctx, s, s.o_u[qb]);
+                    c.dst = (char *)origin4(s, B + L.seg) + ((size_t)b * (every + 2) + j) * fb;
+                    c.esz = 4;
+                    c.ex = s.nx;
+                    c.ey = s.ny;
+                    c.ez = s.nz;
+                    c.sy = c.dy = s.P;
+                    c.sz = c.dz = s.S;
+                    fdtd_set_copy_vec(c);
+                }
+        maxrows = std::max(maxrows, (long)s.ny * s.nz);
+        hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)std::min<long>(((long)s.nx * s.ny * s.nz + 255) / 256, 65536)),
+                           dim3(256), 0, st, grad[q], (long)s.nx * s.ny * s.nz);
+    }
+    const ShotH &s0h = ctx->shots[sh[0]];
+    const AdjLayout L0 = adj_layout(ctx, s0h, every, nt);
+    const AdjShot *tab_d = (const AdjShot *)(s0h.ck_buf + L0.tab);
+    const CopyJob *jobs_d = (const CopyJob *)(s0h.ck_buf + L0.jobs);
+    const CopyJob *rjobs_d = (const CopyJob *)(s0h.ck_buf + L0.rjobs);
+    const int *wmap_d = (const int *)(s0h.ck_buf + L0.wmap), *bmap_d = (const int *)(s0h.ck_buf + L0.bmap);
+    AHIP(ctx, hipMemcpyAsync((void *)tab_d, tab.data(), sizeof(AdjShot) * nsh, hipMemcpyHostToDevice, st));
+    AHIP(ctx, hipMemcpyAsync((void *)jobs_d, jobs.data(), sizeof(CopyJob) * jobs.size(), hipMemcpyHostToDevice, st));
+    AHIP(ctx, hipMemcpyAsync((void *)rjobs_d, rjobs.data(), sizeof(CopyJob) * rjobs.size(), hipMemcpyHostToDevice,
+                             st));
+    if (!wmap.empty())
+        AHIP(ctx, hipMemcpyAsync((void *)wmap_d, wmap.data(), sizeof(int) * wmap.size(), hipMemcpyHostToDevice, st));
+    AHIP(ctx, hipMemcpyAsync((void *)bmap_d, bmap.data(), sizeof(int) * bmap.size(), hipMemcpyHostToDevice, st));
+    AHIP(ctx, hipStreamSynchronize(st));
+    auto copy_level = [&](int b, int j, int qb) {
+        fdtd_launch_copy_jobs(jobs_d + ((size_t)(b * (every + 2) + j) * 2 + qb) * nsh, nsh, maxrows, st);
+    };
+
+    // the context's step count and level roles, restored on exit: the other shots
+    // of the context keep their forward state
+    const long step_in = ctx->step;
+    const int iu_in = ctx->iu, ium1_in = ctx->ium1;
+    const bool was_saving = ctx->saving;
+    ctx->saving = false;
+    const int step_shot = nsh == nctx ? -1 : sh[0];
+    int *stepc = (int *)fdtd_ws(ctx, ctx->o_stepc);
+    hipStream_t sa = st;
+    if (!ctx->single_stream) {
+        if (!ctx->adj_stream) {
+            AHIP(ctx, hipStreamCreateWithFlags(&ctx->adj_stream, hipStreamNonBlocking));
+            for (auto &e : ctx->ev_adj) AHIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        }
+        sa = ctx->adj_stream;
+        AHIP(ctx, hipEventRecord(ctx->ev_adj[4], st));   // the set-up above, before any sweep
+        AHIP(ctx, hipStreamWaitEvent(sa, ctx->ev_adj[4], 0));
+    }
+    int par = 0;
+    for (int k = nck - 1; k >= 0; --k) {
+        const int s0 = k * every, s1 = std::min(s0 + every, nt);
+        const int b = k & 1;
+        if (sa != st && k + 2 <= nck - 1) AHIP(ctx, hipStreamWaitEvent(st, ctx->ev_adj[2 + b], 0));
+        // restore the states before step s0 (one copy launch for every shot), then
+        // recompute the segment's levels
+        fdtd_launch_copy_jobs(rjobs_d + ((size_t)k * 2 + ctx->iu) * 8 * nsh, 8 * nsh, maxck, st);
+        fdtd_launch_set_int(stepc, s0, st);
+        ctx->step = s0;
+        copy_level(b, 1, ctx->iu);
+        copy_level(b, 0, ctx->ium1);
+        for (int n = s0; n < s1; ++n) {
+            fdtd_enqueue_step_shot(ctx, step_shot);
+            copy_level(b, n - s0 + 2, ctx->iu);
+        }
+        if (sa != st) {
+            AHIP(ctx, hipEventRecord(ctx->ev_adj[b], st));
+            AHIP(ctx, hipStreamWaitEvent(sa, ctx->ev_adj[b], 0));
+        }
+        // reverse sweep over the segment
+        for (int n = s1 - 1; n >= s0; --n) {
+            const AdjStep as{par, b, n - s0, n};
+            if (maxg > 0) hipLaunchKernelGGL(k_adj_resid, dim3((maxg + 255) / 256, nsh), dim3(256), 0, sa, tab_d, as);
+            if (ubase > 0) {
+                hipLaunchKernelGGL(k_adj_p1, dim3((unsigned)((ubase + 3) / 4)), dim3(256), 0, sa, tab_d, wmap_d, ubase,
+                                   as);
+                hipLaunchKernelGGL(k_adj_p2, dim3((unsigned)((ubase + 3) / 4)), dim3(256), 0, sa, tab_d, wmap_d, ubase,
+                                   as);
+            }
+            hipLaunchKernelGGL(k_adj_p3, dim3((unsigned)bbase), dim3(256), 0, sa, tab_d, bmap_d, as);
+            par ^= 1;
+        }
+        if (sa != st) AHIP(ctx, hipEventRecord(ctx->ev_adj[2 + b], sa));
+        AHIP(ctx, hipGetLastError());
+    }
+    if (sa != st) {
+        AHIP(ctx, hipEventRecord(ctx->ev_adj[4], sa));
+        AHIP(ctx, hipStreamWaitEvent(st, ctx->ev_adj[4], 0));
+    }
+    for (int q = 0; q < nsh; ++q) {
+        const ShotH &s = ctx->shots[sh[q]];
+        hipLaunchKernelGGL(k_adj_finish, dim3((s.nx + 255) / 256, s.ny, s.nz), dim3(256), 0, st, dd + sh[q], grad[q],
+                           s.c.dt);
+    }
+    ctx->saving = was_saving;
+    ctx->step = step_in;
+    ctx->iu = iu_in;
+    ctx->ium1 = ium1_in;
+    fdtd_launch_set_int(stepc, (int)step_in, st);
+    fdtd_clear_graphs(ctx);
+    for (int q = 0; q < nsh; ++q) {
+        ctx->hdesc[sh[q]] = saved[q];
+        AHIP(ctx, hipMemcpyAsync(dd + sh[q], &ctx->hdesc[sh[q]], sizeof(DevShot), hipMemcpyHostToDevice, st));
+    }
+    AHIP(ctx, hipStreamSynchronize(st));
+    AHIP(ctx, hipGetLastError());
+    return FDTD_OK;
+}
+
 extern "C" {
 
 int fdtd_adjoint_workspace_size(const fdtd_ctx *ctx, int32_t shot, int32_t every, int32_t nt, size_t *bytes) {
     if (!ctx || !bytes || shot < 0 || shot >= (int)ctx->shots.size() || every <= 0 || nt <= 0) return FDTD_EINVAL;
-    *bytes = adj_layout(ctx->shots[shot], every, nt).total;
+    *bytes = adj_layout(ctx, ctx->shots[shot], every, nt).total;
     return FDTD_OK;
 }
 
@@ -312,7 +652,7 @@ int fdtd_set_checkpointing(fdtd_ctx *ctx, int32_t shot, int32_t every, void *buf
     if (((uintptr_t)buf_dev) & 255) AFAIL(ctx, FDTD_EINVAL, "adjoint buffer must be 256-byte aligned");
     // capacity: the largest nt this buffer holds checkpoints for
     int nck = 0;
-    while (adj_layout(s, every, (nck + 1) * every).total <= bytes && nck < (1 << 20)) ++nck;
+    while (adj_layout(ctx, s, every, (nck + 1) * every).total <= bytes && nck < (1 << 20)) ++nck;
     if (nck == 0) AFAIL(ctx, FDTD_ENOMEM, "adjoint buffer too small");
     s.ck_every = every;
     s.ck_count = nck;
@@ -325,145 +665,14 @@ int fdtd_set_checkpointing(fdtd_ctx *ctx, int32_t shot, int32_t every, void *buf
 int fdtd_adjoint(fdtd_ctx *ctx, int32_t shot, int32_t nt, const float *resid_dev, double *grad_v_dev) {
     if (!ctx || shot < 0 || shot >= (int)ctx->shots.size() || nt <= 0 || !resid_dev || !grad_v_dev)
         return FDTD_EINVAL;
-    if (!ctx->ws) AFAIL(ctx, FDTD_ESTATE, "no workspace bound");
-    ShotH &s = ctx->shots[shot];
-    if (s.ck_every <= 0 || !s.ck_buf) AFAIL(ctx, FDTD_ESTATE, "checkpointing is not set for shot %d", shot);
-    if (nt > s.ck_nt) AFAIL(ctx, FDTD_ENOMEM, "adjoint buffer holds checkpoints for %d steps, asked %d", s.ck_nt, nt);
-    if (ctx->step < nt) AFAIL(ctx, FDTD_ESTATE, "run the forward for %d steps first (at step %ld)", nt, ctx->step);
-    if (!s.vel_set) AFAIL(ctx, FDTD_ESTATE, "no velocity model");
-    const int every = s.ck_every;
-    AdjLayout L = adj_layout(s, every, nt);
-    if (L.total > s.ck_bytes)
-        AFAIL(ctx, FDTD_ENOMEM, "adjoint buffer of %zu bytes, %zu needed (receivers set after sizing it?)", s.ck_bytes,
-              L.total);
-    char *B = s.ck_buf;
-    hipStream_t st = ctx->stream;
-    DevShot *dd = (DevShot *)fdtd_ws(ctx, ctx->o_desc);
-    const DevShot *sp = dd + shot;
+    return adjoint_sweep(ctx, std::vector<int>{shot}, nt, &resid_dev, &grad_v_dev);
+}
 
-    // recomputation must not overwrite the recorded traces
-    DevShot saved = ctx->hdesc[shot];
-    ctx->hdesc[shot].traces = nullptr;
-    ctx->hdesc[shot].trace_cap = 0;
-    AHIP(ctx, hipMemcpyAsync(dd + shot, &ctx->hdesc[shot], sizeof(DevShot), hipMemcpyHostToDevice, st));
-    AHIP(ctx, hipStreamSynchronize(st));
-
-    // adjoint state to zero (W_d stays zero outside the slabs)
-    fdtd_launch_fill_zero(B + L.mu1, a256(s.elems * 4), st);
-    fdtd_launch_fill_zero(B + L.mu2, a256(s.elems * 4), st);
-    AdjArgs a;
-    memset(&a, 0, sizeof a);
-    a.s = sp;
-    a.mu1 = (float *)origin4(s, B + L.mu1);
-    a.mu2 = (float *)origin4(s, B + L.mu2);
-    for (int d = 0; d < 3; ++d) {
-        fdtd_launch_fill_zero(B + L.psib[d], a256(s.psi_elems[d] * 4), st);
-        fdtd_launch_fill_zero(B + L.zetab[d], a256(s.psi_elems[d] * 4), st);
-        a.psib[d] = (float *)(B + L.psib[d]);
-        a.zetab[d] = (float *)(B + L.zetab[d]);
-        if (s.Llo[d] + s.Lhi[d] > 0) {
-            fdtd_launch_fill_zero(B + L.E[d], a256(s.elems * 4), st);
-            fdtd_launch_fill_zero(B + L.K[d], a256(s.elems * 4), st);
-            fdtd_launch_fill_zero(B + L.W[d], a256(s.elems * 4), st);
-            a.E[d] = (float *)origin4(s, B + L.E[d]);
-            a.K[d] = (float *)origin4(s, B + L.K[d]);
-            a.W[d] = (float *)origin4(s, B + L.W[d]);
-        }
-    }
-    // receivers grouped by location, in first-appearance order; receiver order within a group
-    int ngroups = 0;
-    if (s.nrec > 0) {
-        std::vector<int32_t> h((size_t)s.nrec * 3);
-        AHIP(ctx, hipMemcpy(h.data(), s.rec, h.size() * 4, hipMemcpyDeviceToHost));
-        std::vector<int> gstart, ridx;
-        std::vector<std::vector<int>> members;
-        std::map<std::array<int32_t, 3>, int> where;
-        for (int r = 0; r < s.nrec; ++r) {
-            const std::array<int32_t, 3> key{h[3 * r], h[3 * r + 1], h[3 * r + 2]};
-            auto it = where.find(key);
-            if (it == where.end()) {
-                where[key] = (int)members.size();
-                members.push_back({r});
-            } else {
-                members[it->second].push_back(r);
-            }
-        }
-        for (auto &m : members) {
-            gstart.push_back((int)ridx.size());
-            ridx.insert(ridx.end(), m.begin(), m.end());
-        }
-        gstart.push_back((int)ridx.size());
-        ngroups = (int)members.size();
-        AHIP(ctx, hipMemcpyAsync(B + L.gstart, gstart.data(), gstart.size() * 4, hipMemcpyHostToDevice, st));
-        AHIP(ctx, hipMemcpyAsync(B + L.ridx, ridx.data(), ridx.size() * 4, hipMemcpyHostToDevice, st));
-        AHIP(ctx, hipStreamSynchronize(st));
-    }
-    const int *gstart_d = (const int *)(B + L.gstart), *ridx_d = (const int *)(B + L.ridx);
-    const long N = (long)s.nx * s.ny * s.nz;
-    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)std::min<long>((N + 255) / 256, 65536)), dim3(256), 0, st,
-                       grad_v_dev, N);
-    a.G = grad_v_dev;
-    const size_t fb = a256(s.elems * s.esz);
-    char *seg = B + L.seg;
-    // the context's step count and level roles, restored on exit: the other shots
-    // of the context keep their forward state, so that each shot's adjoint can
-    // follow one batched forward run
-    const long step_in = ctx->step;
-    const int iu_in = ctx->iu, ium1_in = ctx->ium1;
-    const bool was_saving = ctx->saving;
-    ctx->saving = false;
-    // largest per-axis thread count of passes 1 and 2 (slab points)
-    long slab_max = 0;
-    for (int d = 0; d < 3; ++d) slab_max = std::max(slab_max, slab_count(s, d));
-    const int nck = (nt + every - 1) / every;
-    const float inv_scale = (float)(1.0 / s.scale);
-    int *stepc = (int *)fdtd_ws(ctx, ctx->o_stepc);
-    for (int k = nck - 1; k >= 0; --k) {
-        const int s0 = k * every, s1 = std::min(s0 + every, nt);
-        // restore the state before step s0, then recompute the segment's levels
-        fdtd_restore_state(ctx, shot, B + L.ck + (size_t)k * fdtd_state_bytes(s));
-        fdtd_launch_set_int(stepc, s0, st);
-        ctx->step = s0;
-        AHIP(ctx, hipMemcpyAsync(seg + fb, fdtd_ws(ctx, s.o_u[ctx->iu]), s.elems * s.esz,
-                                 hipMemcpyDeviceToDevice, st));
-        AHIP(ctx, hipMemcpyAsync(seg, fdtd_ws(ctx, s.o_u[ctx->ium1]), s.elems * s.esz,
-                                 hipMemcpyDeviceToDevice, st));
-        for (int n = s0; n < s1; ++n) {
-            fdtd_enqueue_step_shot(ctx, shot);
-            AHIP(ctx, hipMemcpyAsync(seg + (size_t)(n - s0 + 2) * fb, fdtd_ws(ctx, s.o_u[ctx->iu]),
-                                     s.elems * s.esz, hipMemcpyDeviceToDevice, st));
-        }
-        // reverse sweep over the segment
-        for (int n = s1 - 1; n >= s0; --n) {
-            if (ngroups > 0)
-                hipLaunchKernelGGL(k_adj_resid, dim3((ngroups + 255) / 256), dim3(256), 0, st, a.mu1, sp,
-                                   resid_dev + (size_t)n * s.nrec, gstart_d, ridx_d, ngroups);
-            a.up = (const float *)origin4(s, seg + (size_t)(n - s0 + 2) * fb);
-            a.u0 = (const float *)origin4(s, seg + (size_t)(n - s0 + 1) * fb);
-            a.um = (const float *)origin4(s, seg + (size_t)(n - s0) * fb);
-            if (slab_max > 0) {   // the three axes in one launch each (disjoint outputs)
-                hipLaunchKernelGGL(k_adj_p1, dim3((unsigned)((slab_max + 255) / 256), 3), dim3(256), 0, st, a);
-                hipLaunchKernelGGL(k_adj_p2, dim3((unsigned)((slab_max + 255) / 256), 3), dim3(256), 0, st, a);
-            }
-            hipLaunchKernelGGL(k_adj_p3, dim3((s.nx + 63) / 64, (s.ny + 3) / 4, s.nz), dim3(64, 4), 0, st, a,
-                               inv_scale);
-            std::swap(a.mu1, a.mu2);
-        }
-        AHIP(ctx, hipGetLastError());
-    }
-    hipLaunchKernelGGL(k_adj_finish, dim3((s.nx + 255) / 256, s.ny, s.nz), dim3(256), 0, st, sp, grad_v_dev,
-                       s.c.dt);
-    ctx->saving = was_saving;
-    ctx->step = step_in;
-    ctx->iu = iu_in;
-    ctx->ium1 = ium1_in;
-    fdtd_launch_set_int(stepc, (int)step_in, st);
-    fdtd_clear_graphs(ctx);
-    ctx->hdesc[shot] = saved;
-    AHIP(ctx, hipMemcpyAsync(dd + shot, &ctx->hdesc[shot], sizeof(DevShot), hipMemcpyHostToDevice, st));
-    AHIP(ctx, hipStreamSynchronize(st));
-    AHIP(ctx, hipGetLastError());
-    return FDTD_OK;
+int fdtd_adjoint_batch(fdtd_ctx *ctx, int32_t nt, const float *const *resid_dev, double *const *grad_v_dev) {
+    if (!ctx || nt <= 0 || !resid_dev || !grad_v_dev) return FDTD_EINVAL;
+    std::vector<int> sh(ctx->shots.size());
+    for (size_t i = 0; i < sh.size(); ++i) sh[i] = (int)i;
+    return adjoint_sweep(ctx, sh, nt, resid_dev, grad_v_dev);
 }
 
 }  // extern "C"

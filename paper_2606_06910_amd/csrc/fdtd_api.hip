@@ -1573,6 +1573,9 @@ void fdtd_destroy(fdtd_ctx *ctx) {
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->adj_stream) (void)hipStreamDestroy(ctx->adj_stream);
+    for (auto e : ctx->ev_adj)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -1590,3 +1593,4 @@ int fdtd_rewrite_work(fdtd_ctx *ctx) { return write_work_lists(ctx); }
 int fdtd_reupload(fdtd_ctx *ctx) { return upload_desc(ctx); }
 int fdtd_ready(fdtd_ctx *ctx) { return ready(ctx); }
 int fdtd_zero_state(fdtd_ctx *ctx) { return zero_state(ctx); }
+void fdtd_set_copy_vec(CopyJob &j) { set_copy_vec(j); }

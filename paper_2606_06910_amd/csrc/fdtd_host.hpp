@@ -74,6 +74,10 @@ struct fdtd_ctx {
     hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
     hipStream_t side = nullptr;         // second stream: interior update concurrent with psi + band
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // adjoint: reverse sweep of one segment on its own stream while the main
+    // stream recomputes the next segment's levels (double-buffered)
+    hipStream_t adj_stream = nullptr;
+    hipEvent_t ev_adj[5] = {};          // ready[2], free[2], join
     bool single_stream = false;         // never create the side stream (everything on `stream`)
     char *ws = nullptr;
     size_t ws_bytes = 0, need = 0;
@@ -125,6 +129,7 @@ int fdtd_rewrite_work(fdtd_ctx *ctx);
 int fdtd_reupload(fdtd_ctx *ctx);
 int fdtd_ready(fdtd_ctx *ctx);
 int fdtd_zero_state(fdtd_ctx *ctx);
+void fdtd_set_copy_vec(CopyJob &j);
 
 inline void fdtd_clear_graphs(fdtd_ctx *ctx) {
     for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second.exec);

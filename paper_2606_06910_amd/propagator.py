@@ -207,6 +207,16 @@ class Propagator:
         check(self.L.fdtd_adjoint(self.ctx, shot, int(nt), _ptr(r), _ptr(g)), self.ctx)
         return g
 
+    def adjoint_all(self, nt: int, resids: Sequence[torch.Tensor]) -> List[torch.Tensor]:
+        """Gradients of every shot in one batched reverse sweep (one residual per shot)."""
+        assert len(resids) == len(self.shots)
+        rs = [r.to(device=self.device, dtype=torch.float32).contiguous() for r in resids]
+        gs = [torch.empty(sh.shape, dtype=torch.float64, device=self.device) for sh in self.shots]
+        RA = (ctypes.c_void_p * len(rs))(*[r.data_ptr() for r in rs])
+        GA = (ctypes.c_void_p * len(gs))(*[g.data_ptr() for g in gs])
+        check(self.L.fdtd_adjoint_batch(self.ctx, int(nt), RA, GA), self.ctx)
+        return gs
+
     def close(self) -> None:
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             self.stream.synchronize()

@@ -3,7 +3,8 @@
 checkpoints every 25 steps), advanced in a batched context together with the
 next smallest shot: traces and FP64 velocity gradient against the FP64
 oracle's; the next shot's gradient, taken after the first one's in the same
-context, equals that shot's gradient run alone bit for bit.
+context, equals that shot's gradient run alone bit for bit, and the batched
+sweep over both shots gives both gradients bit for bit.
 
 Bar (written here): traces within relative L2 1e-5, gradient within 1e-4 (the
 adjoint tests' bar) on the whole grid and on each axis's band; the residual
@@ -58,7 +59,9 @@ def test_smallest_batched_shot_gradient_matches_oracle():
     # gradient of that shot run alone (same residual)
     r1 = torch.randn(K, 64, generator=torch.Generator().manual_seed(7)) * 1e-3
     g1 = p.adjoint(1, K, r1).cpu().numpy()
+    ga = [g.cpu().numpy() for g in p.adjoint_all(K, [torch.from_numpy(resid.astype(np.float32)), r1])]
     p.close()
+    assert np.array_equal(ga[0], gg) and np.array_equal(ga[1], g1), "batched sweep differs from the single sweeps"
     (w1, v1), vr1 = data[1], vref[1]
     q = Propagator([Shot(n=w1.n, h=w1.h, dt=w1.dt, cpml=w1.cpml, v_ref=vr1)])
     q.set_velocity(0, torch.from_numpy(v1.astype(np.float32)).cuda())
