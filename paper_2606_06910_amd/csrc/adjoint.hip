@@ -18,9 +18,9 @@
 // it enters mu^{n+1}, first.  The model enters only through m = v^2 dt^2
 // multiplying (Lt u^n + f^n) = (u^{n+1} - 2u^n + u^{n-1}) / m, so
 // dJ/dv = (2/v) sum_n lambda^{n+1} (u^{n+1} - 2u^n + u^{n-1})
-//       = 2 dt / (m sqrt(m)) sum_n mu^{n+1} (u^{n+1} - 2u^n + u^{n-1}),
+//       = 2 dt / (m sqrt(m)) sum_n mu^{n+1} (e^{n+1} - e^n),  e^n = u^n - u^{n-1},
 // accumulated in FP64.  Forward levels are recomputed per segment from
-// checkpoints saved every `every` steps.  One sweep covers one shot or every
+// checkpoints saved every `every` steps, and the increments e kept (FP32).  One sweep covers one shot or every
 // shot of the context: each pass is one launch over all of them.
 #include "fdtd_host.hpp"
 #include "fdtd_launch.hpp"
@@ -41,9 +41,9 @@ struct AdjShot {
     float *E[3];             // origin-adjusted full-grid arrays, written at slab points of axis d only:
     float *K[3];             //   E_d, kinv E_d and W_d = dkinv E_d + a (psi_b - D1_d E_d);
     float *W[3];             //   W_d stays zero elsewhere
-    const float *lev;        // recomputed forward levels (FP32, origin-adjusted slot 0 of half 0)
-    long lstride;            // elements between level slots
-    int nslot;               // slots per half: every + 2
+    const float *lev;        // increments e of the recomputed levels (FP32, origin-adjusted slot 0 of half 0)
+    long lstride;            // elements between slots
+    int nslot;               // slots per half: every + 1
     float inv_scale;         // 1 / storage scale of the fields
     double *G;               // dense accumulator sum mu^{n+1} (u^{n+1} - 2u^n + u^{n-1})
     const float *resid;      // dJ/dtraces [nt][nrec]
@@ -54,7 +54,7 @@ struct AdjShot {
 };
 // A wave of passes 1, 2 and a block of pass 3 find their shot in a table
 // indexed by wave or block (one scalar load), not by searching the shots.
-// one reverse step: mu^{n+1} = mu[par]; u^{n-1}, u^n, u^{n+1} in slots j, j+1, j+2 of half `half`
+// one reverse step: mu^{n+1} = mu[par]; e^n, e^{n+1} in slots j, j+1 of half `half`
 struct AdjStep {
     int par, half, j, n;
 };
@@ -80,6 +80,25 @@ __global__ __launch_bounds__(256) void k_adj_resid(const AdjShot *__restrict__ A
     for (int k = k0; k < k1; ++k) r += row[a.ridx[k]];
     float *mu = a.mu[st.par];
     mu[i] = fmaf(s.m[i], r, mu[i]);
+}
+
+// Increment e = u[q] - u[q ^ 1] of one shot's two level buffers (the newest
+// level minus the one before) into a slot, over the grid: blockIdx.y is the
+// shot, blocks stride over the rows.
+struct DiffJob {
+    const float *a, *b;   // origin-adjusted
+    float *d;
+    int nx, ny, nz, P;
+    long S;
+};
+__global__ __launch_bounds__(256) void k_adj_diff(const DiffJob *__restrict__ jobs) {
+    const DiffJob j = jobs[blockIdx.y];
+    const int rows = j.ny * j.nz;
+    for (int r = (int)blockIdx.x; r < rows; r += (int)gridDim.x) {
+        const int z = r / j.ny, y = r - z * j.ny;
+        const long o = (long)z * j.S + (long)y * j.P;
+        for (int x = (int)threadIdx.x; x < j.nx; x += 256) j.d[o + x] = j.a[o + x] - j.b[o + x];
+    }
 }
 
 // Passes 1 and 2 take one wave per unit: a run of up to 64 slab points of one
@@ -232,10 +251,9 @@ __global__ __launch_bounds__(256) void k_adj_p3(const AdjShot *__restrict__ A, c
         }
     }
     const float out = leapfrog(s.m[i], (t[0] + t[1]) + t[2], c, mu2[i]);
-    // gradient: mu^{n+1} (u^{n+1} - 2 u^n + u^{n-1})
-    const float *um = a.lev + ((long)st.half * a.nslot + st.j) * a.lstride;
-    const float *u0 = um + a.lstride, *up = u0 + a.lstride;
-    const double d2u = (((double)up[i] - 2.0 * (double)u0[i]) + (double)um[i]) * (double)a.inv_scale;
+    // gradient: mu^{n+1} (e^{n+1} - e^n)
+    const float *e0 = a.lev + ((long)st.half * a.nslot + st.j) * a.lstride;
+    const double d2u = ((double)e0[i + a.lstride] - (double)e0[i]) * (double)a.inv_scale;
     const long gi = ((long)z * s.ny + y) * s.nx + x;
     a.G[gi] += (double)c * d2u;
     mu2[i] = out;
@@ -303,10 +321,13 @@ struct AdjLayout {
     // AdjShot entries, level-copy jobs, checkpoint-restore jobs, wave -> shot and block -> shot maps
     size_t tab = 0, jobs = 0, rjobs = 0, wmap = 0, bmap = 0;
     size_t total = 0;
-    int nck = 0;
+    int nck = 0;   // checkpoint slots
 };
 
-static AdjLayout adj_layout(const fdtd_ctx *ctx, const ShotH &s, int every, int nt) {
+// The regions sit at offsets fixed by the buffer's checkpoint capacity
+// (nslots), never by the steps of one sweep: a sweep over fewer steps than
+// the forward checkpointed must not place its state over later checkpoints.
+static AdjLayout adj_layout(const fdtd_ctx *ctx, const ShotH &s, int every, int nslots) {
     AdjLayout L;
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -321,9 +342,9 @@ static AdjLayout adj_layout(const fdtd_ctx *ctx, const ShotH &s, int every, int 
         waves += c.waves();
         blocks += c.blocks(t);
     }
-    L.nck = (nt + every - 1) / every;
+    L.nck = nslots;
     L.ck = take(fdtd_state_bytes(s) * (size_t)L.nck);
-    L.seg = take(a256(s.elems * s.esz) * (size_t)(every + 2) * 2);
+    L.seg = take(a256(s.elems * s.esz) * (size_t)(every + 1) * 2);   // two segments' increments
     L.mu[0] = take(s.elems * 4);
     L.mu[1] = take(s.elems * 4);
     for (int d = 0; d < 3; ++d) {
@@ -337,7 +358,7 @@ static AdjLayout adj_layout(const fdtd_ctx *ctx, const ShotH &s, int every, int 
     L.gstart = take((size_t)(s.nrec + 1) * 4);
     L.ridx = take((size_t)std::max(s.nrec, 1) * 4);
     L.tab = take(sizeof(AdjShot) * nctx);
-    L.jobs = take(sizeof(CopyJob) * (size_t)(2 * (every + 2) * 2) * nctx);
+    L.jobs = take(sizeof(DiffJob) * (size_t)(2 * (every + 1) * 2) * nctx);
     L.rjobs = take(sizeof(CopyJob) * (size_t)L.nck * 2 * 8 * nctx);
     L.wmap = take(sizeof(int) * (size_t)std::max(waves, 1L));
     L.bmap = take(sizeof(int) * (size_t)std::max(blocks, 1L));
@@ -366,11 +387,11 @@ static char *origin4(const ShotH &s, char *base) { return base + origin_elems(s)
 
 // One reverse sweep over the shots sh (one shot, or every shot of the context).
 // The reverse sweep of segment k runs on the adjoint stream while the main
-// stream restores checkpoint k - 1 and recomputes its levels into the other
-// half of each level buffer: the two touch disjoint memory (the forward state
-// and one half, the adjoint state and the other half).  ev_adj[b] (ready): the
-// levels of half b are written; ev_adj[2 + b] (free): the sweep that read
-// half b is done.
+// stream restores checkpoint k - 1, recomputes its levels and keeps their
+// increments in the other half of each increment buffer: the two touch
+// disjoint memory (the forward state and one half, the adjoint state and the
+// other half).  ev_adj[b] (ready): the increments of half b are written;
+// ev_adj[2 + b] (free): the sweep that read half b is done.
 static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, const float *const *resid,
                          double *const *grad) {
     const int nsh = (int)sh.size(), nctx = (int)ctx->shots.size();
@@ -386,7 +407,7 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
             AFAIL(ctx, FDTD_ENOMEM, "shot %d: adjoint buffer holds checkpoints for %d steps, asked %d", sh[q], s.ck_nt,
                   nt);
         if (!s.vel_set) AFAIL(ctx, FDTD_ESTATE, "shot %d: no velocity model", sh[q]);
-        const AdjLayout L = adj_layout(ctx, s, every, nt);
+        const AdjLayout L = adj_layout(ctx, s, every, s.ck_count);
         if (L.total > s.ck_bytes)
             AFAIL(ctx, FDTD_ENOMEM, "shot %d: adjoint buffer of %zu bytes, %zu needed (receivers set after sizing it?)",
                   sh[q], s.ck_bytes, L.total);
@@ -410,13 +431,14 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
     // checkpoint-restore jobs
     const int nck = (nt + every - 1) / every;
     std::vector<AdjShot> tab(nsh);
-    std::vector<CopyJob> jobs((size_t)2 * (every + 2) * 2 * nsh), rjobs((size_t)nck * 2 * 8 * nsh);
+    std::vector<DiffJob> jobs((size_t)2 * (every + 1) * 2 * nsh);
+    std::vector<CopyJob> rjobs((size_t)nck * 2 * 8 * nsh);
     std::vector<int> wmap, bmap;
     int ubase = 0, bbase = 0, maxg = 0;
     long maxrows = 0, maxck = 0;
     for (int q = 0; q < nsh; ++q) {
         const ShotH &s = ctx->shots[sh[q]];
-        const AdjLayout L = adj_layout(ctx, s, every, nt);
+        const AdjLayout L = adj_layout(ctx, s, every, s.ck_count);
         char *B = s.ck_buf;
         AdjShot &a = tab[q];
         memset(&a, 0, sizeof a);
@@ -442,7 +464,7 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
         const size_t fb = a256(s.elems * s.esz);
         a.lev = (const float *)origin4(s, B + L.seg);
         a.lstride = (long)(fb / 4);
-        a.nslot = every + 2;
+        a.nslot = every + 1;
         a.inv_scale = (float)(1.0 / s.scale);
         a.G = grad[q];
         a.resid = resid[q];
@@ -511,41 +533,42 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
                     off += len[f];
                 }
             }
-        // level copies: the grid box of level buffer qb into slot j of half b
+        // increments: level buffer qb minus the other one into slot j of half b
         for (int b = 0; b < 2; ++b)
-            for (int j = 0; j < every + 2; ++j)
+            for (int j = 0; j < every + 1; ++j)
                 for (int qb = 0; qb < 2; ++qb) {
-                    CopyJob &c = jobs[((size_t)(b * (every + 2) + j) * 2 + qb) * nsh + q];
-                    c.src = fdtd_field_origin(ctx, s, s.o_u[qb]);
-                    c.dst = (char *)origin4(s, B + L.seg) + ((size_t)b * (every + 2) + j) * fb;
-                    c.esz = 4;
-                    c.ex = s.nx;
-                    c.ey = s.ny;
-                    c.ez = s.nz;
-                    c.sy = c.dy = s.P;
-                    c.sz = c.dz = s.S;
-                    fdtd_set_copy_vec(c);
+                    DiffJob &c = jobs[((size_t)(b * (every + 1) + j) * 2 + qb) * nsh + q];
+                    c.a = (const float *)fdtd_field_origin(ctx, s, s.o_u[qb]);
+                    c.b = (const float *)fdtd_field_origin(ctx, s, s.o_u[qb ^ 1]);
+                    c.d = (float *)(origin4(s, B + L.seg) + ((size_t)b * (every + 1) + j) * fb);
+                    c.nx = s.nx;
+                    c.ny = s.ny;
+                    c.nz = s.nz;
+                    c.P = s.P;
+                    c.S = s.S;
                 }
         maxrows = std::max(maxrows, (long)s.ny * s.nz);
         hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)std::min<long>(((long)s.nx * s.ny * s.nz + 255) / 256, 65536)),
                            dim3(256), 0, st, grad[q], (long)s.nx * s.ny * s.nz);
     }
     const ShotH &s0h = ctx->shots[sh[0]];
-    const AdjLayout L0 = adj_layout(ctx, s0h, every, nt);
+    const AdjLayout L0 = adj_layout(ctx, s0h, every, s0h.ck_count);
     const AdjShot *tab_d = (const AdjShot *)(s0h.ck_buf + L0.tab);
-    const CopyJob *jobs_d = (const CopyJob *)(s0h.ck_buf + L0.jobs);
+    const DiffJob *jobs_d = (const DiffJob *)(s0h.ck_buf + L0.jobs);
     const CopyJob *rjobs_d = (const CopyJob *)(s0h.ck_buf + L0.rjobs);
     const int *wmap_d = (const int *)(s0h.ck_buf + L0.wmap), *bmap_d = (const int *)(s0h.ck_buf + L0.bmap);
     AHIP(ctx, hipMemcpyAsync((void *)tab_d, tab.data(), sizeof(AdjShot) * nsh, hipMemcpyHostToDevice, st));
-    AHIP(ctx, hipMemcpyAsync((void *)jobs_d, jobs.data(), sizeof(CopyJob) * jobs.size(), hipMemcpyHostToDevice, st));
+    AHIP(ctx, hipMemcpyAsync((void *)jobs_d, jobs.data(), sizeof(DiffJob) * jobs.size(), hipMemcpyHostToDevice, st));
     AHIP(ctx, hipMemcpyAsync((void *)rjobs_d, rjobs.data(), sizeof(CopyJob) * rjobs.size(), hipMemcpyHostToDevice,
                              st));
     if (!wmap.empty())
         AHIP(ctx, hipMemcpyAsync((void *)wmap_d, wmap.data(), sizeof(int) * wmap.size(), hipMemcpyHostToDevice, st));
     AHIP(ctx, hipMemcpyAsync((void *)bmap_d, bmap.data(), sizeof(int) * bmap.size(), hipMemcpyHostToDevice, st));
     AHIP(ctx, hipStreamSynchronize(st));
-    auto copy_level = [&](int b, int j, int qb) {
-        fdtd_launch_copy_jobs(jobs_d + ((size_t)(b * (every + 2) + j) * 2 + qb) * nsh, nsh, maxrows, st);
+    // e of the newest level (in buffer qb) into slot j of half b, every shot in one launch
+    auto store_increment = [&](int b, int j, int qb) {
+        hipLaunchKernelGGL(k_adj_diff, dim3((unsigned)std::min<long>(maxrows, 2048), nsh), dim3(256), 0, st,
+                           jobs_d + ((size_t)(b * (every + 1) + j) * 2 + qb) * nsh);
     };
 
     // the context's step count and level roles, restored on exit: the other shots
@@ -576,11 +599,10 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
         fdtd_launch_copy_jobs(rjobs_d + ((size_t)k * 2 + ctx->iu) * 8 * nsh, 8 * nsh, maxck, st);
         fdtd_launch_set_int(stepc, s0, st);
         ctx->step = s0;
-        copy_level(b, 1, ctx->iu);
-        copy_level(b, 0, ctx->ium1);
+        store_increment(b, 0, ctx->iu);   // e^{s0} = u^{s0} - u^{s0 - 1}
         for (int n = s0; n < s1; ++n) {
             fdtd_enqueue_step_shot(ctx, step_shot);
-            copy_level(b, n - s0 + 2, ctx->iu);
+            store_increment(b, n - s0 + 1, ctx->iu);   // e^{n+1}
         }
         if (sa != st) {
             AHIP(ctx, hipEventRecord(ctx->ev_adj[b], st));
@@ -630,7 +652,7 @@ extern "C" {
 
 int fdtd_adjoint_workspace_size(const fdtd_ctx *ctx, int32_t shot, int32_t every, int32_t nt, size_t *bytes) {
     if (!ctx || !bytes || shot < 0 || shot >= (int)ctx->shots.size() || every <= 0 || nt <= 0) return FDTD_EINVAL;
-    *bytes = adj_layout(ctx, ctx->shots[shot], every, nt).total;
+    *bytes = adj_layout(ctx, ctx->shots[shot], every, (nt + every - 1) / every).total;
     return FDTD_OK;
 }
 
@@ -652,7 +674,7 @@ int fdtd_set_checkpointing(fdtd_ctx *ctx, int32_t shot, int32_t every, void *buf
     if (((uintptr_t)buf_dev) & 255) AFAIL(ctx, FDTD_EINVAL, "adjoint buffer must be 256-byte aligned");
     // capacity: the largest nt this buffer holds checkpoints for
     int nck = 0;
-    while (adj_layout(ctx, s, every, (nck + 1) * every).total <= bytes && nck < (1 << 20)) ++nck;
+    while (adj_layout(ctx, s, every, nck + 1).total <= bytes && nck < (1 << 20)) ++nck;
     if (nck == 0) AFAIL(ctx, FDTD_ENOMEM, "adjoint buffer too small");
     s.ck_every = every;
     s.ck_count = nck;

@@ -77,6 +77,31 @@ def test_gradient_independent_of_checkpoint_interval(adj_case):
     assert np.array_equal(g1, g2) and np.array_equal(g1, g3)
 
 
+def test_shorter_sweep_keeps_the_later_checkpoints(adj_case):
+    """A sweep over the first segment only, before the full one, leaves the full
+    gradient bit for bit as it is alone: a short sweep places nothing over the
+    checkpoints it does not use."""
+    import torch
+
+    from paper_2606_06910_amd import Propagator, Shot
+
+    w, dobs, _, _ = adj_case
+    _, g_alone = _gpu_grad(w, dobs, every=25)
+    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml, v_ref=float(v32(w).max()), variant=2)])
+    p.set_velocity(0, torch.from_numpy(w.v.astype(np.float32)).cuda())
+    p.inject_source(0, w.src[0], torch.from_numpy(w.wavelet.astype(np.float32)))
+    p.set_receivers(0, w.rec)
+    p.set_checkpointing(0, 25, w.nt)
+    tr = p.record(0, w.nt)
+    p.step(w.nt)
+    torch.cuda.synchronize()
+    resid = torch.from_numpy((tr.cpu().double().numpy() - dobs).astype(np.float32))
+    p.adjoint(0, 25, resid[:25].contiguous())
+    g = p.adjoint(0, w.nt, resid).cpu().numpy()
+    p.close()
+    assert np.array_equal(g, g_alone)
+
+
 def test_autograd_function(adj_case):
     import torch
 
