@@ -57,9 +57,14 @@ __device__ __forceinline__ void axis_point(const DevShot &s, int d, int c, AxisP
 //    from a u^n queue that reaches z + 8.
 // Each layer point is advanced once, by the tile that owns it, with the psi
 // pass's operations, so the bits do not change.
+// LDS plane of a tile: its BAND_TX x BAND_TY points and a 4-cell halo on each
+// side along x and y (corners unused), and a dummy slot for lanes without a halo value
+constexpr int kBandLW = BAND_TX + 2 * FDTD_R, kBandLH = BAND_TY + 2 * FDTD_R;
+constexpr int kBandLB = kBandLW * kBandLH + 1;
+
 template <typename T, int KIND, bool FUSE>
 __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, const BandItem wi, const Roles &R,
-                                          int zchunk, const int *__restrict__ stepc) {
+                                          int zchunk, const int *__restrict__ stepc, float *Lds) {
     constexpr bool HAS_Y = KIND <= 1, HAS_Z = KIND == 0;
     constexpr bool FZ = FUSE && HAS_Z;   // psi_z advanced in the z queue
     constexpr int QN = FZ ? 13 : 9;      // u^n queue: planes z - 4 .. z + QN - 5
@@ -69,12 +74,22 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
     band_box(n3, s.Llo, s.Lhi, s.ghost, R.ext, wi.box, blo, bhi);
     int x0, x1;
     band_xtiles(s.nx, s.Llo[0], s.Lhi[0], wi.box, blo[0], bhi[0], wi.tx, &x0, &x1);
-    const int x = x0 + (int)(threadIdx.x % BAND_TX);
-    const int y = blo[1] + wi.ty * BAND_TY + (int)(threadIdx.x / BAND_TX);
+    const int lx = (int)(threadIdx.x % BAND_TX), ly = (int)(threadIdx.x / BAND_TX);
+    const int x = x0 + lx;
+    const int yt = blo[1] + wi.ty * BAND_TY;   // first row of the tile
+    const int y = yt + ly;
     // z boxes are walked whole (their tile list has one chunk), the others in chunks
     const int za = KIND == 0 ? blo[2] : blo[2] + wi.zc * zchunk;
-    if (x >= x1 || y >= bhi[1] || za >= bhi[2]) return;   // no barriers below
+    // the whole tile (uniform, barriers below): also the idle items that pad the
+    // list (x0 past x1, a coordinate no layer data may be read at)
+    if (za >= bhi[2] || yt >= bhi[1] || x0 >= x1) return;
     const int zb = KIND == 0 ? bhi[2] : min(za + zchunk, bhi[2]);
+    // Every lane of the tile stages its u^n into the LDS plane, where the x and
+    // y stencil taps of the points are read; lanes past the box end (act
+    // false) compute nothing and store nothing.  A lane position outside the
+    // rows and columns the field buffer holds reads zero (it is no tap of any
+    // point of the box).
+    const bool act = x < x1 && y < bhi[1];
 
     const Coef K = load_coef(s);
     float w1[3][5];
@@ -97,11 +112,28 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
     const uint32_t vo = (uint32_t)(((long)(y + fy - 4) * P + x) * esz);
     const uint32_t vc = vo + (uint32_t)((4 * P + 4) * esz);                 // the point itself
     const uint32_t vcm = (uint32_t)(((long)(y + fy) * P + x + 4) * 4);      // the point in m
-    const uint32_t Sb = (uint32_t)(S * esz), Smb = (uint32_t)(S * 4), Pb = (uint32_t)(P * esz);
+    const uint32_t Sb = (uint32_t)(S * esz), Smb = (uint32_t)(S * 4);
+    auto held = [&](int xp, int yp) { return xp >= -4 && xp < nx + 4 && yp >= -fy && yp < s.ny + fy; };
+    auto lane_off = [&](int xp, int yp) -> uint32_t {
+        return held(xp, yp) ? (uint32_t)(((long)(yp + fy) * P + xp + 4) * esz) : kBufSkip;
+    };
+    const uint32_t vcq = lane_off(x, y);             // the lane's u^n column (z queue, LDS plane)
+    const uint32_t vca = act ? vc : kBufSkip;        // the point's own loads and stores
+    const uint32_t vcma = act ? vcm : kBufSkip;
+    // LDS slots: the lane's own, and its halo value(s): the 4 x 32 rows above and
+    // below the tile (one per lane), the 8 x 4 columns left and right of it (lanes 0..63)
+    const int own = (ly + FDTD_R) * kBandLW + lx + FDTD_R;
+    const int t = (int)threadIdx.x;
+    const int hr1 = (t >> 5) < 4 ? (t >> 5) : (t >> 5) + BAND_TY, hc1 = FDTD_R + (t & 31);
+    const int hslot1 = hr1 * kBandLW + hc1;
+    const uint32_t hoff1 = lane_off(x0 - FDTD_R + hc1, yt - FDTD_R + hr1);
+    const int hr2 = FDTD_R + (t >> 3), hc2 = (t & 7) < 4 ? (t & 7) : BAND_TX + (t & 7);
+    const int hslot2 = t < 64 ? hr2 * kBandLW + hc2 : kBandLB - 1;
+    const uint32_t hoff2 = t < 64 ? lane_off(x0 - FDTD_R + hc2, yt - FDTD_R + hr2) : kBufSkip;
 
     AxisPt AX, AY;
-    axis_point(s, 0, x, AX);
-    if constexpr (HAS_Y) axis_point(s, 1, y, AY);
+    axis_point(s, 0, act ? x : x0, AX);
+    if constexpr (HAS_Y) axis_point(s, 1, act ? y : yt, AY);
     // psi_d and zeta_d of an axis through one descriptor (zeta_d follows psi_d in the workspace)
     const Rsrc rpx = make_rsrc(s.psi[0]);
     const uint32_t zdx = (uint32_t)((const char *)s.zeta[0] - (const char *)s.psi[0]);
@@ -118,8 +150,8 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
     uint32_t px_off[8], py_off[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-        px_off[j] = AX.npos[j] != xlo + xhi ? xoff(j < 4 ? x - (j + 1) : x + (j - 3)) : kBufSkip;
-    const uint32_t zx_off = AX.slab ? xoff(x) : 0u;
+        px_off[j] = act && AX.npos[j] != xlo + xhi ? xoff(j < 4 ? x - (j + 1) : x + (j - 3)) : kBufSkip;
+    const uint32_t zx_off = act && AX.slab ? xoff(x) : kBufSkip;
     // FUSE: source lanes of the 8 x neighbours within the wave and the mask of
     // those inside the x slabs (all of them lie in this tile row); whether the
     // tile reaches the x band at all (uniform)
@@ -144,8 +176,8 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
         rpy = make_rsrc(s.psi[1]);
         zdy = (uint32_t)((const char *)s.zeta[1] - (const char *)s.psi[1]);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) py_off[j] = 4 * (uint32_t)(AY.npos[j] * nx + x);
-        zy_off = 4 * (uint32_t)(AY.pos * nx + x);
+        for (int j = 0; j < 8; ++j) py_off[j] = act ? 4 * (uint32_t)(AY.npos[j] * nx + x) : kBufSkip;
+        zy_off = act ? 4 * (uint32_t)(AY.pos * nx + x) : kBufSkip;
         Spy = (uint32_t)((long)s.SY * nx * 4);
     }
     const int nz = s.nz, zlo = s.Llo[2], zhi = s.Lhi[2];
@@ -153,7 +185,7 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
         rpz = make_rsrc(s.psi[2]);
         rpr = make_rsrc(s.prof);
         zdz = (uint32_t)((const char *)s.zeta[2] - (const char *)s.psi[2]);
-        vz_col = (uint32_t)(((long)(y + fy) * nx + x) * 4);
+        vz_col = act ? (uint32_t)(((long)(y + fy) * nx + x) * 4) : kBufSkip;
         Spz = (uint32_t)((long)s.PY * nx * 4);
     }
     // plane p of the z slabs (uniform condition)
@@ -190,7 +222,7 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
     // z queues at the column: q[o] = u(x, y, z - 4 + o); pq[o] = psi_z at z - 4 + o (0 outside its slab)
     float q[QN], pq[9];
 #pragma unroll
-    for (int o = 0; o < QN - 1; ++o) q[o] = Buf<T>::ld(ru, vc, o * Sb);
+    for (int o = 0; o < QN - 1; ++o) q[o] = Buf<T>::ld(ru, vcq, o * Sb);
     if constexpr (FZ) {
         // planes za - 4 .. za - 1 lie outside the z slabs (the host enables FUSE
         // only when the two z boxes share no layer point); za .. za + 3 are
@@ -228,17 +260,10 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
     auto load = [&](int z, PL &p) {
         const uint32_t pz = (uint32_t)(z - za + 4) * Sb;
         // FZ: the head u(z + 8) is needed only while z + 4 is a grid plane (it may lie past the frame)
-        const uint32_t vq = (!FZ || z + 4 < nz) ? vc : kBufSkip;
+        const uint32_t vq = (!FZ || z + 4 < nz) ? vcq : kBufSkip;
         p.qn = Buf<T>::ld(ru, vq, pz + (QN - 5) * Sb);
-#pragma unroll
-        for (int l = 1; l <= 4; ++l) {
-            p.xl[l - 1] = Buf<T>::ld(ru, vc - (uint32_t)(l * esz), pz);
-            p.xh[l - 1] = Buf<T>::ld(ru, vc + (uint32_t)(l * esz), pz);
-            p.yl[l - 1] = Buf<T>::ld(ru, vc - (uint32_t)l * Pb, pz);
-            p.yh[l - 1] = Buf<T>::ld(ru, vc + (uint32_t)l * Pb, pz);
-        }
-        p.second = Buf<T>::ld(rs, vc, pz);
-        p.mm = Buf<float>::ld(rm, vcm, (uint32_t)(z - za + 4) * Smb);
+        p.second = Buf<T>::ld(rs, vca, pz);
+        p.mm = Buf<float>::ld(rm, vcma, (uint32_t)(z - za + 4) * Smb);
         // (a y neighbour outside the slabs reads the zero slot of its row)
         const uint32_t sox = (uint32_t)(z + fz) * Spx;
         if constexpr (FUSE) {
@@ -362,7 +387,7 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
         const float lt = (L[0] + L[1]) + L[2];
         const bool src = src_col && wrap_ghost(s, 2, z) == s.sz;
         const Upd up = time_update<T>(p.mm, lt, c, p.second, src, srcamp);
-        if (!in_box(R, x, y, z)) {
+        if (act && !in_box(R, x, y, z)) {
             const uint32_t pz = (uint32_t)(z - za + 4) * Sb;
             Buf<T>::st(rw, vc, pz, up.u);
             if constexpr (IsInc<T>::v) Buf<T>::st(rs, vc, pz, up.d);
@@ -380,11 +405,33 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
         }
     };
 
+    // per plane: stage the lane's u^n (the queue centre) and the halo values
+    // loaded one plane earlier into one of two LDS planes, issue the plane's
+    // other loads and the next plane's halo, then one barrier and the taps
+    float h1 = Buf<T>::ld(ru, hoff1, 4 * Sb), h2 = Buf<T>::ld(ru, hoff2, 4 * Sb);
     PL A;
+    int buf = 0;
 #pragma unroll 1
     for (int z = za; z < zb; ++z) {
+        float *Lp = Lds + buf * kBandLB;
+        Lp[own] = q[4];
+        Lp[hslot1] = h1;
+        Lp[hslot2] = h2;
         load(z, A);
+        // (plane z + 1 lies inside the field's frame planes even when z + 1 = zb)
+        const uint32_t zn1 = (uint32_t)(z + 1 - za + 4) * Sb;
+        h1 = Buf<T>::ld(ru, hoff1, zn1);
+        h2 = Buf<T>::ld(ru, hoff2, zn1);
+        __syncthreads();
+#pragma unroll
+        for (int l = 1; l <= 4; ++l) {
+            A.xl[l - 1] = Lp[own - l];
+            A.xh[l - 1] = Lp[own + l];
+            A.yl[l - 1] = Lp[own - l * kBandLW];
+            A.yh[l - 1] = Lp[own + l * kBandLW];
+        }
         compute(z, A);
+        buf ^= 1;
     }
 }
 
@@ -393,16 +440,17 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
 template <typename T>
 __global__ __launch_bounds__(256) void k_band(const DevShot *__restrict__ shots, const BandItem *__restrict__ work,
                                               Roles R, int zchunk, const int *__restrict__ stepc) {
+    __shared__ float Lds[2 * kBandLB];
     const BandItem wi = work[blockIdx.x];
     const int kind = wi.box >> 1;
     if (shots[wi.shot].fused) {
-        if (kind == 0) band_tile<T, 0, true>(shots, wi, R, zchunk, stepc);
-        else if (kind == 1) band_tile<T, 1, true>(shots, wi, R, zchunk, stepc);
-        else band_tile<T, 2, true>(shots, wi, R, zchunk, stepc);
+        if (kind == 0) band_tile<T, 0, true>(shots, wi, R, zchunk, stepc, Lds);
+        else if (kind == 1) band_tile<T, 1, true>(shots, wi, R, zchunk, stepc, Lds);
+        else band_tile<T, 2, true>(shots, wi, R, zchunk, stepc, Lds);
     } else {
-        if (kind == 0) band_tile<T, 0, false>(shots, wi, R, zchunk, stepc);
-        else if (kind == 1) band_tile<T, 1, false>(shots, wi, R, zchunk, stepc);
-        else band_tile<T, 2, false>(shots, wi, R, zchunk, stepc);
+        if (kind == 0) band_tile<T, 0, false>(shots, wi, R, zchunk, stepc, Lds);
+        else if (kind == 1) band_tile<T, 1, false>(shots, wi, R, zchunk, stepc, Lds);
+        else band_tile<T, 2, false>(shots, wi, R, zchunk, stepc, Lds);
     }
 }
 
