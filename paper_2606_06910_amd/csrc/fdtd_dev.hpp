@@ -204,6 +204,30 @@ __host__ __device__ inline int band_xtiles(int nx, int Llo, int Lhi, int k, int 
     return nlo + nhi;
 }
 
+// LDS plane of a band-kernel tile: its BAND_TX x BAND_TY points and a 4-cell
+// halo on each side along x and y (corners unused), slot (column c, row r) =
+// r * kBandLW + c, plus a dummy slot for lanes without a second halo value.
+constexpr int kBandLW = BAND_TX + 2 * FDTD_R, kBandLH = BAND_TY + 2 * FDTD_R;
+constexpr int kBandLB = kBandLW * kBandLH + 1;
+// The halo value lane t of a tile stages: k = 0 one of the 4 rows above or
+// below the tile (every lane), k = 1 one of the 4 columns left or right of it
+// (lanes below 2 * 4 * BAND_TY).  (c, r): its slot; c = -1 when the lane has none.
+__host__ __device__ inline void band_halo(int t, int k, int &c, int &r) {
+    if (k == 0) {
+        const int q = t / BAND_TX;
+        r = q < FDTD_R ? q : q + BAND_TY;
+        c = FDTD_R + t % BAND_TX;
+        return;
+    }
+    if (t >= 2 * FDTD_R * BAND_TY) {
+        c = r = -1;
+        return;
+    }
+    const int j = t % (2 * FDTD_R);
+    r = FDTD_R + t / (2 * FDTD_R);
+    c = j < FDTD_R ? j : BAND_TX + j;
+}
+
 // ---------------------------------------------------------------------------
 // layer geometry
 // ---------------------------------------------------------------------------

@@ -57,11 +57,6 @@ __device__ __forceinline__ void axis_point(const DevShot &s, int d, int c, AxisP
 //    from a u^n queue that reaches z + 8.
 // Each layer point is advanced once, by the tile that owns it, with the psi
 // pass's operations, so the bits do not change.
-// LDS plane of a tile: its BAND_TX x BAND_TY points and a 4-cell halo on each
-// side along x and y (corners unused), and a dummy slot for lanes without a halo value
-constexpr int kBandLW = BAND_TX + 2 * FDTD_R, kBandLH = BAND_TY + 2 * FDTD_R;
-constexpr int kBandLB = kBandLW * kBandLH + 1;
-
 template <typename T, int KIND, bool FUSE>
 __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, const BandItem wi, const Roles &R,
                                           int zchunk, const int *__restrict__ stepc, float *Lds) {
@@ -120,16 +115,16 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
     const uint32_t vcq = lane_off(x, y);             // the lane's u^n column (z queue, LDS plane)
     const uint32_t vca = act ? vc : kBufSkip;        // the point's own loads and stores
     const uint32_t vcma = act ? vcm : kBufSkip;
-    // LDS slots: the lane's own, and its halo value(s): the 4 x 32 rows above and
-    // below the tile (one per lane), the 8 x 4 columns left and right of it (lanes 0..63)
+    // LDS slots (band_halo): the lane's own and its halo value(s), slot (c, r)
+    // holding the point (x0 - 4 + c, yt - 4 + r)
     const int own = (ly + FDTD_R) * kBandLW + lx + FDTD_R;
-    const int t = (int)threadIdx.x;
-    const int hr1 = (t >> 5) < 4 ? (t >> 5) : (t >> 5) + BAND_TY, hc1 = FDTD_R + (t & 31);
+    int hc1, hr1, hc2, hr2;
+    band_halo((int)threadIdx.x, 0, hc1, hr1);
+    band_halo((int)threadIdx.x, 1, hc2, hr2);
     const int hslot1 = hr1 * kBandLW + hc1;
     const uint32_t hoff1 = lane_off(x0 - FDTD_R + hc1, yt - FDTD_R + hr1);
-    const int hr2 = FDTD_R + (t >> 3), hc2 = (t & 7) < 4 ? (t & 7) : BAND_TX + (t & 7);
-    const int hslot2 = t < 64 ? hr2 * kBandLW + hc2 : kBandLB - 1;
-    const uint32_t hoff2 = t < 64 ? lane_off(x0 - FDTD_R + hc2, yt - FDTD_R + hr2) : kBufSkip;
+    const int hslot2 = hc2 >= 0 ? hr2 * kBandLW + hc2 : kBandLB - 1;
+    const uint32_t hoff2 = hc2 >= 0 ? lane_off(x0 - FDTD_R + hc2, yt - FDTD_R + hr2) : kBufSkip;
 
     AxisPt AX, AY;
     axis_point(s, 0, act ? x : x0, AX);

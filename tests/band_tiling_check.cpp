@@ -5,7 +5,12 @@
 // the x bands and the z bands each far enough apart), every x-layer point lies
 // in the same tile row as each band point that reads it, and every z-layer
 // point in the same z-box walk as its readers, with the walk's first planes
-// outside the layers and at least 5 planes deep.  Prints "ok <cases> <fused>".
+// outside the layers and at least 5 planes deep.  And the LDS staging of every
+// tile: each x and y stencil tap of each of its points is found in the slot that
+// the tile's lanes fill with that position (their own u^n, or a halo value from
+// band_halo), loaded from a position the field buffer holds (rows within the
+// frame of fy = max(4, ext + 4), columns within 4 of the grid).  Prints
+// "ok <cases> <fused>".
 #include "fdtd_dev.hpp"
 
 #include <array>
@@ -34,6 +39,48 @@ struct Table {
     }
     Owner &at(int x, int y, int z) { return v[((size_t)(z + ext) * ny + (y + ext)) * nx + x]; }
 };
+// Replay of one tile's LDS staging (the band kernel's slots and band_halo):
+// every tap of every point of the tile is the position its slot is filled
+// with, from a position inside the field buffer's rows [-fy, ny + fy) and
+// columns [-4, nx + 4).
+bool staging_ok(const int *n, int fy, int x0, int x1, int yt, int yend) {
+    struct Fill {
+        int x, y;
+        bool held;
+    };
+    std::vector<Fill> slot(kBandLB, Fill{0, 0, false});
+    std::vector<bool> set(kBandLB, false);
+    auto held = [&](int xp, int yp) { return xp >= -4 && xp < n[0] + 4 && yp >= -fy && yp < n[1] + fy; };
+    auto put = [&](int c, int r) {
+        const int i = r * kBandLW + c, xp = x0 - FDTD_R + c, yp = yt - FDTD_R + r;
+        if (i < 0 || i >= kBandLB - 1) return false;
+        slot[i] = Fill{xp, yp, held(xp, yp)};
+        set[i] = true;
+        return true;
+    };
+    for (int t = 0; t < BAND_TX * BAND_TY; ++t) {
+        if (!put(FDTD_R + t % BAND_TX, FDTD_R + t / BAND_TX)) return false;
+        for (int k = 0; k < 2; ++k) {
+            int c, r;
+            band_halo(t, k, c, r);
+            if (c >= 0 && !put(c, r)) return false;
+        }
+    }
+    for (int t = 0; t < BAND_TX * BAND_TY; ++t) {
+        const int lx = t % BAND_TX, ly = t / BAND_TX, x = x0 + lx, y = yt + ly;
+        if (x >= x1 || y >= yend) continue;
+        const int own = (ly + FDTD_R) * kBandLW + lx + FDTD_R;
+        for (int l = 1; l <= FDTD_R; ++l) {
+            const int idx[4] = {own - l, own + l, own - l * kBandLW, own + l * kBandLW};
+            const int px[4] = {x - l, x + l, x, x}, py[4] = {y, y, y - l, y + l};
+            for (int j = 0; j < 4; ++j) {
+                const Fill &f = slot[idx[j]];
+                if (!set[idx[j]] || f.x != px[j] || f.y != py[j] || !f.held) return false;
+            }
+        }
+    }
+    return true;
+}
 }  // namespace
 
 int main(int argc, char **argv) {
@@ -73,6 +120,10 @@ int main(int argc, char **argv) {
                         band_xtiles(n[0], lo[0], hi[0], b, blo[0], bhi[0], tx, &x0, &x1);
                         if (x1 <= x0 || x1 - x0 > BAND_TX) {
                             printf("FAIL tile width %d\n", x1 - x0);
+                            return 1;
+                        }
+                        if (!staging_ok(n, gh[1] ? ext + 4 : 4, x0, x1, blo[1] + ty * BAND_TY, bhi[1])) {
+                            printf("FAIL LDS staging of tile box %d tx %d ty %d\n", b, tx, ty);
                             return 1;
                         }
                         const int za = b < 2 ? blo[2] : blo[2] + 32 * zc, zb = b < 2 ? bhi[2] : std::min(za + 32, bhi[2]);
