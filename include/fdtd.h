@@ -183,6 +183,16 @@ int fdtd_load_state(fdtd_ctx *ctx, const void *src_dev, size_t bytes);
  * NaN or Inf is present. */
 int fdtd_check_finite(fdtd_ctx *ctx);
 
+/* NaN/Inf sentinel (failure detection; the paper has none).  With every > 0,
+ * fdtd_step scans the newest wavefield level of every shot after each step
+ * whose count is a multiple of `every`, into a sticky device flag, and when a
+ * call enqueued a scan it synchronises once at its end and returns
+ * FDTD_ENONFINITE if the flag is set; fdtd_step_graph scans once after each
+ * graph launch instead.  every = 0 turns it off (the default).  The flag is
+ * cleared by this call and by fdtd_reset.  EINVAL for every < 0, ESTATE
+ * without a bound workspace. */
+int fdtd_set_sentinel(fdtd_ctx *ctx, int32_t every);
+
 /* Size in bytes of the device buffer fdtd_adjoint needs for one shot with
  * checkpoints every `every` steps over nt steps (checkpoints, two segments of
  * recomputed levels, adjoint state, the receivers grouped by location, and

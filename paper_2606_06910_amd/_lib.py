@@ -93,6 +93,7 @@ _SIGS = {
     "fdtd_reset": (ctypes.c_int, [_P]),
     "fdtd_get_step": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
     "fdtd_check_finite": (ctypes.c_int, [_P]),
+    "fdtd_set_sentinel": (ctypes.c_int, [_P, ctypes.c_int32]),
     "fdtd_state_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "fdtd_save_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "fdtd_load_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),

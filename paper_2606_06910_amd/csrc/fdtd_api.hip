@@ -786,9 +786,21 @@ static void enqueue_tblock(fdtd_ctx *ctx) {
 }
 
 // nsteps steps of every shot (temporal blocks where they apply)
-static void enqueue_steps(fdtd_ctx *ctx, int nsteps) {
-    int k = 0;
+// NaN/Inf sentinel: scan the newest level of every shot into the sticky flag
+// (scratch slot 3), cleared only by fdtd_set_sentinel and fdtd_reset
+static void enqueue_sentinel(fdtd_ctx *ctx) {
+    unsigned int *flag = (unsigned int *)wsp(ctx, ctx->o_scratch) + 3;
+    for (auto &s : ctx->shots)
+        fdtd_launch_finite(ctx->storage, field_origin(ctx, s, s.o_u[ctx->iu]), s.nx, s.ny, s.nz, s.P, s.S, flag,
+                           ctx->stream);
+}
+
+// nsteps steps; returns how many sentinel scans were enqueued (a scan follows
+// each step whose count is a multiple of sentinel_every)
+static int enqueue_steps(fdtd_ctx *ctx, int nsteps) {
+    int k = 0, scans = 0;
     while (k < nsteps) {
+        const long before = ctx->step;
         if (tblock_active(ctx) && nsteps - k >= ctx->shots[0].tk) {
             enqueue_tblock(ctx);
             k += ctx->shots[0].tk;
@@ -796,7 +808,25 @@ static void enqueue_steps(fdtd_ctx *ctx, int nsteps) {
             enqueue_step(ctx, -1);
             ++k;
         }
+        const long e = ctx->sentinel_every;
+        if (e > 0 && ctx->step / e != before / e) {
+            enqueue_sentinel(ctx);
+            ++scans;
+        }
     }
+    return scans;
+}
+
+// read the sentinel flag (synchronises the stream)
+static int sentinel_check(fdtd_ctx *ctx) {
+    unsigned int bad = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&bad, (unsigned int *)wsp(ctx, ctx->o_scratch) + 3, 4, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (bad)
+        FAIL(ctx, FDTD_ENONFINITE, "non-finite value in a wavefield at or before step %ld (sentinel every %d steps)",
+             ctx->step, ctx->sentinel_every);
+    return FDTD_OK;
 }
 
 static int ready(fdtd_ctx *ctx) {
@@ -1281,16 +1311,25 @@ int fdtd_step(fdtd_ctx *ctx, int32_t nsteps) {
     if (!ctx || nsteps < 0) return FDTD_EINVAL;
     int rc = ready(ctx);
     if (rc) return rc;
-    int done = 0;
+    int done = 0, scans = 0;
     while (done < nsteps) {
         const int chunk = std::min(nsteps - done, 256);
-        enqueue_steps(ctx, chunk);
+        scans += enqueue_steps(ctx, chunk);
         done += chunk;
         if (ctx->timing && ctx->ev_used > 2000) {
             rc = drain_timing(ctx);
             if (rc) return rc;
         }
     }
+    HIPCHK(ctx, hipGetLastError());
+    return scans > 0 ? sentinel_check(ctx) : FDTD_OK;
+}
+
+int fdtd_set_sentinel(fdtd_ctx *ctx, int32_t every) {
+    if (!ctx || every < 0) return FDTD_EINVAL;
+    if (!ctx->ws) FAIL(ctx, FDTD_ESTATE, "no workspace bound");
+    ctx->sentinel_every = every;
+    fdtd_launch_set_int((int *)wsp(ctx, ctx->o_scratch) + 3, 0, ctx->stream);
     HIPCHK(ctx, hipGetLastError());
     return FDTD_OK;
 }
@@ -1352,7 +1391,10 @@ int fdtd_step_graph(fdtd_ctx *ctx, int32_t nsteps) {
             (void)hipGetLastError();
             FAIL(ctx, FDTD_EHIP, "graph capture: %s", hipGetErrorString(e));
         }
+        const int sentinel = ctx->sentinel_every;
+        ctx->sentinel_every = 0;   // graphs hold no scans: one scan follows each graph launch
         enqueue_steps(ctx, nsteps);
+        ctx->sentinel_every = sentinel;
         const int end_iu = ctx->iu, end_ium1 = ctx->ium1;
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(ctx->stream, &g);
@@ -1374,6 +1416,10 @@ int fdtd_step_graph(fdtd_ctx *ctx, int32_t nsteps) {
     ctx->step += nsteps;
     ctx->iu = it->second.end_iu;
     ctx->ium1 = it->second.end_ium1;
+    if (ctx->sentinel_every > 0) {
+        enqueue_sentinel(ctx);
+        return sentinel_check(ctx);
+    }
     return FDTD_OK;
 }
 
@@ -1415,6 +1461,7 @@ int fdtd_set_field(fdtd_ctx *ctx, int32_t shot, int32_t which, const float *src_
 int fdtd_reset(fdtd_ctx *ctx) {
     if (!ctx) return FDTD_EINVAL;
     if (!ctx->ws) FAIL(ctx, FDTD_ESTATE, "no workspace bound");
+    fdtd_launch_set_int((int *)wsp(ctx, ctx->o_scratch) + 3, 0, ctx->stream);   // sentinel flag
     return zero_state(ctx);
 }
 

@@ -91,6 +91,7 @@ struct fdtd_ctx {
     };
     std::vector<Group> groups;
     int storage = 0;
+    int sentinel_every = 0;   // > 0: scan the newest level for NaN/Inf after every such step (scratch slot 3)
     int iu = 0;         // level buffer holding u^n
     int ium1 = 1;       // level buffer holding u^{n-1} (FP32) -- 16-bit keeps d^n in its own buffer
     long step = 0;

@@ -153,6 +153,10 @@ class Propagator:
     def check_finite(self) -> None:
         check(self.L.fdtd_check_finite(self.ctx), self.ctx)
 
+    def set_sentinel(self, every: int) -> None:
+        """Scan for NaN/Inf every `every` steps while stepping (0: off); step raises FDTDError then."""
+        check(self.L.fdtd_set_sentinel(self.ctx, int(every)), self.ctx)
+
     def set_plan(self, shot: int, variant: int, tile_ry: int = 2, zchunk: int = 64, tblock_k: int = 1,
                  tile_cols: int = 1) -> None:
         check(self.L.fdtd_set_plan(self.ctx, shot, variant, tile_ry, zchunk, tblock_k, tile_cols), self.ctx)

@@ -91,6 +91,9 @@ def test_create_and_workspace_size_on_host():
     # calls that need a workspace fail cleanly before one is bound
     assert L.fdtd_step(ctx, 1) == -3
     assert b"workspace" in L.fdtd_last_error(ctx)
+    assert L.fdtd_set_sentinel(ctx, 5) == -3      # sentinel: needs a workspace too
+    assert L.fdtd_set_sentinel(ctx, -1) == -1     # and a non-negative interval
+    assert L.fdtd_set_sentinel(None, 5) == -1
     L.fdtd_destroy(ctx)
 
 

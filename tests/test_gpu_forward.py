@@ -208,6 +208,34 @@ def test_error_paths():
     q.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_nan_sentinel(graph):
+    """A NaN set into u^n from the host: stepping on without the sentinel raises
+    nothing; with a scan every 5 steps the next call that scans reports
+    ENONFINITE (eager: after the scan step; graph: after the launch); after
+    fdtd_reset the flag is clear and a clean run steps on."""
+    import torch
+
+    from paper_2606_06910_amd import FDTDError, Propagator, Shot
+
+    w = _ragged((24, 24, 24), (10.0, 10.0, 10.0), (4,) * 6, 10, 9)
+    p = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml)])
+    p.set_velocity(0, torch.from_numpy(w.v.astype(np.float32)).cuda())
+    p.step(3)
+    f = torch.zeros(w.v.shape, device="cuda")
+    f[12, 12, 12] = float("nan")
+    p.set_field(0, 0, f)
+    p.step(4, graph=graph)            # sentinel off
+    p.set_sentinel(5)
+    p.step(2, graph=False)            # steps 8, 9: no scan yet
+    with pytest.raises(FDTDError, match="ENONFINITE"):
+        p.step(5, graph=graph)
+    p.reset()
+    p.set_sentinel(5)
+    p.step(10, graph=graph)
+    p.close()
+
+
 @pytest.mark.parametrize("n", [(512, 512, 512)])
 def test_full_size_variants_bitwise_and_crop_oracle(n):
     """Full layered 512^3 shape, 50 steps: naive and z-march agree bit for bit;
