@@ -49,11 +49,14 @@ struct AdjShot {
     const float *resid;      // dJ/dtraces [nt][nrec]
     const int *gstart, *ridx;   // receivers grouped by location (k_adj_resid)
     int ngroups, nrec;
-    int ubase, ucnt[3], uch[3];   // passes 1, 2: first wave unit, units and chunks per row of each axis
     int bbase, btx, bty;          // pass 3: first block, tiles along x and y
 };
-// A wave of passes 1, 2 and a block of pass 3 find their shot in a table
-// indexed by wave or block (one scalar load), not by searching the shots.
+// A block of passes 1, 2 or 3 finds its shot (and for 1, 2 its axis and first
+// slab point) in a table indexed by block (scalar loads), not by searching.
+struct SlabBlock {
+    int shot_axis;   // shot of the sweep * 4 + axis
+    int t0;          // first slab point of the block along that axis
+};
 // one reverse step: mu^{n+1} = mu[par]; e^n, e^{n+1} in slots j, j+1 of half `half`
 struct AdjStep {
     int par, half, j, n;
@@ -101,47 +104,40 @@ __global__ __launch_bounds__(256) void k_adj_diff(const DiffJob *__restrict__ jo
     }
 }
 
-// Passes 1 and 2 take one wave per unit: a run of up to 64 slab points of one
-// axis along x (the x slab points of one row, or 64 points of a y- or z-slab
-// row), so that the lanes read consecutive addresses.  Returns the lane's
-// shot, axis and point.
-__device__ __forceinline__ bool slab_unit(const AdjShot *__restrict__ A, const int *__restrict__ wave_shot, int nwave,
-                                          int &sh, int &d, int &x, int &y, int &z, int &k) {
-    const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    const int lane = (int)(threadIdx.x & 63);
-    if (w >= nwave) return false;
-    sh = wave_shot[w];
-    const AdjShot &a = A[sh];
-    int u = w - a.ubase;
-    d = 0;
-    while (d < 3 && u >= a.ucnt[d]) u -= a.ucnt[d++];
-    if (d == 3) return false;
-    const DevShot &s = a.s;
-    const int ch = u % a.uch[d], row = u / a.uch[d];
+// Passes 1 and 2 take one thread per slab point: a block holds 256 consecutive
+// points of one shot's axis (the slab points of axis d in the order x fastest,
+// then y, then z, with the coordinate along d running over the slab positions).
+__device__ __forceinline__ bool slab_point(const AdjShot *__restrict__ A, const SlabBlock *__restrict__ blk, int &sh,
+                                           int &d, int &x, int &y, int &z, int &k) {
+    const SlabBlock b = blk[blockIdx.x];
+    sh = b.shot_axis >> 2;
+    d = b.shot_axis & 3;
+    const DevShot &s = A[sh].s;
     const int lo = s.Llo[d], hi = s.Lhi[d];
+    const int t = b.t0 + (int)threadIdx.x;
     if (d == 0) {
-        const int is = ch * 64 + lane;
-        if (is >= s.LX) return false;
+        const int is = t % s.LX, r = t / s.LX;
+        y = r % s.ny;
+        z = r / s.ny;
         x = is < lo ? is : s.nx - hi + (is - lo);
-        y = row % s.ny;
-        z = row / s.ny;
         k = x;
-        return true;
+        return z < s.nz;
     }
-    x = ch * 64 + lane;
-    if (x >= s.nx) return false;
+    x = t % s.nx;
+    const int r = t / s.nx;
     if (d == 1) {
-        const int js = row % s.LY;
-        z = row / s.LY;
+        const int js = r % s.LY;
+        z = r / s.LY;
         y = js < lo ? js : s.ny - hi + (js - lo);
         k = y;
     } else {
-        y = row % s.ny;
-        const int ks = row / s.ny;
+        y = r % s.ny;
+        const int ks = r / s.ny;
         z = ks < lo ? ks : s.nz - hi + (ks - lo);
         k = z;
+        return ks < s.LZ;
     }
-    return true;
+    return z < s.nz;
 }
 
 // whether coordinate c (possibly outside [0, n)) lies in a slab of the axis
@@ -150,10 +146,10 @@ __device__ __forceinline__ bool slab_in_grid(int c, int n, int lo, int hi) {
 }
 
 // pass 1 on slab points: the zeta adjoint, E_d and K_d
-__global__ __launch_bounds__(256) void k_adj_p1(const AdjShot *__restrict__ A, const int *__restrict__ wave_shot,
-                                                int nwave, AdjStep st) {
+__global__ __launch_bounds__(256) void k_adj_p1(const AdjShot *__restrict__ A, const SlabBlock *__restrict__ blk,
+                                                AdjStep st) {
     int sh, d, x, y, z, k;
-    if (!slab_unit(A, wave_shot, nwave, sh, d, x, y, z, k)) return;
+    if (!slab_point(A, blk, sh, d, x, y, z, k)) return;
     const AdjShot &a = A[sh];
     const DevShot &s = a.s;
     const long i = fidx(s, x, y, z);
@@ -169,10 +165,10 @@ __global__ __launch_bounds__(256) void k_adj_p1(const AdjShot *__restrict__ A, c
 
 // pass 2 on slab points: the psi adjoint and W_d = dkinv E_d + a (psi_b - D1_d E_d),
 // E_d being Lbar = mu^{n+1} at the taps outside the slab
-__global__ __launch_bounds__(256) void k_adj_p2(const AdjShot *__restrict__ A, const int *__restrict__ wave_shot,
-                                                int nwave, AdjStep st) {
+__global__ __launch_bounds__(256) void k_adj_p2(const AdjShot *__restrict__ A, const SlabBlock *__restrict__ blk,
+                                                AdjStep st) {
     int sh, d, x, y, z, k;
-    if (!slab_unit(A, wave_shot, nwave, sh, d, x, y, z, k)) return;
+    if (!slab_point(A, blk, sh, d, x, y, z, k)) return;
     const AdjShot &a = A[sh];
     const DevShot &s = a.s;
     const int n = coord_n(s, d), lo = s.Llo[d], hi = s.Lhi[d];
@@ -295,20 +291,23 @@ static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
     } while (0)
 
 namespace {
-// waves of passes 1, 2 and blocks of pass 3 of one shot
+// blocks of passes 1, 2 (slab points) and of pass 3 of one shot
 struct AdjCounts {
-    int uch[3], ucnt[3], btx, bty;
-    long waves() const { return (long)ucnt[0] + ucnt[1] + ucnt[2]; }
+    long slab[3];   // slab points per axis
+    int btx, bty;
+    long slab_blocks() const {
+        long b = 0;
+        for (int d = 0; d < 3; ++d) b += (slab[d] + 255) / 256;
+        return b;
+    }
     long blocks(const ShotH &s) const { return (long)btx * bty * s.nz; }
 };
 static AdjCounts adj_counts(const ShotH &s) {
     AdjCounts c;
     const int cx = (s.nx + 63) / 64;
-    c.uch[0] = (s.LX + 63) / 64;
-    c.uch[1] = c.uch[2] = cx;
-    c.ucnt[0] = s.LX > 0 ? s.ny * s.nz * c.uch[0] : 0;
-    c.ucnt[1] = s.LY > 0 ? s.LY * s.nz * cx : 0;
-    c.ucnt[2] = s.LZ > 0 ? s.ny * s.LZ * cx : 0;
+    c.slab[0] = (long)s.LX * s.ny * s.nz;
+    c.slab[1] = (long)s.nx * s.LY * s.nz;
+    c.slab[2] = (long)s.nx * s.ny * s.LZ;
     c.btx = cx;
     c.bty = (s.ny + 3) / 4;
     return c;
@@ -318,8 +317,8 @@ struct AdjLayout {
     size_t ck = 0, seg = 0, mu[2] = {}, psib[3] = {}, zetab[3] = {}, E[3] = {}, K[3] = {}, W[3] = {};
     size_t gstart = 0, ridx = 0;   // receivers grouped by location (k_adj_resid)
     // tables of a sweep over every shot of the context (those of a sweep's first shot are used):
-    // AdjShot entries, level-copy jobs, checkpoint-restore jobs, wave -> shot and block -> shot maps
-    size_t tab = 0, jobs = 0, rjobs = 0, wmap = 0, bmap = 0;
+    // AdjShot entries, increment jobs, checkpoint-restore jobs, the slab-pass and pass-3 block tables
+    size_t tab = 0, jobs = 0, rjobs = 0, smap = 0, bmap = 0;
     size_t total = 0;
     int nck = 0;   // checkpoint slots
 };
@@ -336,10 +335,10 @@ static AdjLayout adj_layout(const fdtd_ctx *ctx, const ShotH &s, int every, int 
         return o;
     };
     const size_t nctx = ctx->shots.size();
-    long waves = 0, blocks = 0;
+    long sblocks = 0, blocks = 0;
     for (const ShotH &t : ctx->shots) {
         const AdjCounts c = adj_counts(t);
-        waves += c.waves();
+        sblocks += c.slab_blocks();
         blocks += c.blocks(t);
     }
     L.nck = nslots;
@@ -360,7 +359,7 @@ static AdjLayout adj_layout(const fdtd_ctx *ctx, const ShotH &s, int every, int 
     L.tab = take(sizeof(AdjShot) * nctx);
     L.jobs = take(sizeof(DiffJob) * (size_t)(2 * (every + 1) * 2) * nctx);
     L.rjobs = take(sizeof(CopyJob) * (size_t)L.nck * 2 * 8 * nctx);
-    L.wmap = take(sizeof(int) * (size_t)std::max(waves, 1L));
+    L.smap = take(sizeof(SlabBlock) * (size_t)std::max(sblocks, 1L));
     L.bmap = take(sizeof(int) * (size_t)std::max(blocks, 1L));
     L.total = off;
     return L;
@@ -433,8 +432,9 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
     std::vector<AdjShot> tab(nsh);
     std::vector<DiffJob> jobs((size_t)2 * (every + 1) * 2 * nsh);
     std::vector<CopyJob> rjobs((size_t)nck * 2 * 8 * nsh);
-    std::vector<int> wmap, bmap;
-    int ubase = 0, bbase = 0, maxg = 0;
+    std::vector<SlabBlock> smap;
+    std::vector<int> bmap;
+    int bbase = 0, maxg = 0;
     long maxrows = 0, maxck = 0;
     for (int q = 0; q < nsh; ++q) {
         const ShotH &s = ctx->shots[sh[q]];
@@ -501,13 +501,8 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
         maxg = std::max(maxg, a.ngroups);
         // wave units of passes 1, 2 and blocks of pass 3
         const AdjCounts cnt = adj_counts(s);
-        for (int d = 0; d < 3; ++d) {
-            a.uch[d] = cnt.uch[d];
-            a.ucnt[d] = cnt.ucnt[d];
-        }
-        a.ubase = ubase;
-        ubase += (int)cnt.waves();
-        wmap.insert(wmap.end(), (size_t)cnt.waves(), q);
+        for (int d = 0; d < 3; ++d)
+            for (long t0 = 0; t0 < cnt.slab[d]; t0 += 256) smap.push_back(SlabBlock{q * 4 + d, (int)t0});
         a.btx = cnt.btx;
         a.bty = cnt.bty;
         a.bbase = bbase;
@@ -556,13 +551,16 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
     const AdjShot *tab_d = (const AdjShot *)(s0h.ck_buf + L0.tab);
     const DiffJob *jobs_d = (const DiffJob *)(s0h.ck_buf + L0.jobs);
     const CopyJob *rjobs_d = (const CopyJob *)(s0h.ck_buf + L0.rjobs);
-    const int *wmap_d = (const int *)(s0h.ck_buf + L0.wmap), *bmap_d = (const int *)(s0h.ck_buf + L0.bmap);
+    const SlabBlock *smap_d = (const SlabBlock *)(s0h.ck_buf + L0.smap);
+    const int *bmap_d = (const int *)(s0h.ck_buf + L0.bmap);
+    const unsigned nslab = (unsigned)smap.size();
     AHIP(ctx, hipMemcpyAsync((void *)tab_d, tab.data(), sizeof(AdjShot) * nsh, hipMemcpyHostToDevice, st));
     AHIP(ctx, hipMemcpyAsync((void *)jobs_d, jobs.data(), sizeof(DiffJob) * jobs.size(), hipMemcpyHostToDevice, st));
     AHIP(ctx, hipMemcpyAsync((void *)rjobs_d, rjobs.data(), sizeof(CopyJob) * rjobs.size(), hipMemcpyHostToDevice,
                              st));
-    if (!wmap.empty())
-        AHIP(ctx, hipMemcpyAsync((void *)wmap_d, wmap.data(), sizeof(int) * wmap.size(), hipMemcpyHostToDevice, st));
+    if (!smap.empty())
+        AHIP(ctx, hipMemcpyAsync((void *)smap_d, smap.data(), sizeof(SlabBlock) * smap.size(), hipMemcpyHostToDevice,
+                                 st));
     AHIP(ctx, hipMemcpyAsync((void *)bmap_d, bmap.data(), sizeof(int) * bmap.size(), hipMemcpyHostToDevice, st));
     AHIP(ctx, hipStreamSynchronize(st));
     // e of the newest level (in buffer qb) into slot j of half b, every shot in one launch
@@ -612,11 +610,9 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
         for (int n = s1 - 1; n >= s0; --n) {
             const AdjStep as{par, b, n - s0, n};
             if (maxg > 0) hipLaunchKernelGGL(k_adj_resid, dim3((maxg + 255) / 256, nsh), dim3(256), 0, sa, tab_d, as);
-            if (ubase > 0) {
-                hipLaunchKernelGGL(k_adj_p1, dim3((unsigned)((ubase + 3) / 4)), dim3(256), 0, sa, tab_d, wmap_d, ubase,
-                                   as);
-                hipLaunchKernelGGL(k_adj_p2, dim3((unsigned)((ubase + 3) / 4)), dim3(256), 0, sa, tab_d, wmap_d, ubase,
-                                   as);
+            if (nslab > 0) {
+                hipLaunchKernelGGL(k_adj_p1, dim3(nslab), dim3(256), 0, sa, tab_d, smap_d, as);
+                hipLaunchKernelGGL(k_adj_p2, dim3(nslab), dim3(256), 0, sa, tab_d, smap_d, as);
             }
             hipLaunchKernelGGL(k_adj_p3, dim3((unsigned)bbase), dim3(256), 0, sa, tab_d, bmap_d, as);
             par ^= 1;
