@@ -162,3 +162,17 @@ def test_adjoint_state_errors():
     with pytest.raises(FDTDError):          # forward not run yet
         p.adjoint(0, 10, torch.zeros(10, len(w.rec)))
     p.close()
+    # batched sweep: every shot needs checkpointing, all with one interval
+    q = Propagator([Shot(n=w.n, h=w.h, dt=w.dt, cpml=w.cpml)] * 2)
+    for k in range(2):
+        q.set_velocity(k, torch.from_numpy(w.v.astype(np.float32)).cuda())
+        q.set_receivers(k, w.rec)
+    q.set_checkpointing(0, 5, 10)
+    q.step(10)
+    r = [torch.zeros(10, len(w.rec)) for _ in range(2)]
+    with pytest.raises(FDTDError, match="ESTATE"):       # shot 1 has no checkpointing
+        q.adjoint_all(10, r)
+    q.set_checkpointing(1, 2, 10)
+    with pytest.raises(FDTDError, match="EINVAL"):       # two intervals
+        q.adjoint_all(10, r)
+    q.close()
