@@ -128,7 +128,8 @@ struct WorkItem {
 
 // Work item of the band kernel: shot, band box, x tile, y tile, z chunk.
 #define BAND_TX 32
-#define BAND_TY 8
+#define BAND_TY 8          // tile rows (BAND_TX x BAND_TY threads), and
+#define BAND_TY_TALL 16    // those of the taller tiles of large single-shot contexts
 struct BandItem {
     int shot, box, tx, ty, zc, pad0, pad1, pad2;
 };
@@ -204,22 +205,27 @@ __host__ __device__ inline int band_xtiles(int nx, int Llo, int Lhi, int k, int 
     return nlo + nhi;
 }
 
-// LDS plane of a band-kernel tile: its BAND_TX x BAND_TY points and a 4-cell
-// halo on each side along x and y (corners unused), slot (column c, row r) =
-// r * kBandLW + c, plus a dummy slot for lanes without a second halo value.
-constexpr int kBandLW = BAND_TX + 2 * FDTD_R, kBandLH = BAND_TY + 2 * FDTD_R;
-constexpr int kBandLB = kBandLW * kBandLH + 1;
-// The halo value lane t of a tile stages: k = 0 one of the 4 rows above or
-// below the tile (every lane), k = 1 one of the 4 columns left or right of it
-// (lanes below 2 * 4 * BAND_TY).  (c, r): its slot; c = -1 when the lane has none.
-__host__ __device__ inline void band_halo(int t, int k, int &c, int &r) {
+// LDS plane of a band-kernel tile of ty rows: its BAND_TX x ty points and a
+// 4-cell halo on each side along x and y (corners unused), slot (column c,
+// row r) = r * kBandLW + c, plus a dummy slot for lanes without a halo value.
+constexpr int kBandLW = BAND_TX + 2 * FDTD_R;
+__host__ __device__ constexpr int band_lds(int ty) { return kBandLW * (ty + 2 * FDTD_R) + 1; }
+// The halo value lane t of a tile of ty rows stages: k = 0 one of the 4 rows
+// above or below the tile (lanes below 2 * 4 * BAND_TX), k = 1 one of the 4
+// columns left or right of it (lanes below 2 * 4 * ty).  (c, r): its slot;
+// c = -1 when the lane has none.
+__host__ __device__ inline void band_halo(int t, int k, int ty, int &c, int &r) {
     if (k == 0) {
+        if (t >= 2 * FDTD_R * BAND_TX) {
+            c = r = -1;
+            return;
+        }
         const int q = t / BAND_TX;
-        r = q < FDTD_R ? q : q + BAND_TY;
+        r = q < FDTD_R ? q : q + ty;
         c = FDTD_R + t % BAND_TX;
         return;
     }
-    if (t >= 2 * FDTD_R * BAND_TY) {
+    if (t >= 2 * FDTD_R * ty) {
         c = r = -1;
         return;
     }

@@ -13,7 +13,7 @@ constexpr int kOFF = 128;   // leading pad of every field (elements)
 constexpr int kTYMAX = 64;  // tallest y tile (rows) a kernel may overhang
 constexpr int kMaxRec = 65536;  // receivers per shot with temporal blocking
 constexpr int kTimingClasses = 6;   // update, psi, record, exchange, band update, temporal block
-constexpr int kBandTX = BAND_TX, kBandTY = BAND_TY, kBandZ = 32;   // band-kernel tile and z chunk
+constexpr int kBandTX = BAND_TX, kBandZ = 32;   // band-kernel tile width and z chunk
 constexpr int kCUs = 256;   // compute units of an MI355X (the default z-march plan shares them)
 constexpr long kSmallShot = 150L * 150 * 150;   // a lone shot below this many points runs naive by default
 
@@ -91,6 +91,7 @@ struct fdtd_ctx {
     };
     std::vector<Group> groups;
     int storage = 0;
+    int band_ty = BAND_TY;    // band-kernel tile rows: BAND_TY_TALL for one shot of 2^27 points or more
     int sentinel_every = 0;   // > 0: scan the newest level for NaN/Inf after every such step (scratch slot 3)
     int iu = 0;         // level buffer holding u^n
     int ium1 = 1;       // level buffer holding u^{n-1} (FP32) -- 16-bit keeps d^n in its own buffer

@@ -14,9 +14,9 @@ void fdtd_launch_naive(int stor, const DevShot *d_shots, int shot, int nx, int N
 // 64 x 8 ry points, 2: 128 x 8 ry)
 void fdtd_launch_zmarch(int stor, const DevShot *d_shots, const WorkItem *work, int nwork, int ry, int cols,
                         const Roles &R, int zchunk, const int *stepc, hipStream_t st);
-// band points (tiles of every box kind in one list)
+// band points (tiles of every box kind in one list; ty = BAND_TY or BAND_TY_TALL rows per tile)
 void fdtd_launch_band(int stor, const DevShot *d_shots, const BandItem *work, int nwork, const Roles &R, int zchunk,
-                      const int *stepc, hipStream_t st);
+                      const int *stepc, int ty, hipStream_t st);
 void fdtd_launch_record(int stor, const DevShot *d_shots, int nshots, const Roles &R, int *stepc, hipStream_t st);
 // temporal blocking: args points to a host TBArgs (kernels_tblock.hip); K = 2 or 4
 void fdtd_launch_tblock(const DevShot *d_shots, const WorkItem *work, int nwork, int K, const void *args, int zchunk,

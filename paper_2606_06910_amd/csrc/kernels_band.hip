@@ -57,9 +57,10 @@ __device__ __forceinline__ void axis_point(const DevShot &s, int d, int c, AxisP
 //    from a u^n queue that reaches z + 8.
 // Each layer point is advanced once, by the tile that owns it, with the psi
 // pass's operations, so the bits do not change.
-template <typename T, int KIND, bool FUSE>
+template <typename T, int KIND, bool FUSE, int TY>
 __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, const BandItem wi, const Roles &R,
                                           int zchunk, const int *__restrict__ stepc, float *Lds) {
+    constexpr int LB = band_lds(TY);
     constexpr bool HAS_Y = KIND <= 1, HAS_Z = KIND == 0;
     constexpr bool FZ = FUSE && HAS_Z;   // psi_z advanced in the z queue
     constexpr int QN = FZ ? 13 : 9;      // u^n queue: planes z - 4 .. z + QN - 5
@@ -71,7 +72,7 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
     band_xtiles(s.nx, s.Llo[0], s.Lhi[0], wi.box, blo[0], bhi[0], wi.tx, &x0, &x1);
     const int lx = (int)(threadIdx.x % BAND_TX), ly = (int)(threadIdx.x / BAND_TX);
     const int x = x0 + lx;
-    const int yt = blo[1] + wi.ty * BAND_TY;   // first row of the tile
+    const int yt = blo[1] + wi.ty * TY;   // first row of the tile
     const int y = yt + ly;
     // z boxes are walked whole (their tile list has one chunk), the others in chunks
     const int za = KIND == 0 ? blo[2] : blo[2] + wi.zc * zchunk;
@@ -119,11 +120,11 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
     // holding the point (x0 - 4 + c, yt - 4 + r)
     const int own = (ly + FDTD_R) * kBandLW + lx + FDTD_R;
     int hc1, hr1, hc2, hr2;
-    band_halo((int)threadIdx.x, 0, hc1, hr1);
-    band_halo((int)threadIdx.x, 1, hc2, hr2);
-    const int hslot1 = hr1 * kBandLW + hc1;
-    const uint32_t hoff1 = lane_off(x0 - FDTD_R + hc1, yt - FDTD_R + hr1);
-    const int hslot2 = hc2 >= 0 ? hr2 * kBandLW + hc2 : kBandLB - 1;
+    band_halo((int)threadIdx.x, 0, TY, hc1, hr1);
+    band_halo((int)threadIdx.x, 1, TY, hc2, hr2);
+    const int hslot1 = hc1 >= 0 ? hr1 * kBandLW + hc1 : LB - 1;
+    const uint32_t hoff1 = hc1 >= 0 ? lane_off(x0 - FDTD_R + hc1, yt - FDTD_R + hr1) : kBufSkip;
+    const int hslot2 = hc2 >= 0 ? hr2 * kBandLW + hc2 : LB - 1;
     const uint32_t hoff2 = hc2 >= 0 ? lane_off(x0 - FDTD_R + hc2, yt - FDTD_R + hr2) : kBufSkip;
 
     AxisPt AX, AY;
@@ -408,7 +409,7 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
     int buf = 0;
 #pragma unroll 1
     for (int z = za; z < zb; ++z) {
-        float *Lp = Lds + buf * kBandLB;
+        float *Lp = Lds + buf * LB;
         Lp[own] = q[4];
         Lp[hslot1] = h1;
         Lp[hslot2] = h2;
@@ -431,34 +432,40 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
 }
 
 // one launch for the tiles of all three kinds (a workgroup's kind is that of
-// its box), so that they run side by side without extra streams
-template <typename T>
-__global__ __launch_bounds__(256) void k_band(const DevShot *__restrict__ shots, const BandItem *__restrict__ work,
-                                              Roles R, int zchunk, const int *__restrict__ stepc) {
-    __shared__ float Lds[2 * kBandLB];
+// its box), so that they run side by side without extra streams; tiles of TY rows
+template <typename T, int TY>
+__global__ __launch_bounds__(BAND_TX *TY) void k_band(const DevShot *__restrict__ shots,
+                                                     const BandItem *__restrict__ work, Roles R, int zchunk,
+                                                     const int *__restrict__ stepc) {
+    __shared__ float Lds[2 * band_lds(TY)];
     const BandItem wi = work[blockIdx.x];
     const int kind = wi.box >> 1;
     if (shots[wi.shot].fused) {
-        if (kind == 0) band_tile<T, 0, true>(shots, wi, R, zchunk, stepc, Lds);
-        else if (kind == 1) band_tile<T, 1, true>(shots, wi, R, zchunk, stepc, Lds);
-        else band_tile<T, 2, true>(shots, wi, R, zchunk, stepc, Lds);
+        if (kind == 0) band_tile<T, 0, true, TY>(shots, wi, R, zchunk, stepc, Lds);
+        else if (kind == 1) band_tile<T, 1, true, TY>(shots, wi, R, zchunk, stepc, Lds);
+        else band_tile<T, 2, true, TY>(shots, wi, R, zchunk, stepc, Lds);
     } else {
-        if (kind == 0) band_tile<T, 0, false>(shots, wi, R, zchunk, stepc, Lds);
-        else if (kind == 1) band_tile<T, 1, false>(shots, wi, R, zchunk, stepc, Lds);
-        else band_tile<T, 2, false>(shots, wi, R, zchunk, stepc, Lds);
+        if (kind == 0) band_tile<T, 0, false, TY>(shots, wi, R, zchunk, stepc, Lds);
+        else if (kind == 1) band_tile<T, 1, false, TY>(shots, wi, R, zchunk, stepc, Lds);
+        else band_tile<T, 2, false, TY>(shots, wi, R, zchunk, stepc, Lds);
     }
 }
 
 template <typename T>
 static void launch_band_t(const DevShot *d_shots, const BandItem *work, int nwork, const Roles &R, int zchunk,
-                          const int *stepc, hipStream_t st) {
+                          const int *stepc, int ty, hipStream_t st) {
     if (nwork <= 0) return;
-    hipLaunchKernelGGL(k_band<T>, dim3(nwork), dim3(256), 0, st, d_shots, work, R, zchunk, stepc);
+    if (ty == BAND_TY_TALL)
+        hipLaunchKernelGGL((k_band<T, BAND_TY_TALL>), dim3(nwork), dim3(BAND_TX * BAND_TY_TALL), 0, st, d_shots, work,
+                           R, zchunk, stepc);
+    else
+        hipLaunchKernelGGL((k_band<T, BAND_TY>), dim3(nwork), dim3(BAND_TX * BAND_TY), 0, st, d_shots, work, R,
+                           zchunk, stepc);
 }
 
 void fdtd_launch_band(int stor, const DevShot *d_shots, const BandItem *work, int nwork, const Roles &R, int zchunk,
-                      const int *stepc, hipStream_t st) {
-    if (stor == 1) launch_band_t<_Float16>(d_shots, work, nwork, R, zchunk, stepc, st);
-    else if (stor == 2) launch_band_t<__bf16>(d_shots, work, nwork, R, zchunk, stepc, st);
-    else launch_band_t<float>(d_shots, work, nwork, R, zchunk, stepc, st);
+                      const int *stepc, int ty, hipStream_t st) {
+    if (stor == 1) launch_band_t<_Float16>(d_shots, work, nwork, R, zchunk, stepc, ty, st);
+    else if (stor == 2) launch_band_t<__bf16>(d_shots, work, nwork, R, zchunk, stepc, ty, st);
+    else launch_band_t<float>(d_shots, work, nwork, R, zchunk, stepc, ty, st);
 }

@@ -6,7 +6,7 @@
 // in the same tile row as each band point that reads it, and every z-layer
 // point in the same z-box walk as its readers, with the walk's first planes
 // outside the layers and at least 5 planes deep.  And the LDS staging of every
-// tile: each x and y stencil tap of each of its points is found in the slot that
+// tile (tiles of BAND_TY rows in even cases, BAND_TY_TALL in odd ones): each x and y stencil tap of each of its points is found in the slot that
 // the tile's lanes fill with that position (their own u^n, or a halo value from
 // band_halo), loaded from a position the field buffer holds (rows within the
 // frame of fy = max(4, ext + 4), columns within 4 of the grid).  Prints
@@ -43,30 +43,31 @@ struct Table {
 // every tap of every point of the tile is the position its slot is filled
 // with, from a position inside the field buffer's rows [-fy, ny + fy) and
 // columns [-4, nx + 4).
-bool staging_ok(const int *n, int fy, int x0, int x1, int yt, int yend) {
+bool staging_ok(const int *n, int fy, int x0, int x1, int yt, int yend, int ty) {
     struct Fill {
         int x, y;
         bool held;
     };
-    std::vector<Fill> slot(kBandLB, Fill{0, 0, false});
-    std::vector<bool> set(kBandLB, false);
+    const int LB = band_lds(ty);
+    std::vector<Fill> slot(LB, Fill{0, 0, false});
+    std::vector<bool> set(LB, false);
     auto held = [&](int xp, int yp) { return xp >= -4 && xp < n[0] + 4 && yp >= -fy && yp < n[1] + fy; };
     auto put = [&](int c, int r) {
         const int i = r * kBandLW + c, xp = x0 - FDTD_R + c, yp = yt - FDTD_R + r;
-        if (i < 0 || i >= kBandLB - 1) return false;
+        if (i < 0 || i >= LB - 1) return false;
         slot[i] = Fill{xp, yp, held(xp, yp)};
         set[i] = true;
         return true;
     };
-    for (int t = 0; t < BAND_TX * BAND_TY; ++t) {
+    for (int t = 0; t < BAND_TX * ty; ++t) {
         if (!put(FDTD_R + t % BAND_TX, FDTD_R + t / BAND_TX)) return false;
         for (int k = 0; k < 2; ++k) {
             int c, r;
-            band_halo(t, k, c, r);
+            band_halo(t, k, ty, c, r);
             if (c >= 0 && !put(c, r)) return false;
         }
     }
-    for (int t = 0; t < BAND_TX * BAND_TY; ++t) {
+    for (int t = 0; t < BAND_TX * ty; ++t) {
         const int lx = t % BAND_TX, ly = t / BAND_TX, x = x0 + lx, y = yt + ly;
         if (x >= x1 || y >= yend) continue;
         const int own = (ly + FDTD_R) * kBandLW + lx + FDTD_R;
@@ -88,6 +89,7 @@ int main(int argc, char **argv) {
     srand(7);
     long nf = 0;
     for (int it = 0; it < cases; ++it) {
+        const int th = it % 2 ? BAND_TY_TALL : BAND_TY;   // tile rows: both heights the library uses
         int n[3], lo[3], hi[3], gh[3] = {0, 0, 0};
         for (int d = 0; d < 3; ++d) {
             n[d] = 9 + rand() % 60;
@@ -112,7 +114,7 @@ int main(int argc, char **argv) {
             if (bhi[0] <= blo[0] || bhi[1] <= blo[1] || bhi[2] <= blo[2]) continue;
             int x0, x1;
             const int ntx = band_xtiles(n[0], lo[0], hi[0], b, blo[0], bhi[0], 0, &x0, &x1);
-            const int nty = (bhi[1] - blo[1] + BAND_TY - 1) / BAND_TY;
+            const int nty = (bhi[1] - blo[1] + th - 1) / th;
             const int nzc = b < 2 ? 1 : (bhi[2] - blo[2] + 31) / 32;
             for (int zc = 0; zc < nzc; ++zc)
                 for (int ty = 0; ty < nty; ++ty)
@@ -122,14 +124,14 @@ int main(int argc, char **argv) {
                             printf("FAIL tile width %d\n", x1 - x0);
                             return 1;
                         }
-                        if (!staging_ok(n, gh[1] ? ext + 4 : 4, x0, x1, blo[1] + ty * BAND_TY, bhi[1])) {
+                        if (!staging_ok(n, gh[1] ? ext + 4 : 4, x0, x1, blo[1] + ty * th, bhi[1], th)) {
                             printf("FAIL LDS staging of tile box %d tx %d ty %d\n", b, tx, ty);
                             return 1;
                         }
                         const int za = b < 2 ? blo[2] : blo[2] + 32 * zc, zb = b < 2 ? bhi[2] : std::min(za + 32, bhi[2]);
                         for (int z = za; z < zb; ++z)
-                            for (int r = 0; r < BAND_TY; ++r) {
-                                const int y = blo[1] + ty * BAND_TY + r;
+                            for (int r = 0; r < th; ++r) {
+                                const int y = blo[1] + ty * th + r;
                                 if (y >= bhi[1]) continue;
                                 for (int x = x0; x < x1; ++x) {
                                     Owner &w = own.at(x, y, z);
