@@ -195,8 +195,9 @@ int fdtd_set_sentinel(fdtd_ctx *ctx, int32_t every);
 
 /* Size in bytes of the device buffer fdtd_adjoint needs for one shot with
  * checkpoints every `every` steps over nt steps (checkpoints, two segments of
- * recomputed levels, adjoint state, the receivers grouped by location, and
- * the tables of a sweep over all shots of this context).  It depends on the shot's receiver count: set the receivers
+ * recomputed levels, adjoint state with a ring of up to 17 adjoint levels,
+ * the receivers grouped by location, and the tables of a sweep over all
+ * shots of this context).  It depends on the shot's receiver count: set the receivers
  * first (fdtd_adjoint returns ENOMEM if they outgrew the buffer since). */
 int fdtd_adjoint_workspace_size(const fdtd_ctx *ctx, int32_t shot, int32_t every, int32_t nt, size_t *bytes);
 

@@ -20,8 +20,11 @@
 // dJ/dv = (2/v) sum_n lambda^{n+1} (u^{n+1} - 2u^n + u^{n-1})
 //       = 2 dt / (m sqrt(m)) sum_n mu^{n+1} (e^{n+1} - e^n),  e^n = u^n - u^{n-1},
 // accumulated in FP64.  Forward levels are recomputed per segment from
-// checkpoints saved every `every` steps, and the increments e kept (FP32).  One sweep covers one shot or every
-// shot of the context: each pass is one launch over all of them.
+// checkpoints saved every `every` steps, and the increments e kept (FP32).
+// The mu levels live in a ring of G + 1 slots (G <= 16 steps), so that
+// the FP64 accumulator is read and written once per G reverse steps, by a
+// pass over the last G levels, and not by every step.  One sweep covers one
+// shot or every shot of the context: each pass is one launch over all of them.
 #include "fdtd_host.hpp"
 #include "fdtd_launch.hpp"
 
@@ -36,7 +39,9 @@
 // Adjoint state of one shot of a sweep (device array, one entry per shot).
 struct AdjShot {
     DevShot s;               // the forward descriptor (geometry, m, profiles, coefficients)
-    float *mu[2];            // mu^{n+1} = mu[par], mu^{n+2} in / mu^n out = mu[par ^ 1] (origin-adjusted)
+    float *mu;               // ring slot 0 of the mu levels (origin-adjusted); mu^n is in slot n mod mslots
+    long mstride;            // elements between ring slots
+    int mslots;              // ring slots: G + 1
     float *psib[3], *zetab[3];          // compact slab layouts (as psi)
     float *E[3];             // origin-adjusted full-grid arrays, written at slab points of axis d only:
     float *K[3];             //   E_d, kinv E_d and W_d = dkinv E_d + a (psi_b - D1_d E_d);
@@ -45,11 +50,11 @@ struct AdjShot {
     long lstride;            // elements between slots
     int nslot;               // slots per half: every + 1
     float inv_scale;         // 1 / storage scale of the fields
-    double *G;               // dense accumulator sum mu^{n+1} (u^{n+1} - 2u^n + u^{n-1})
+    double *G;               // dense accumulator sum mu^{n+1} (u^{n+1} - 2u^n + u^{n-1}), [nz][ny][nx]
     const float *resid;      // dJ/dtraces [nt][nrec]
     const int *gstart, *ridx;   // receivers grouped by location (k_adj_resid)
     int ngroups, nrec;
-    int bbase, btx, bty;          // pass 3: first block, tiles along x and y
+    int bbase, btx, bty;          // pass 3 and the gradient pass: first block, tiles along x and y
 };
 // A block of passes 1, 2 or 3 finds its shot (and for 1, 2 its axis and first
 // slab point) in a table indexed by block (scalar loads), not by searching.
@@ -57,14 +62,22 @@ struct SlabBlock {
     int shot_axis;   // shot of the sweep * 4 + axis
     int t0;          // first slab point of the block along that axis
 };
-// one reverse step: mu^{n+1} = mu[par]; e^n, e^{n+1} in slots j, j+1 of half `half`
+// one reverse step n: mu^n goes to ring slot m0, mu^{n+1} and mu^{n+2} are in
+// slots m1 and m2 (n, n + 1, n + 2 mod the ring size)
 struct AdjStep {
-    int par, half, j, n;
+    int n, m0, m1, m2;
+};
+// gradient pass over reverse steps n_lo .. n_lo + cnt - 1 of the segment that
+// starts at step s0: e^n, e^{n+1} are in slots n - s0, n - s0 + 1 of half `half`
+struct AdjGrad {
+    int half, s0, n_lo, cnt;
 };
 
 __device__ __forceinline__ long fidx(const DevShot &s, int x, int y, int z) {
     return (long)z * s.S + (long)y * s.P + x;
 }
+
+__device__ __forceinline__ float *mu_slot(const AdjShot &a, int k) { return a.mu + (long)k * a.mstride; }
 
 // residual injection: one thread per distinct receiver location of shot
 // blockIdx.y; the residuals of the receivers there are summed in receiver
@@ -81,7 +94,7 @@ __global__ __launch_bounds__(256) void k_adj_resid(const AdjShot *__restrict__ A
     const long i = fidx(s, q[0], q[1], q[2]);
     float r = 0.0f;
     for (int k = k0; k < k1; ++k) r += row[a.ridx[k]];
-    float *mu = a.mu[st.par];
+    float *mu = mu_slot(a, st.m1);
     mu[i] = fmaf(s.m[i], r, mu[i]);
 }
 
@@ -153,7 +166,7 @@ __global__ __launch_bounds__(256) void k_adj_p1(const AdjShot *__restrict__ A, c
     const AdjShot &a = A[sh];
     const DevShot &s = a.s;
     const long i = fidx(s, x, y, z);
-    const float lb = a.mu[st.par][i];
+    const float lb = mu_slot(a, st.m1)[i];
     float *zb = &a.zetab[d][psi_index(s, d, x, y, z)];
     const float kinv = prof_at(s, d, 2, k);
     const float zt = *zb + lb;
@@ -174,7 +187,7 @@ __global__ __launch_bounds__(256) void k_adj_p2(const AdjShot *__restrict__ A, c
     const int n = coord_n(s, d), lo = s.Llo[d], hi = s.Lhi[d];
     const long i = fidx(s, x, y, z);
     const long stride = d == 0 ? 1 : (d == 1 ? s.P : s.S);
-    const float *E = a.E[d], *mu1 = a.mu[st.par];
+    const float *E = a.E[d], *mu1 = mu_slot(a, st.m1);
     float el[4], eh[4];
 #pragma unroll
     for (int l = 1; l <= 4; ++l) {
@@ -187,36 +200,49 @@ __global__ __launch_bounds__(256) void k_adj_p2(const AdjShot *__restrict__ A, c
     a.psib[d][pi] = prof_at(s, d, 0, k) * pt;
 }
 
-// Pass 3 on every point: mu^n and the gradient accumulation.  A block is a
-// 64 x 4 tile of one plane of one shot (one y row per wave).  Along an axis d
-// whose band the wave does not touch, the axis term is D2_d mu^{n+1}.  A wave
-// that touches it evaluates D2_d(K_d) - D1_d(W_d) for all its lanes, taking
-// K_d from its array at slab taps and mu^{n+1} at the others.  At a lane
-// outside the band no tap lies in the slab, so this is D2_d mu^{n+1} with the
-// same bits (the W_d taps are exact zeros).  The y and z tests are
-// wave-uniform and the x test is taken per 64-point tile.
+// The point of this thread in pass 3's and the gradient pass's block tiling
+// (a block is a 64 x 4 tile of one plane of one shot, one y row per wave);
+// false for threads past the grid.
+struct TilePoint {
+    int x, y, z, x0;
+};
+__device__ __forceinline__ bool tile_point(const AdjShot &a, int lb, TilePoint &p) {
+    const DevShot &s = a.s;
+    const int nxy = a.btx * a.bty;
+    p.z = lb / nxy;
+    const int r = lb - p.z * nxy;
+    if (p.z >= s.nz) return false;
+    const int by = r / a.btx, bx = r - by * a.btx;
+    p.x0 = bx * 64;
+    p.x = p.x0 + (int)(threadIdx.x & 63);
+    p.y = __builtin_amdgcn_readfirstlane(by * 4 + (int)(threadIdx.x >> 6));
+    return p.x < s.nx && p.y < s.ny;
+}
+
+// Pass 3 on every point: mu^n = 2 mu^{n+1} - mu^{n+2} + m sum_d t_d, each
+// point taking its taps from memory.  Along an axis d whose band the wave does
+// not touch, t_d = D2_d mu^{n+1}.  A wave that touches it evaluates
+// D2_d(K_d) - D1_d(W_d) for all its lanes, taking K_d from its array at slab
+// taps and mu^{n+1} at the others.  At a lane outside the band no tap lies in
+// the slab, so this is D2_d mu^{n+1} with the same bits (the W_d taps are
+// exact zeros).  The y and z tests are wave-uniform and the x test is taken
+// per 64-point tile.
 __global__ __launch_bounds__(256) void k_adj_p3(const AdjShot *__restrict__ A, const int *__restrict__ block_shot,
                                                 AdjStep st) {
     const int b = (int)blockIdx.x;
     const AdjShot &a = A[block_shot[b]];
     const DevShot &s = a.s;
-    const int lb = b - a.bbase, nxy = a.btx * a.bty;
-    const int z = lb / nxy, r = lb - z * nxy;
-    if (z >= s.nz) return;
-    const int by = r / a.btx, bx = r - by * a.btx;
-    const int x0 = bx * 64;
-    const int x = x0 + (int)(threadIdx.x & 63);
-    const int y = __builtin_amdgcn_readfirstlane(by * 4 + (int)(threadIdx.x >> 6));
-    if (x >= s.nx || y >= s.ny) return;
-    const int xe = min(x0 + 64, s.nx) - 1;   // last x of the tile
+    TilePoint p;
+    if (!tile_point(a, b - a.bbase, p)) return;
+    const int x = p.x, y = p.y, z = p.z;
+    const int xe = min(p.x0 + 64, s.nx) - 1;   // last x of the tile
     const long i = fidx(s, x, y, z);
     const int cc[3] = {x, y, z};
     const long stv[3] = {1, (long)s.P, (long)s.S};
     // the band of an axis is an interval at each end of the grid, so a tile meets it iff one of its end points lies in it
-    const bool touch[3] = {in_band(x0, s.nx, s.Llo[0], s.Lhi[0]) || in_band(xe, s.nx, s.Llo[0], s.Lhi[0]),
+    const bool touch[3] = {in_band(p.x0, s.nx, s.Llo[0], s.Lhi[0]) || in_band(xe, s.nx, s.Llo[0], s.Lhi[0]),
                            in_band(y, s.ny, s.Llo[1], s.Lhi[1]), in_band(z, s.nz, s.Llo[2], s.Lhi[2])};
-    const float *mu1 = a.mu[st.par];
-    float *mu2 = a.mu[st.par ^ 1];
+    const float *mu1 = mu_slot(a, st.m1);
     const float c = mu1[i];
     float t[3];
 #pragma unroll
@@ -246,13 +272,36 @@ __global__ __launch_bounds__(256) void k_adj_p3(const AdjShot *__restrict__ A, c
             t[d] = d2_axis(s.w2[d], kc, lo, hi) - d1_axis(s.w1[d], wl, wh);
         }
     }
-    const float out = leapfrog(s.m[i], (t[0] + t[1]) + t[2], c, mu2[i]);
-    // gradient: mu^{n+1} (e^{n+1} - e^n)
-    const float *e0 = a.lev + ((long)st.half * a.nslot + st.j) * a.lstride;
-    const double d2u = ((double)e0[i + a.lstride] - (double)e0[i]) * (double)a.inv_scale;
-    const long gi = ((long)z * s.ny + y) * s.nx + x;
-    a.G[gi] += (double)c * d2u;
-    mu2[i] = out;
+    mu_slot(a, st.m0)[i] = leapfrog(s.m[i], (t[0] + t[1]) + t[2], c, mu_slot(a, st.m2)[i]);
+}
+
+// Gradient pass over cnt reverse steps, taken in the sweep's order (n from
+// high to low): G += mu^{n+1} (e^{n+1} - e^n) / scale in FP64 at every point,
+// reading the accumulator once.  Same block tiling as pass 3.
+__global__ __launch_bounds__(256) void k_adj_grad(const AdjShot *__restrict__ A, const int *__restrict__ block_shot,
+                                                  AdjGrad g) {
+    const int b = (int)blockIdx.x;
+    const AdjShot &a = A[block_shot[b]];
+    const DevShot &s = a.s;
+    TilePoint p;
+    if (!tile_point(a, b - a.bbase, p)) return;
+    const long i = fidx(s, p.x, p.y, p.z);
+    const long gi = ((long)p.z * s.ny + p.y) * s.nx + p.x;
+    const float *e = a.lev + (long)g.half * a.nslot * a.lstride + i;
+    const double sc = (double)a.inv_scale;
+    const int top = g.n_lo + g.cnt - 1;
+    int ms = (top + 1) % a.mslots;   // ring slot of mu^{n+1}
+    float ehi = e[(long)(top - g.s0 + 1) * a.lstride];
+    double acc = a.G[gi];
+#pragma unroll 4
+    for (int n = top; n >= g.n_lo; --n) {
+        const float elo = e[(long)(n - g.s0) * a.lstride];
+        const float c = mu_slot(a, ms)[i];
+        acc += (double)c * (((double)ehi - (double)elo) * sc);
+        ehi = elo;
+        ms = ms == 0 ? a.mslots - 1 : ms - 1;
+    }
+    a.G[gi] = acc;
 }
 
 // dJ/dv = 2 G dt / (m sqrt(m))  (G sums mu = m lambda; v = sqrt(m) / dt)
@@ -291,7 +340,7 @@ static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
     } while (0)
 
 namespace {
-// blocks of passes 1, 2 (slab points) and of pass 3 of one shot
+// blocks of passes 1, 2 (slab points) and of pass 3 and the gradient pass of one shot
 struct AdjCounts {
     long slab[3];   // slab points per axis
     int btx, bty;
@@ -314,7 +363,7 @@ static AdjCounts adj_counts(const ShotH &s) {
 }
 
 struct AdjLayout {
-    size_t ck = 0, seg = 0, mu[2] = {}, psib[3] = {}, zetab[3] = {}, E[3] = {}, K[3] = {}, W[3] = {};
+    size_t ck = 0, seg = 0, mu = 0, psib[3] = {}, zetab[3] = {}, E[3] = {}, K[3] = {}, W[3] = {};
     size_t gstart = 0, ridx = 0;   // receivers grouped by location (k_adj_resid)
     // tables of a sweep over every shot of the context (those of a sweep's first shot are used):
     // AdjShot entries, increment jobs, checkpoint-restore jobs, the slab-pass and pass-3 block tables
@@ -326,6 +375,14 @@ struct AdjLayout {
 // The regions sit at offsets fixed by the buffer's checkpoint capacity
 // (nslots), never by the steps of one sweep: a sweep over fewer steps than
 // the forward checkpointed must not place its state over later checkpoints.
+// reverse steps per gradient pass (at most 16, a segment split evenly), and
+// the mu ring that holds their levels
+static int grad_chunk(int every) {
+    const int passes = (every + 15) / 16;
+    return (every + passes - 1) / passes;
+}
+static int mu_slots(int every) { return grad_chunk(every) + 1; }
+
 static AdjLayout adj_layout(const fdtd_ctx *ctx, const ShotH &s, int every, int nslots) {
     AdjLayout L;
     size_t off = 0;
@@ -344,8 +401,7 @@ static AdjLayout adj_layout(const fdtd_ctx *ctx, const ShotH &s, int every, int 
     L.nck = nslots;
     L.ck = take(fdtd_state_bytes(s) * (size_t)L.nck);
     L.seg = take(a256(s.elems * s.esz) * (size_t)(every + 1) * 2);   // two segments' increments
-    L.mu[0] = take(s.elems * 4);
-    L.mu[1] = take(s.elems * 4);
+    L.mu = take(a256(s.elems * 4) * (size_t)mu_slots(every));   // the ring of mu levels
     for (int d = 0; d < 3; ++d) {
         const size_t full = (s.Llo[d] + s.Lhi[d]) > 0 ? s.elems * 4 : 0;
         L.psib[d] = take(s.psi_elems[d] * 4);
@@ -443,10 +499,10 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
         AdjShot &a = tab[q];
         memset(&a, 0, sizeof a);
         a.s = ctx->hdesc[sh[q]];
-        for (int h = 0; h < 2; ++h) {
-            fdtd_launch_fill_zero(B + L.mu[h], a256(s.elems * 4), st);
-            a.mu[h] = (float *)origin4(s, B + L.mu[h]);
-        }
+        fdtd_launch_fill_zero(B + L.mu, a256(s.elems * 4) * (size_t)mu_slots(every), st);
+        a.mu = (float *)origin4(s, B + L.mu);
+        a.mstride = (long)(a256(s.elems * 4) / 4);
+        a.mslots = mu_slots(every);
         for (int d = 0; d < 3; ++d) {
             fdtd_launch_fill_zero(B + L.psib[d], a256(s.psi_elems[d] * 4), st);
             fdtd_launch_fill_zero(B + L.zetab[d], a256(s.psi_elems[d] * 4), st);
@@ -587,7 +643,7 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
         AHIP(ctx, hipEventRecord(ctx->ev_adj[4], st));   // the set-up above, before any sweep
         AHIP(ctx, hipStreamWaitEvent(sa, ctx->ev_adj[4], 0));
     }
-    int par = 0;
+    const int M = mu_slots(every), chunk = grad_chunk(every);
     for (int k = nck - 1; k >= 0; --k) {
         const int s0 = k * every, s1 = std::min(s0 + every, nt);
         const int b = k & 1;
@@ -606,16 +662,24 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
             AHIP(ctx, hipEventRecord(ctx->ev_adj[b], st));
             AHIP(ctx, hipStreamWaitEvent(sa, ctx->ev_adj[b], 0));
         }
-        // reverse sweep over the segment
+        // reverse sweep over the segment; after every `chunk` steps (and at the
+        // segment's start) the gradient pass folds the steps since the last one
+        // into G, while their mu^{n+1} are still in the ring (the ring holds the
+        // chunk's cnt + 1 <= M levels n .. n + cnt)
+        int top = s1 - 1;
         for (int n = s1 - 1; n >= s0; --n) {
-            const AdjStep as{par, b, n - s0, n};
+            const AdjStep as{n, n % M, (n + 1) % M, (n + 2) % M};
             if (maxg > 0) hipLaunchKernelGGL(k_adj_resid, dim3((maxg + 255) / 256, nsh), dim3(256), 0, sa, tab_d, as);
             if (nslab > 0) {
                 hipLaunchKernelGGL(k_adj_p1, dim3(nslab), dim3(256), 0, sa, tab_d, smap_d, as);
                 hipLaunchKernelGGL(k_adj_p2, dim3(nslab), dim3(256), 0, sa, tab_d, smap_d, as);
             }
             hipLaunchKernelGGL(k_adj_p3, dim3((unsigned)bbase), dim3(256), 0, sa, tab_d, bmap_d, as);
-            par ^= 1;
+            if (top - n + 1 == chunk || n == s0) {
+                const AdjGrad ag{b, s0, n, top - n + 1};
+                hipLaunchKernelGGL(k_adj_grad, dim3((unsigned)bbase), dim3(256), 0, sa, tab_d, bmap_d, ag);
+                top = n - 1;
+            }
         }
         if (sa != st) AHIP(ctx, hipEventRecord(ctx->ev_adj[2 + b], sa));
         AHIP(ctx, hipGetLastError());
