@@ -74,6 +74,30 @@ def step_bytes(n, cpml, field_bytes=4):
     return (3 * field_bytes + 4) * N + 16 * slab_points(n, cpml)
 
 
+def adjoint_step_bytes(n, cpml, every):
+    """Algorithmic bytes of one step of an FP32 adjoint sweep: the recomputed
+    forward step and its level increment (two levels read, one written); on
+    each axis' layer points pass 1 (mu and zeta_b read; zeta_b, E and K
+    written) and pass 2 (E and psi_b read; W and psi_b written); pass 3 on
+    every point (mu^{n+1}, mu^{n+2}, m read; mu^n written); and the gradient
+    pass (mu^{n+1} and one increment per step, the FP64 accumulator read and
+    written once per pass of G <= 16 steps, a segment split evenly)."""
+    N = n[0] * n[1] * n[2]
+    passes = -(-every // 16)
+    G = -(-every // passes)
+    return step_bytes(n, cpml) + 12 * N + (20 + 16) * slab_points(n, cpml) + 16 * N + (8 + 16 / G) * N
+
+
+def sweep_roofline(nbytes_per_step, steps, ms):
+    """Whole-sweep rate: algorithmic bytes of every recomputed and reverse step
+    over the sweep's wall time (the sweep's kernels overlap on two streams, so
+    no single kernel's duration is taken)."""
+    gbs = nbytes_per_step * steps / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "kind": "whole sweep, algorithmic bytes over wall time",
+            "algorithmic_bytes_per_step": int(nbytes_per_step)}
+
+
 def exchange_bytes(n, cpml, s, field_bytes=4):
     """Algorithmic bytes of one ghost exchange of the pencil share (ghost
     faces on y and z, depth g = 4 s): u^n to depth g, and for s > 1 u^{n-1}
@@ -422,9 +446,11 @@ def adjoint_leg(nshots=3, K=600, every=25):
         f, a = run([d])
         one_f += f
         one_a += a
+    nb = sum(adjoint_step_bytes(w.n, w.cpml, every) for w, _ in data)
     return {"shots": [list(shapes[i]) for i in order], "steps": K, "checkpoint_every": every,
             "forward_with_checkpoints_mpts": round(npts * K / (fwd_ms / 1e3) / 1e6, 1),
             "adjoint_mpts": round(npts * K / (adj_ms / 1e3) / 1e6, 1),
+            "adjoint_roofline": sweep_roofline(nb, K, adj_ms),
             "one_context_per_shot": {"forward_with_checkpoints_mpts": round(npts * K / (one_f / 1e3) / 1e6, 1),
                                      "adjoint_mpts": round(npts * K / (one_a / 1e3) / 1e6, 1)}}
 
@@ -473,7 +499,23 @@ def batched_leg(K=600, nshots=24):
     pb.autotune(os.path.join(ROOT, "paper_2606_06910_amd", "autotune_cache.json"))
     setup(pb, range(nshots))
     ms_b = timed(pb, K)
+    # per-kernel durations (eager, the kernels of a step one after another) and
+    # the rooflines of the z-march and the band kernel over all shots
+    pb.reset()
+    pb.set_timing(True)
+    pb.step(8)
+    pb.set_timing(True)
+    pb.step(40)
+    tm = {kn: pb.timing(c) for c, kn in enumerate(KERNEL_CLASSES)}
+    pb.set_timing(False)
     pb.close()
+    cp = (15,) * 6
+    kb = {"update": sum(interior_kernel_bytes(sh, cp) for sh in shapes),
+          "band": sum(band_kernel_bytes(sh, cp) for sh in shapes),
+          "psi": sum(psi_kernel_bytes(sh, cp) for sh in shapes)}
+    kms = {k: round(v[0], 5) for k, v in tm.items() if v[1] > 0}
+    dom = max(("update", "band"), key=lambda k: kms.get(k, 0.0))
+    names = {"update": "k_zmarch (points outside the layer bands, all shots)", "band": "k_band (band points, all shots)"}
     ms_s = 0.0
     for i in range(nshots):
         p = Propagator([shots[i]])
@@ -482,7 +524,10 @@ def batched_leg(K=600, nshots=24):
         p.close()
     return {"shots": nshots, "points": npts, "steps": K,
             "batched_mpts": round(npts * K / (ms_b / 1e3) / 1e6, 1),
-            "sequential_mpts": round(npts * K / (ms_s / 1e3) / 1e6, 1)}
+            "sequential_mpts": round(npts * K / (ms_s / 1e3) / 1e6, 1),
+            "kernel_ms": kms,
+            "kernel_algorithmic_gbs": {k: round(kb[k] / (kms[k] / 1e3) / 1e9, 1) for k in kb if k in kms},
+            "roofline": roofline(kb[dom], kms[dom], names[dom])}
 
 
 def batched_fwd_adj_leg(K=600, every=25, nshots=24):
@@ -548,9 +593,11 @@ def batched_fwd_adj_leg(K=600, every=25, nshots=24):
     gnorm = float(torch.sqrt(sum((g * g).sum() for g in grads)))
     finite = all(bool(torch.isfinite(g).all()) for g in grads)
     p.close()
+    nb = sum(adjoint_step_bytes(w.n, w.cpml, every) for w, _ in data)
     return {"shots": nshots, "points": npts, "steps": K, "checkpoint_every": every, "receivers_per_shot": 64,
             "forward_with_checkpoints_mpts": round(npts * K / (fwd_ms / 1e3) / 1e6, 1),
             "gradient_mpts": round(npts * K / (adj_ms / 1e3) / 1e6, 1),
+            "gradient_roofline": sweep_roofline(nb, K, adj_ms),
             "forward_s": round(fwd_ms / 1e3, 3), "gradient_s": round(adj_ms / 1e3, 3),
             "misfit": float("%.6e" % misfit), "gradient_l2": float("%.6e" % gnorm), "gradient_finite": finite}
 

@@ -46,3 +46,11 @@ def test_measured_traffic_needs_matching_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic((8, 8, 8), (2, 2, 1, 1)) == 10 * 1024 * 2 + 5 * 1024
     f.write_text(f.read_text().replace(bench.sources_digest(), "0" * 64))
     assert bench.measured_traffic((8, 8, 8), (2, 2, 1)) is None
+
+
+@pytest.mark.parametrize("every,G", [(1, 1), (7, 7), (16, 16), (17, 9), (25, 13), (120, 15)])
+def test_adjoint_step_bytes_without_layers(every, G):
+    # no layers: forward step 16 B, increment 12 B, pass 3 16 B, gradient pass 8 + 16 / G B per point
+    n = (10, 12, 14)
+    N = 10 * 12 * 14
+    assert bench.adjoint_step_bytes(n, (0,) * 6, every) == pytest.approx(N * (16 + 12 + 16 + 8 + 16 / G))
