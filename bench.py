@@ -20,8 +20,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
 COPY_CEILING_GBS = 5090.0   # plain 1 GiB device copy, read + write (copy_1GiB_counters.txt)
-STREAM_CEILING_GBS = 5730.0  # o = a + b * c over 400 MiB FP32 arrays: the interior's 3-read 1-write mix
-                             # (--stream-probe 400; stream_probe_400MiB_kernel_trace.txt)
+STREAM_CEILING_GBS = 5855.0  # o = a + b * c over 400 MiB FP32 arrays: the interior's 3-read 1-write mix, this
+                             # library's one-shot-block kernel (--leg stream_ceiling;
+                             # stream_probe_kernel_400MiB_kernel_trace.txt; torch's addcmul: 5.73 TB/s)
 
 
 def slab_points_axis(n, cpml, d):
@@ -725,7 +726,8 @@ def stream_ceiling_leg(mib=400):
     """This library's own streaming kernel (fdtd_stream_probe: o = a + b * c,
     16-byte lanes, three FP32 streams read and one written, the interior
     update's access mix) over arrays far larger than the caches: TB/s of the
-    best of several grid sizes and in-flight depths (HIP events, 20 launches)."""
+    best of one-shot blocks and grid-stride loops over several grid sizes, at
+    several in-flight depths (HIP events, 20 launches)."""
     import ctypes
 
     import torch
@@ -739,7 +741,7 @@ def stream_ceiling_leg(mib=400):
     st = torch.cuda.current_stream()
     ptr = [ctypes.c_void_p(t.data_ptr()) for t in (a, b, c, o)]
     best = None
-    for blocks in (1024, 2048, 4096, 8192):
+    for blocks in (0, 1024, 2048, 4096, 8192):   # 0: one-shot blocks
         for unroll in (1, 2, 4):
             for _ in range(3):
                 assert L.fdtd_stream_probe(*ptr, n, blocks, unroll, ctypes.c_void_p(st.cuda_stream)) == 0
@@ -755,7 +757,8 @@ def stream_ceiling_leg(mib=400):
             if best is None or tbs > best["TB_per_s"]:
                 best = {"TB_per_s": round(tbs, 3), "ms": round(ms, 4), "blocks": blocks, "unroll": unroll}
     assert torch.allclose(o, a + b * c)
-    return {"kernel": "k_stream_probe (o = a + b * c, float4 lanes)", "bytes_per_launch": 16 * n, "best": best}
+    return {"kernel": "k_stream_chunk (blocks 0) / k_stream_probe (o = a + b * c, float4 lanes)",
+            "bytes_per_launch": 16 * n, "best": best}
 
 
 def oracle_timings_leg(full=False):

@@ -272,8 +272,11 @@ int fdtd_get_timing(fdtd_ctx *ctx, int32_t kernel_class, double *mean_ms, int64_
  * read, one written: the interior update's mix of u^n, u^{n-1}, m in and
  * u^{n+1} out), 16 bytes per lane, a grid-stride loop over `blocks` blocks of
  * 256 threads with `unroll` (1, 2 or 4) independent 16-byte pieces per thread
- * in flight.  All four arrays are device arrays of n floats, 16-byte aligned,
- * n a multiple of 4 (EINVAL otherwise).  Asynchronous on hip_stream. */
+ * in flight.  blocks = 0 selects one-shot blocks instead: each block of 256
+ * threads streams 256 * unroll consecutive 16-byte pieces once and exits, its
+ * stores carrying the non-temporal hint of the field stores.  All four arrays
+ * are device arrays of n floats, 16-byte aligned, n a multiple of 4 (EINVAL
+ * otherwise, and for blocks < 0).  Asynchronous on hip_stream. */
 int fdtd_stream_probe(const float *a_dev, const float *b_dev, const float *c_dev, float *o_dev, size_t n,
                       int32_t blocks, int32_t unroll, void *hip_stream);
 

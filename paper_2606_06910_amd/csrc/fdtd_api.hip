@@ -1613,7 +1613,8 @@ int fdtd_load_state(fdtd_ctx *ctx, const void *src_dev, size_t bytes) {
 
 int fdtd_stream_probe(const float *a_dev, const float *b_dev, const float *c_dev, float *o_dev, size_t n,
                       int32_t blocks, int32_t unroll, void *hip_stream) {
-    if (!a_dev || !b_dev || !c_dev || !o_dev || n == 0 || (n & 3) || blocks <= 0 || blocks > (1 << 20))
+    if (!a_dev || !b_dev || !c_dev || !o_dev || n == 0 || (n & 3) || blocks < 0 || blocks > (1 << 20) ||
+        n / 4 / 256 >= (1u << 31))
         return FDTD_EINVAL;
     if ((((uintptr_t)a_dev | (uintptr_t)b_dev | (uintptr_t)c_dev | (uintptr_t)o_dev) & 15) != 0) return FDTD_EINVAL;
     fdtd_launch_stream_probe(a_dev, b_dev, c_dev, o_dev, n / 4, blocks, unroll, (hipStream_t)hip_stream);

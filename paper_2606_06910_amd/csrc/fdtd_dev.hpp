@@ -350,13 +350,19 @@ constexpr uint32_t kBufSkip = 0x80000000u;
 __device__ __forceinline__ Rsrc make_rsrc(const void *base) {
     return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, 0x7fffffff, 0x00020000);
 }
+// Field stores carry the non-temporal hint (cache-policy bit `nt`): a level
+// written in one step is read only in the next, long after it has left the
+// caches, so it need not displace the lines the other streams are re-reading.
+// (Measured on the overlapped step: 768^3 FP32 2.17 -> 2.09 ms, 512^3 about
+// 1 % faster.  The same hint on the loads made the 512^3 step 16 % slower.)
+constexpr int kStoreNT = 2;
 template <typename T> struct Buf;
 template <> struct Buf<float> {
     static __device__ __forceinline__ float ld(Rsrc r, uint32_t vo, uint32_t so) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
     }
     static __device__ __forceinline__ void st(Rsrc r, uint32_t vo, uint32_t so, float v) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, kStoreNT);
     }
 };
 template <> struct Buf<_Float16> {
@@ -364,7 +370,7 @@ template <> struct Buf<_Float16> {
         return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
     }
     static __device__ __forceinline__ void st(Rsrc r, uint32_t vo, uint32_t so, float v) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, vo, so, kStoreNT);
     }
 };
 template <> struct Buf<__bf16> {
@@ -372,7 +378,7 @@ template <> struct Buf<__bf16> {
         return (float)__builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
     }
     static __device__ __forceinline__ void st(Rsrc r, uint32_t vo, uint32_t so, float v) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (__bf16)v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (__bf16)v), r, vo, so, kStoreNT);
     }
 };
 

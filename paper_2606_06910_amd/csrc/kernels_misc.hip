@@ -223,10 +223,46 @@ __global__ __launch_bounds__(256) void k_stream_probe(const float4 *__restrict__
         o[i] = make_float4(fmaf(y.x, z.x, x.x), fmaf(y.y, z.y, x.y), fmaf(y.z, z.z, x.z), fmaf(y.w, z.w, x.w));
     }
 }
+// The same mix in one-shot blocks: block i streams the 256 U consecutive
+// float4 pieces from 256 U i on (thread t the pieces t, t + 256, ...) and
+// exits; the stores carry the non-temporal hint, as the field stores do.
+typedef float fdtd_v4f __attribute__((ext_vector_type(4)));
+template <int U>
+__global__ __launch_bounds__(256) void k_stream_chunk(const float4 *__restrict__ a, const float4 *__restrict__ b,
+                                                     const float4 *__restrict__ c, float4 *__restrict__ o, size_t n4) {
+    const size_t base = (size_t)blockIdx.x * 256 * U + threadIdx.x;
+    float4 x[U], y[U], z[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const size_t i = base + (size_t)k * 256;
+        if (i < n4) {
+            x[k] = a[i];
+            y[k] = b[i];
+            z[k] = c[i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const size_t i = base + (size_t)k * 256;
+        if (i < n4) {
+            const fdtd_v4f r = {fmaf(y[k].x, z[k].x, x[k].x), fmaf(y[k].y, z[k].y, x[k].y),
+                                fmaf(y[k].z, z[k].z, x[k].z), fmaf(y[k].w, z[k].w, x[k].w)};
+            __builtin_nontemporal_store(r, (fdtd_v4f *)&o[i]);
+        }
+    }
+}
 void fdtd_launch_stream_probe(const float *a, const float *b, const float *c, float *o, size_t n4, int blocks,
                               int unroll, hipStream_t st) {
     const dim3 g((unsigned)blocks), t(256);
     const float4 *A = (const float4 *)a, *B = (const float4 *)b, *C = (const float4 *)c;
+    if (blocks == 0) {
+        const int u = unroll >= 4 ? 4 : (unroll == 2 ? 2 : 1);
+        const dim3 gc((unsigned)((n4 + 256 * (size_t)u - 1) / (256 * (size_t)u)));
+        if (u == 4) hipLaunchKernelGGL(k_stream_chunk<4>, gc, t, 0, st, A, B, C, (float4 *)o, n4);
+        else if (u == 2) hipLaunchKernelGGL(k_stream_chunk<2>, gc, t, 0, st, A, B, C, (float4 *)o, n4);
+        else hipLaunchKernelGGL(k_stream_chunk<1>, gc, t, 0, st, A, B, C, (float4 *)o, n4);
+        return;
+    }
     if (unroll >= 4) hipLaunchKernelGGL(k_stream_probe<4>, g, t, 0, st, A, B, C, (float4 *)o, n4);
     else if (unroll == 2) hipLaunchKernelGGL(k_stream_probe<2>, g, t, 0, st, A, B, C, (float4 *)o, n4);
     else hipLaunchKernelGGL(k_stream_probe<1>, g, t, 0, st, A, B, C, (float4 *)o, n4);
