@@ -113,7 +113,9 @@ __global__ __launch_bounds__(256) void k_adj_diff(const DiffJob *__restrict__ jo
     for (int r = (int)blockIdx.x; r < rows; r += (int)gridDim.x) {
         const int z = r / j.ny, y = r - z * j.ny;
         const long o = (long)z * j.S + (long)y * j.P;
-        for (int x = (int)threadIdx.x; x < j.nx; x += 256) j.d[o + x] = j.a[o + x] - j.b[o + x];
+        // (non-temporal store: the increment is read back only by the gradient pass)
+        for (int x = (int)threadIdx.x; x < j.nx; x += 256)
+            __builtin_nontemporal_store(j.a[o + x] - j.b[o + x], &j.d[o + x]);
     }
 }
 
@@ -272,7 +274,9 @@ __global__ __launch_bounds__(256) void k_adj_p3(const AdjShot *__restrict__ A, c
             t[d] = d2_axis(s.w2[d], kc, lo, hi) - d1_axis(s.w1[d], wl, wh);
         }
     }
-    mu_slot(a, st.m0)[i] = leapfrog(s.m[i], (t[0] + t[1]) + t[2], c, mu_slot(a, st.m2)[i]);
+    // non-temporal store, as the forward field stores (3 smallest batched shots: 290 -> 286 us per
+    // reverse step with this and the increments' hint)
+    __builtin_nontemporal_store(leapfrog(s.m[i], (t[0] + t[1]) + t[2], c, mu_slot(a, st.m2)[i]), &mu_slot(a, st.m0)[i]);
 }
 
 // Gradient pass over cnt reverse steps, taken in the sweep's order (n from
