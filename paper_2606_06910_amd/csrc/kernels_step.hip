@@ -223,8 +223,8 @@ __device__ __forceinline__ void zbody(ZCtx<T, NW, RY> &C, const DevShot &s, floa
         for (int k = 0; k < G::HS; ++k) hq[slot(6)][k] = Buf<T>::ld(C.ru, C.hoff[k], s6);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            umn[r] = Buf<T>::ld(C.rs, C.offs[r], s2);
-            mn[r] = Buf<float>::ld(C.rm, C.offm[r], m2);
+            umn[r] = Buf<T>::ldnt(C.rs, C.offs[r], s2);
+            mn[r] = Buf<float>::ldnt(C.rm, C.offm[r], m2);
         }
     }
     // centre plane to LDS
@@ -399,10 +399,10 @@ __global__ __launch_bounds__(64 * NW) void k_zmarch(const DevShot *__restrict__ 
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
                 q[ZQ - 1][r] = 0.0f;
-                C.umc[r] = Buf<T>::ld(rs, C.offs[r], 0);
-                C.mc[r] = Buf<float>::ld(rm, C.offm[r], 0);
-                C.um1[r] = Buf<T>::ld(rs, C.offs[r], C.Sb);
-                C.m1[r] = Buf<float>::ld(rm, C.offm[r], C.Smb);
+                C.umc[r] = Buf<T>::ldnt(rs, C.offs[r], 0);
+                C.mc[r] = Buf<float>::ldnt(rm, C.offm[r], 0);
+                C.um1[r] = Buf<T>::ldnt(rs, C.offs[r], C.Sb);
+                C.m1[r] = Buf<float>::ldnt(rm, C.offm[r], C.Smb);
             }
             // halo of planes a .. a + 5 (slots 4 .. 9)
 #pragma unroll
