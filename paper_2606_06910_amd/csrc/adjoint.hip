@@ -113,9 +113,11 @@ __global__ __launch_bounds__(256) void k_adj_diff(const DiffJob *__restrict__ jo
     for (int r = (int)blockIdx.x; r < rows; r += (int)gridDim.x) {
         const int z = r / j.ny, y = r - z * j.ny;
         const long o = (long)z * j.S + (long)y * j.P;
-        // (non-temporal store: the increment is read back only by the gradient pass)
+        // (non-temporal accesses: the levels are read once here, the increment only by the
+        // gradient pass)
         for (int x = (int)threadIdx.x; x < j.nx; x += 256)
-            __builtin_nontemporal_store(j.a[o + x] - j.b[o + x], &j.d[o + x]);
+            __builtin_nontemporal_store(__builtin_nontemporal_load(&j.a[o + x]) - __builtin_nontemporal_load(&j.b[o + x]),
+                                        &j.d[o + x]);
     }
 }
 
@@ -274,9 +276,12 @@ __global__ __launch_bounds__(256) void k_adj_p3(const AdjShot *__restrict__ A, c
             t[d] = d2_axis(s.w2[d], kc, lo, hi) - d1_axis(s.w1[d], wl, wh);
         }
     }
-    // non-temporal store, as the forward field stores (3 smallest batched shots: 290 -> 286 us per
-    // reverse step with this and the increments' hint)
-    __builtin_nontemporal_store(leapfrog(s.m[i], (t[0] + t[1]) + t[2], c, mu_slot(a, st.m2)[i]), &mu_slot(a, st.m0)[i]);
+    // non-temporal store, and loads for the streams read once (m, mu^{n+2}), as in the forward
+    // step (3 smallest batched shots: 290 -> 285 us per reverse step with these and the
+    // increments' and gradient pass's hints)
+    __builtin_nontemporal_store(leapfrog(__builtin_nontemporal_load(&s.m[i]), (t[0] + t[1]) + t[2], c,
+                                         __builtin_nontemporal_load(&mu_slot(a, st.m2)[i])),
+                                &mu_slot(a, st.m0)[i]);
 }
 
 // Gradient pass over cnt reverse steps, taken in the sweep's order (n from
@@ -299,8 +304,8 @@ __global__ __launch_bounds__(256) void k_adj_grad(const AdjShot *__restrict__ A,
     double acc = a.G[gi];
 #pragma unroll 4
     for (int n = top; n >= g.n_lo; --n) {
-        const float elo = e[(long)(n - g.s0) * a.lstride];
-        const float c = mu_slot(a, ms)[i];
+        const float elo = __builtin_nontemporal_load(&e[(long)(n - g.s0) * a.lstride]);   // read once
+        const float c = __builtin_nontemporal_load(&mu_slot(a, ms)[i]);
         acc += (double)c * (((double)ehi - (double)elo) * sc);
         ehi = elo;
         ms = ms == 0 ? a.mslots - 1 : ms - 1;
