@@ -36,11 +36,28 @@ def slab_points(n, cpml):
     return sum(slab_points_axis(n, cpml, d) for d in range(3))
 
 
+def x_range(nx, lo, hi, tile=32):
+    """The z-march's x range [a, b): outside the x bands, narrowed to whole
+    32-point band tiles where a band fits one (the low bound to 32, the high
+    one to max(b rounded down to a multiple of 32, nx - 32)), unless that would
+    make the range empty."""
+    a = min(lo + 4, nx) if lo > 0 else 0
+    b = max(nx - hi - 4, a) if hi > 0 else nx
+    a2, b2 = a, b
+    if lo > 0 and a <= tile:
+        a2 = tile
+    if hi > 0 and nx - b <= tile:
+        b2 = max(b // tile * tile, nx - tile)
+    return (a2, b2) if a2 <= b2 else (a, b)
+
+
 def band_split(n, cpml):
-    """(points outside every band, band points); the band of an axis is its
-    layer plus the 4-cell margin the psi derivative reaches."""
-    inner = 1
-    for d in range(3):
+    """(points the z-march updates, points of the band boxes): the band of an
+    axis is its layer plus the 4-cell margin the psi derivative reaches, and
+    along x the band boxes are widened to whole tiles (x_range)."""
+    a, b = x_range(n[0], cpml[0], cpml[1])
+    inner = b - a
+    for d in (1, 2):
         lo, hi = cpml[2 * d], cpml[2 * d + 1]
         a = min(lo + 4, n[d]) if lo > 0 else 0
         b = max(n[d] - hi - 4, a) if hi > 0 else n[d]

@@ -92,6 +92,7 @@ static void plan_shot(ShotH &s) {
         const int gh[3] = {0, s.gy, s.gz}, n3[3] = {s.nx, s.ny, s.nz};
         double inner = 1.0;
         for (int d = 0; d < 3; ++d) {
+            // (the points outside the bands proper, on which the rule was measured)
             int a, b, e0, e1;
             band_range(n3[d], s.Llo[d], s.Lhi[d], gh[d], ext, a, b, e0, e1);
             inner *= (double)(b - a) / (double)(e1 - e0);
@@ -125,8 +126,9 @@ static void plan_shot(ShotH &s) {
     s.tb_bufs = s.variant == FDTD_VARIANT_TBLOCK;
     const int nn[3] = {s.nx, s.ny, s.nz};
     for (int d = 0; d < 3; ++d) {
-        int lo = s.Llo[d] > 0 ? s.Llo[d] + 4 : 0;
-        int hi = s.Lhi[d] > 0 ? nn[d] - s.Lhi[d] - 4 : nn[d];
+        int lo, hi, e0, e1;   // the non-band range, as the band boxes and the z-march take it
+        if (d == 0) band_range_x(nn[0], s.Llo[0], s.Lhi[0], lo, hi, e0, e1);
+        else band_range(nn[d], s.Llo[d], s.Lhi[d], 0, 0, lo, hi, e0, e1);
         if (d == 0) {   // float4 columns: x bounds on multiples of 4
             lo = (lo + 3) / 4 * 4;
             hi = hi / 4 * 4;

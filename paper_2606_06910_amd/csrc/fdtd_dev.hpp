@@ -152,10 +152,31 @@ __host__ __device__ inline void band_range(int n, int Llo, int Lhi, int ghost, i
     a = Llo > 0 ? (Llo + FDTD_R < n ? Llo + FDTD_R : n) : e0;
     b = Lhi > 0 ? (n - Lhi - FDTD_R > a ? n - Lhi - FDTD_R : a) : e1;
 }
+// Along x the non-band range is narrowed to whole band tiles where a band fits
+// one: [a, b) becomes [BAND_TX, b') with b' = max(b rounded down to a multiple
+// of BAND_TX, n - BAND_TX), so that each x band box is one tile wide with every
+// lane busy, and the non-band range starts on a 128-byte line (and, when n is
+// a multiple of BAND_TX, ends on one).  The points between the band and the
+// new bounds lie in no band; the band kernel gives them the interior
+// arithmetic.  Where the two boxes would overlap, the range stays [a, b).
+__host__ __device__ inline void band_range_x(int n, int Llo, int Lhi, int &a, int &b, int &e0, int &e1) {
+    band_range(n, Llo, Lhi, 0, 0, a, b, e0, e1);
+    int a2 = a, b2 = b;
+    if (Llo > 0 && a <= BAND_TX) a2 = BAND_TX;
+    if (Lhi > 0 && n - b <= BAND_TX) {
+        const int r = b / BAND_TX * BAND_TX;
+        b2 = r > n - BAND_TX ? r : n - BAND_TX;
+    }
+    if (a2 <= b2) {
+        a = a2;
+        b = b2;
+    }
+}
 __host__ __device__ inline void band_box(const int n[3], const int Llo[3], const int Lhi[3], const int ghost[3],
                                          int ext, int k, int lo[3], int hi[3]) {
     int a[3], b[3];
-    for (int d = 0; d < 3; ++d) band_range(n[d], Llo[d], Lhi[d], ghost[d], ext, a[d], b[d], lo[d], hi[d]);
+    band_range_x(n[0], Llo[0], Lhi[0], a[0], b[0], lo[0], hi[0]);
+    for (int d = 1; d < 3; ++d) band_range(n[d], Llo[d], Lhi[d], ghost[d], ext, a[d], b[d], lo[d], hi[d]);
     if (k == 6) {
         for (int d = 0; d < 3; ++d) {
             lo[d] = a[d];
@@ -190,7 +211,7 @@ __host__ __device__ inline int band_xtiles(int nx, int Llo, int Lhi, int k, int 
     int cut = hi0;
     if (k < 4) {
         int a, b, e0, e1;
-        band_range(nx, Llo, Lhi, 0, 0, a, b, e0, e1);
+        band_range_x(nx, Llo, Lhi, a, b, e0, e1);
         if (b > lo0 && b < hi0) cut = b;
     }
     const int nlo = (cut - lo0 + BAND_TX - 1) / BAND_TX;

@@ -163,7 +163,7 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
             xvalid |= (AX.npos[j] != xlo + xhi) ? (1u << j) : 0u;
         }
         int a, b, e0, e1;
-        band_range(nx, s.Llo[0], s.Lhi[0], 0, 0, a, b, e0, e1);
+        band_range_x(nx, s.Llo[0], s.Lhi[0], a, b, e0, e1);
         xedge = x0 < a || x1 > b;
     }
     Rsrc rpy = rpx, rpz = rpx, rpr = rpx;
@@ -362,7 +362,8 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
             }
             zo[2] = p.zz;
         }
-        // arithmetic of lap_point (every point here lies in a band)
+        // arithmetic of lap_point (every point of a z or y box lies in a band; an x box
+        // also holds points of no band, between the x band and the whole-tile bound)
         const float *lo[3] = {p.xl, p.yl, zl};
         const float *hi[3] = {p.xh, p.yh, zh};
         const AxisPt *A3[3] = {&AX, &AY, &AZ};
@@ -380,7 +381,10 @@ __device__ __forceinline__ void band_tile(const DevShot *__restrict__ shots, con
             const float dpsi = d1_axis(w1[d], pl[d], ph[d]);
             L[d] = cpml_axis(d2, d1, dpsi, A3[d]->kinv, A3[d]->dkinv, A3[d]->a, A3[d]->b, slb[d], zo[d], &zn[d]);
         }
-        const float lt = (L[0] + L[1]) + L[2];
+        float lt = (L[0] + L[1]) + L[2];
+        if constexpr (KIND == 2) {
+            if (!bnd[0]) lt = lap_interior(K, c, lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]);
+        }
         const bool src = src_col && wrap_ghost(s, 2, z) == s.sz;
         const Upd up = time_update<T>(p.mm, lt, c, p.second, src, srcamp);
         if (act && !in_box(R, x, y, z)) {

@@ -1,7 +1,8 @@
 // Host-only brute force over random grids: the band kernel's tiles (band_box
 // boxes, band_xtiles x tiles, rows of BAND_TY, z chunks of 32 except z boxes,
 // which are walked whole) cover every band point of the compute box exactly
-// once; and, on geometries the library fuses (each x band at most BAND_TX wide,
+// once, and along x the points up to the whole-tile bounds of the non-band x
+// range (band_range_x), and nothing else; and, on geometries the library fuses (each x band at most BAND_TX wide,
 // the x bands and the z bands each far enough apart), every x-layer point lies
 // in the same tile row as each band point that reads it, and every z-layer
 // point in the same z-box walk as its readers, with the walk's first planes
@@ -158,10 +159,23 @@ int main(int argc, char **argv) {
             int a, b;
             band_range(n[d], lo[d], hi[d], gh[d], ext, a, b, e0[d], e1[d]);
         }
+        // the x band boxes also hold the points between an x band and the whole-tile
+        // bound of the non-band x range (band_range_x), which lie in no band
+        int xa, xb, xe0, xe1;
+        band_range_x(n[0], lo[0], hi[0], xa, xb, xe0, xe1);
+        {
+            // the range only narrows, to [BAND_TX, ...) at the low end, and stays non-empty
+            int a0, b0, f0, f1;
+            band_range(n[0], lo[0], hi[0], 0, 0, a0, b0, f0, f1);
+            if (xa < a0 || xb > b0 || xa > xb || (xa != a0 && xa != BAND_TX)) {
+                printf("FAIL x range [%d, %d) for n %d, layers %d %d\n", xa, xb, n[0], lo[0], hi[0]);
+                return 1;
+            }
+        }
         for (int z = e0[2]; z < e1[2]; ++z)
             for (int y = e0[1]; y < e1[1]; ++y)
                 for (int x = 0; x < n[0]; ++x) {
-                    const bool band = in_band_d(0, x) || in_band_d(1, y) || in_band_d(2, z);
+                    const bool band = in_band_d(0, x) || in_band_d(1, y) || in_band_d(2, z) || x < xa || x >= xb;
                     if (band != (own.at(x, y, z).box >= 0)) {
                         printf("FAIL coverage at (%d,%d,%d): band %d\n", x, y, z, band);
                         return 1;
