@@ -54,7 +54,8 @@ struct AdjShot {
     const float *resid;      // dJ/dtraces [nt][nrec]
     const int *gstart, *ridx;   // receivers grouped by location (k_adj_resid)
     int ngroups, nrec;
-    int bbase, btx, bty;          // pass 3 and the gradient pass: first block, tiles along x and y
+    int bbase, btx, bty;          // the gradient pass: first block, tiles along x and y
+    int bbase2;                   // pass 3 (two planes per block): first block
 };
 // A block of passes 1, 2 or 3 finds its shot (and for 1, 2 its axis and first
 // slab point) in a table indexed by block (scalar loads), not by searching.
@@ -230,24 +231,17 @@ __device__ __forceinline__ bool tile_point(const AdjShot &a, int lb, TilePoint &
 // taps and mu^{n+1} at the others.  At a lane outside the band no tap lies in
 // the slab, so this is D2_d mu^{n+1} with the same bits (the W_d taps are
 // exact zeros).  The y and z tests are wave-uniform and the x test is taken
-// per 64-point tile.
-__global__ __launch_bounds__(256) void k_adj_p3(const AdjShot *__restrict__ A, const int *__restrict__ block_shot,
-                                                AdjStep st) {
-    const int b = (int)blockIdx.x;
-    const AdjShot &a = A[block_shot[b]];
-    const DevShot &s = a.s;
-    TilePoint p;
-    if (!tile_point(a, b - a.bbase, p)) return;
-    const int x = p.x, y = p.y, z = p.z;
-    const int xe = min(p.x0 + 64, s.nx) - 1;   // last x of the tile
+// per 64-point tile.  A block is a 64 x 4 tile of two consecutive planes: a
+// thread loads its column of mu^{n+1} over the ten planes z0 - 4 .. z0 + 5
+// once, for the z taps of both of its points.
+__device__ __forceinline__ void p3_point(const AdjShot &a, const DevShot &s, const AdjStep &st, int x, int y, int z,
+                                         bool tx, const float *col) {
     const long i = fidx(s, x, y, z);
     const int cc[3] = {x, y, z};
     const long stv[3] = {1, (long)s.P, (long)s.S};
-    // the band of an axis is an interval at each end of the grid, so a tile meets it iff one of its end points lies in it
-    const bool touch[3] = {in_band(p.x0, s.nx, s.Llo[0], s.Lhi[0]) || in_band(xe, s.nx, s.Llo[0], s.Lhi[0]),
-                           in_band(y, s.ny, s.Llo[1], s.Lhi[1]), in_band(z, s.nz, s.Llo[2], s.Lhi[2])};
+    const bool touch[3] = {tx, in_band(y, s.ny, s.Llo[1], s.Lhi[1]), in_band(z, s.nz, s.Llo[2], s.Lhi[2])};
     const float *mu1 = mu_slot(a, st.m1);
-    const float c = mu1[i];
+    const float c = col[4];
     float t[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -255,8 +249,8 @@ __global__ __launch_bounds__(256) void k_adj_p3(const AdjShot *__restrict__ A, c
         if (!touch[d]) {
 #pragma unroll
             for (int l = 1; l <= 4; ++l) {
-                lo[l - 1] = mu1[i - l * stv[d]];
-                hi[l - 1] = mu1[i + l * stv[d]];
+                lo[l - 1] = d == 2 ? col[4 - l] : mu1[i - l * stv[d]];
+                hi[l - 1] = d == 2 ? col[4 + l] : mu1[i + l * stv[d]];
             }
             t[d] = d2_axis(s.w2[d], c, lo, hi);
         } else {
@@ -282,6 +276,35 @@ __global__ __launch_bounds__(256) void k_adj_p3(const AdjShot *__restrict__ A, c
     __builtin_nontemporal_store(leapfrog(__builtin_nontemporal_load(&s.m[i]), (t[0] + t[1]) + t[2], c,
                                          __builtin_nontemporal_load(&mu_slot(a, st.m2)[i])),
                                 &mu_slot(a, st.m0)[i]);
+}
+
+__global__ __launch_bounds__(256) void k_adj_p3(const AdjShot *__restrict__ A, const int *__restrict__ block_shot,
+                                                AdjStep st) {
+    const int b = (int)blockIdx.x;
+    const AdjShot &a = A[block_shot[b]];
+    const DevShot &s = a.s;
+    const int lb = b - a.bbase2, nxy = a.btx * a.bty;
+    const int z0 = 2 * (lb / nxy), r = lb - (lb / nxy) * nxy;
+    if (z0 >= s.nz) return;
+    const int by = r / a.btx, bx = r - by * a.btx;
+    const int x0 = bx * 64;
+    const int x = x0 + (int)(threadIdx.x & 63);
+    const int y = __builtin_amdgcn_readfirstlane(by * 4 + (int)(threadIdx.x >> 6));
+    if (x >= s.nx || y >= s.ny) return;
+    // the band of an axis is an interval at each end of the grid, so a tile meets it iff one of its end points lies in it
+    const bool tx = in_band(x0, s.nx, s.Llo[0], s.Lhi[0]) || in_band(min(x0 + 64, s.nx) - 1, s.nx, s.Llo[0], s.Lhi[0]);
+    const bool two = z0 + 1 < s.nz;
+    const float *mu1 = mu_slot(a, st.m1);
+    const long i0 = fidx(s, x, y, z0);
+    // planes z0 - 4 .. z0 + 4 lie in the field with its 4-plane frames; z0 + 5 only when z0 + 1 is a plane
+    // (two planes per block: measured 282.5 -> 274.5 us per reverse step on the three smallest batched
+    // shots; a loop over 2, 4 or 8 planes compiled to one wave less per SIMD and was slower)
+    float col[10];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) col[k] = mu1[i0 + (k - 4) * (long)s.S];
+    col[9] = two ? mu1[i0 + 5 * (long)s.S] : 0.0f;
+    p3_point(a, s, st, x, y, z0, tx, col);
+    if (two) p3_point(a, s, st, x, y, z0 + 1, tx, col + 1);
 }
 
 // Gradient pass over cnt reverse steps, taken in the sweep's order (n from
@@ -359,6 +382,7 @@ struct AdjCounts {
         return b;
     }
     long blocks(const ShotH &s) const { return (long)btx * bty * s.nz; }
+    long blocks2(const ShotH &s) const { return (long)btx * bty * ((s.nz + 1) / 2); }
 };
 static AdjCounts adj_counts(const ShotH &s) {
     AdjCounts c;
@@ -376,7 +400,7 @@ struct AdjLayout {
     size_t gstart = 0, ridx = 0;   // receivers grouped by location (k_adj_resid)
     // tables of a sweep over every shot of the context (those of a sweep's first shot are used):
     // AdjShot entries, increment jobs, checkpoint-restore jobs, the slab-pass and pass-3 block tables
-    size_t tab = 0, jobs = 0, rjobs = 0, smap = 0, bmap = 0;
+    size_t tab = 0, jobs = 0, rjobs = 0, smap = 0, bmap = 0, bmap2 = 0;
     size_t total = 0;
     int nck = 0;   // checkpoint slots
 };
@@ -401,11 +425,12 @@ static AdjLayout adj_layout(const fdtd_ctx *ctx, const ShotH &s, int every, int 
         return o;
     };
     const size_t nctx = ctx->shots.size();
-    long sblocks = 0, blocks = 0;
+    long sblocks = 0, blocks = 0, blocks2 = 0;
     for (const ShotH &t : ctx->shots) {
         const AdjCounts c = adj_counts(t);
         sblocks += c.slab_blocks();
         blocks += c.blocks(t);
+        blocks2 += c.blocks2(t);
     }
     L.nck = nslots;
     L.ck = take(fdtd_state_bytes(s) * (size_t)L.nck);
@@ -426,6 +451,7 @@ static AdjLayout adj_layout(const fdtd_ctx *ctx, const ShotH &s, int every, int 
     L.rjobs = take(sizeof(CopyJob) * (size_t)L.nck * 2 * 8 * nctx);
     L.smap = take(sizeof(SlabBlock) * (size_t)std::max(sblocks, 1L));
     L.bmap = take(sizeof(int) * (size_t)std::max(blocks, 1L));
+    L.bmap2 = take(sizeof(int) * (size_t)std::max(blocks2, 1L));
     L.total = off;
     return L;
 }
@@ -498,8 +524,8 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
     std::vector<DiffJob> jobs((size_t)2 * (every + 1) * 2 * nsh);
     std::vector<CopyJob> rjobs((size_t)nck * 2 * 8 * nsh);
     std::vector<SlabBlock> smap;
-    std::vector<int> bmap;
-    int bbase = 0, maxg = 0;
+    std::vector<int> bmap, bmap2;
+    int bbase = 0, bbase2 = 0, maxg = 0;
     long maxrows = 0, maxck = 0;
     for (int q = 0; q < nsh; ++q) {
         const ShotH &s = ctx->shots[sh[q]];
@@ -573,6 +599,9 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
         a.bbase = bbase;
         bbase += (int)cnt.blocks(s);
         bmap.insert(bmap.end(), (size_t)cnt.blocks(s), q);
+        a.bbase2 = bbase2;
+        bbase2 += (int)cnt.blocks2(s);
+        bmap2.insert(bmap2.end(), (size_t)cnt.blocks2(s), q);
         // checkpoint restore of segment k with u^n going to level buffer iu: u^n,
         // u^{n-1}, then psi_d and zeta_d of each axis, as the checkpoint stores them
         for (int k = 0; k < nck; ++k)
@@ -618,6 +647,7 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
     const CopyJob *rjobs_d = (const CopyJob *)(s0h.ck_buf + L0.rjobs);
     const SlabBlock *smap_d = (const SlabBlock *)(s0h.ck_buf + L0.smap);
     const int *bmap_d = (const int *)(s0h.ck_buf + L0.bmap);
+    const int *bmap2_d = (const int *)(s0h.ck_buf + L0.bmap2);
     const unsigned nslab = (unsigned)smap.size();
     AHIP(ctx, hipMemcpyAsync((void *)tab_d, tab.data(), sizeof(AdjShot) * nsh, hipMemcpyHostToDevice, st));
     AHIP(ctx, hipMemcpyAsync((void *)jobs_d, jobs.data(), sizeof(DiffJob) * jobs.size(), hipMemcpyHostToDevice, st));
@@ -627,6 +657,7 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
         AHIP(ctx, hipMemcpyAsync((void *)smap_d, smap.data(), sizeof(SlabBlock) * smap.size(), hipMemcpyHostToDevice,
                                  st));
     AHIP(ctx, hipMemcpyAsync((void *)bmap_d, bmap.data(), sizeof(int) * bmap.size(), hipMemcpyHostToDevice, st));
+    AHIP(ctx, hipMemcpyAsync((void *)bmap2_d, bmap2.data(), sizeof(int) * bmap2.size(), hipMemcpyHostToDevice, st));
     AHIP(ctx, hipStreamSynchronize(st));
     // e of the newest level (in buffer qb) into slot j of half b, every shot in one launch
     auto store_increment = [&](int b, int j, int qb) {
@@ -683,7 +714,7 @@ static int adjoint_sweep(fdtd_ctx *ctx, const std::vector<int> &sh, int nt, cons
                 hipLaunchKernelGGL(k_adj_p1, dim3(nslab), dim3(256), 0, sa, tab_d, smap_d, as);
                 hipLaunchKernelGGL(k_adj_p2, dim3(nslab), dim3(256), 0, sa, tab_d, smap_d, as);
             }
-            hipLaunchKernelGGL(k_adj_p3, dim3((unsigned)bbase), dim3(256), 0, sa, tab_d, bmap_d, as);
+            hipLaunchKernelGGL(k_adj_p3, dim3((unsigned)bbase2), dim3(256), 0, sa, tab_d, bmap2_d, as);
             if (top - n + 1 == chunk || n == s0) {
                 const AdjGrad ag{b, s0, n, top - n + 1};
                 hipLaunchKernelGGL(k_adj_grad, dim3((unsigned)bbase), dim3(256), 0, sa, tab_d, bmap_d, ag);
