@@ -267,7 +267,7 @@ int fdtd_get_scale(const fdtd_ctx *ctx, int32_t shot, double *scale);
 int fdtd_set_timing(fdtd_ctx *ctx, int32_t enable);
 int fdtd_get_timing(fdtd_ctx *ctx, int32_t kernel_class, double *mean_ms, int64_t *count);
 
-/* Measurement: the streaming ceiling that the interior update is judged
+/* Measurement: the streaming ceiling that the interior update is measured
  * against.  o[i] = a[i] + b[i] * c[i] over n float32 elements (three streams
  * read, one written: the interior update's mix of u^n, u^{n-1}, m in and
  * u^{n+1} out), 16 bytes per lane, a grid-stride loop over `blocks` blocks of
