@@ -17,6 +17,7 @@
 #include <array>
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <vector>
 
 namespace {
@@ -86,6 +87,16 @@ bool staging_ok(const int *n, int fy, int x0, int x1, int yt, int yend, int ty) 
 }  // namespace
 
 int main(int argc, char **argv) {
+    if (argc > 1 && std::string(argv[1]) == "ranges") {
+        // "n lo hi" per line on stdin -> the z-march's x range "a b" (band_range_x)
+        int n, lo, hi;
+        while (scanf("%d %d %d", &n, &lo, &hi) == 3) {
+            int a, b, e0, e1;
+            band_range_x(n, lo, hi, a, b, e0, e1);
+            printf("%d %d\n", a, b);
+        }
+        return 0;
+    }
     const int cases = argc > 1 ? atoi(argv[1]) : 2000;
     srand(7);
     long nf = 0;
